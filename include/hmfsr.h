@@ -1,0 +1,156 @@
+/*
+ * hmfsr.h -- C ABI of libhmfsr, the MI355X (gfx950) kernel-regression burst
+ * merge of Wronski et al., "Handheld Multi-Frame Super-Resolution",
+ * ACM TOG 38(4), 2019.
+ *
+ * The merge (the paper's Fig. 2 (b)-(g), Sec. 5 and supplement S.1) turns a
+ * burst of raw Bayer frames plus per-tile alignment vectors into a linear RGB
+ * image at any output scale: per-frame half-resolution structure tensors give
+ * an anisotropic Gaussian kernel covariance per pixel (Sec. 5.1.2, eq. 3-4,
+ * S.1); a noise-corrected robustness mask weights each aligned frame (Sec.
+ * 5.2, eq. 5-9); every output pixel accumulates the nine nearest Bayer
+ * samples of every frame per colour channel and normalises (Sec. 5.1, eq. 1-2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named as DEVICE pointers must point to memory of the current
+ *    HIP device; host structs are read before the call returns.
+ *  - All device work is enqueued asynchronously on `stream` (a hipStream_t,
+ *    NULL = the default stream); no call synchronises the host.
+ *  - The caller owns every buffer it passes. The library owns an internal
+ *    workspace per device (intermediate per-frame maps) that it allocates on
+ *    first use, grows when a larger burst arrives and frees in
+ *    hmfsr_release(). Calls that run concurrently on one device must use
+ *    the same stream (the workspace is shared); the library serialises its
+ *    host-side bookkeeping with a mutex.
+ *  - Outputs are overwritten, never accumulated into.
+ *  - Descriptor and tuning values are validated on the host before any
+ *    device work: invalid values give HMFSR_E_INVALID and touch nothing.
+ *    Device data (frames, motion) is not inspected.
+ */
+#ifndef HMFSR_H
+#define HMFSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HMFSR_VERSION 100 /* 1.0.0 */
+
+/* Colour filter array layout: colours of the 2x2 Bayer cell read row by row. */
+typedef enum {
+  HMFSR_CFA_RGGB = 0,
+  HMFSR_CFA_GRBG = 1,
+  HMFSR_CFA_GBRG = 2,
+  HMFSR_CFA_BGGR = 3
+} hmfsr_cfa;
+
+typedef enum {
+  HMFSR_OK = 0,
+  HMFSR_E_INVALID = -1,     /* bad descriptor, tuning or NULL pointer          */
+  HMFSR_E_UNSUPPORTED = -2, /* unknown CFA code, or a device that is not gfx950 */
+  HMFSR_E_HIP = -3,         /* a HIP runtime call or kernel launch failed      */
+  HMFSR_E_NOMEM = -4        /* the internal workspace could not be allocated   */
+} hmfsr_status;
+
+/*
+ * Burst descriptor (host struct).
+ *  n_frames     >= 1 frames in the burst (the paper merges 2..15, Sec. 6.4).
+ *  height,width Bayer frame size in pixels; both even and >= 4, <= 32768.
+ *  ref_frame    index of the base frame, 0 <= ref_frame < n_frames. Its
+ *               robustness is 1 (Sec. 5.1, after eq. 1).
+ *  cfa          hmfsr_cfa, the mosaic of every frame.
+ *  black_level, white_level
+ *               raw levels mapped to 0 and 1 (x = (raw - black)/(white - black),
+ *               not clamped); black < white.
+ *  noise_a, noise_b
+ *               noise model of the normalised raw values: variance
+ *               a * x + b (Sec. 5.2.2, heteroscedastic Gaussian); a >= 0, b > 0.
+ *  tile_size    T_s, edge of the square alignment tiles in pixels (S.2 gives
+ *               16, 32 or 64); even, 2..256.
+ *  scale        output magnification s >= 1 (Sec. 7.1: 1x to 3x); <= 8.
+ *  out_height, out_width
+ *               must equal floor(height * scale + 0.5), floor(width * scale + 0.5).
+ *               Output pixel (R, C) sits at base-frame position
+ *               ((C + 1/2) / s, (R + 1/2) / s) in pixel-edge coordinates.
+ */
+typedef struct {
+  int32_t n_frames, height, width;
+  int32_t ref_frame;
+  int32_t cfa;
+  float black_level, white_level;
+  float noise_a, noise_b;
+  int32_t tile_size;
+  float scale;
+  int32_t out_height, out_width;
+} hmfsr_desc;
+
+/*
+ * Tuning scalars (host struct), supplement S.1/S.2 notation.
+ *  k_detail    base kernel standard deviation (px), > 0
+ *  k_denoise   kernel standard deviation multiplier for denoising, > 0
+ *  d_th, d_tr  denoising threshold / transition (gradient units), d_tr > 0
+ *  k_stretch   kernel stretch along edges, > 0
+ *  k_shrink    kernel shrink across edges, > 0
+ *  s           robustness scale s_2 where the local motion is small (eq. 8), >= 0
+ *  t           robustness threshold of eq. (5)
+ *  s_motion    robustness scale s_1 where the motion spread M exceeds m_th, >= 0
+ *  m_th        motion-spread threshold M_th (px), >= 0
+ * All finite.
+ */
+typedef struct {
+  float k_detail, k_denoise, d_th, d_tr, k_stretch, k_shrink, s, t;
+  float s_motion;
+  float m_th;
+} hmfsr_tuning;
+
+/*
+ * hmfsr_merge -- merge one burst (Sec. 5, eq. 1-9).
+ *  frames  DEVICE uint16 [n_frames][height][width], row-major raw CFA values.
+ *  motion  DEVICE float32 [n_frames][TY][TX][2], TY = ceil(height/T_s),
+ *          TX = ceil(width/T_s): displacement (vx, vy) in pixels of base tile
+ *          (ty, tx) in frame n, i.e. base position X is seen at X + v in
+ *          frame n (Sec. 3.2 alignment vectors). motion[ref_frame] is ignored
+ *          and taken as 0.
+ *  out     DEVICE float32 [3][out_height][out_width], planes R, G, B of the
+ *          normalised linear result (eq. 1).
+ * Returns HMFSR_OK, or an error code with nothing enqueued.
+ */
+hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
+                         const uint16_t* frames, const float* motion, float* out,
+                         void* stream);
+
+/*
+ * hmfsr_merge_maps -- the per-frame intermediate maps of the merge, for
+ * inspection (the paper's robustness-mask and kernel visualisations,
+ * Fig. 9 and 7). Same inputs as hmfsr_merge; h = height/2, w = width/2.
+ *  omega     DEVICE float64 [n_frames][3][h][w]: kernel covariance
+ *            (Oxx, Oxy, Oyy) per half-resolution pixel (eq. 4, S.1).
+ *  robust    DEVICE float32 [n_frames][h][w]: R of eq. (5) on the base
+ *            frame's half-resolution grid (1 for the base frame).
+ *  robust_min DEVICE float32 [n_frames][h][w]: its 5x5 minimum (eq. 9).
+ *  s_tile    DEVICE float32 [n_frames][TY][TX]: the rejection strength
+ *            chosen by the motion prior (eq. 7-8; 0 for the base frame).
+ * Any of the four may be NULL to skip it.
+ */
+hmfsr_status hmfsr_merge_maps(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
+                              const uint16_t* frames, const float* motion, double* omega,
+                              float* robust, float* robust_min, float* s_tile, void* stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* hmfsr_strerror(hmfsr_status status);
+
+/* HMFSR_VERSION of the built library. */
+int32_t hmfsr_version(void);
+
+/* Free the internal workspace of every device. Not safe to call while work
+ * that uses it is still running: synchronise the streams first. */
+void hmfsr_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMFSR_H */

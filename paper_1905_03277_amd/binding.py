@@ -1,0 +1,109 @@
+"""ctypes binding of libhmfsr's C ABI (``include/hmfsr.h``).
+
+Argument marshalling only: every step of the merge runs in the library's HIP
+kernels. Functions keep the C names; they take integer device addresses and a
+raw hipStream_t handle, and raise ``HmfsrError`` on any non-OK status. The
+library must have been built (``paper_1905_03277_amd.build``); there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhmfsr.so")
+
+HMFSR_OK, HMFSR_E_INVALID, HMFSR_E_UNSUPPORTED, HMFSR_E_HIP, HMFSR_E_NOMEM = 0, -1, -2, -3, -4
+
+# Every symbol include/hmfsr.h declares.
+EXPORTED = ("hmfsr_merge", "hmfsr_merge_maps", "hmfsr_strerror", "hmfsr_version",
+            "hmfsr_release")
+
+
+class hmfsr_desc(ctypes.Structure):
+    _fields_ = [("n_frames", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("ref_frame", ctypes.c_int32),
+                ("cfa", ctypes.c_int32), ("black_level", ctypes.c_float),
+                ("white_level", ctypes.c_float), ("noise_a", ctypes.c_float),
+                ("noise_b", ctypes.c_float), ("tile_size", ctypes.c_int32),
+                ("scale", ctypes.c_float), ("out_height", ctypes.c_int32),
+                ("out_width", ctypes.c_int32)]
+
+
+class hmfsr_tuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_float) for n in
+                ("k_detail", "k_denoise", "d_th", "d_tr", "k_stretch", "k_shrink", "s", "t",
+                 "s_motion", "m_th")]
+
+
+class HmfsrError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libhmfsr.so (once). Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1905_03277_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32 = ctypes.c_void_p, ctypes.c_int32
+        pd, pt = ctypes.POINTER(hmfsr_desc), ctypes.POINTER(hmfsr_tuning)
+        L.hmfsr_merge.argtypes = [pd, pt, vp, vp, vp, vp]
+        L.hmfsr_merge.restype = i32
+        L.hmfsr_merge_maps.argtypes = [pd, pt, vp, vp, vp, vp, vp, vp, vp]
+        L.hmfsr_merge_maps.restype = i32
+        L.hmfsr_strerror.argtypes = [i32]
+        L.hmfsr_strerror.restype = ctypes.c_char_p
+        L.hmfsr_version.argtypes = []
+        L.hmfsr_version.restype = i32
+        L.hmfsr_release.argtypes = []
+        L.hmfsr_release.restype = None
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return lib().hmfsr_strerror(int(status)).decode()
+
+
+def _check(status: int, what: str):
+    if status != HMFSR_OK:
+        raise HmfsrError(status, what)
+
+
+def make_desc(d) -> hmfsr_desc:
+    """hmfsr_desc from any object with the same field names."""
+    return hmfsr_desc(*(getattr(d, f) for f, _ in hmfsr_desc._fields_))
+
+
+def make_tuning(t) -> hmfsr_tuning:
+    return hmfsr_tuning(*(getattr(t, f) for f, _ in hmfsr_tuning._fields_))
+
+
+def hmfsr_merge(desc: hmfsr_desc, tuning: hmfsr_tuning, frames: int, motion: int, out: int,
+                stream: int = 0) -> None:
+    _check(lib().hmfsr_merge(ctypes.byref(desc), ctypes.byref(tuning), frames, motion, out,
+                             stream or None), "hmfsr_merge")
+
+
+def hmfsr_merge_maps(desc, tuning, frames: int, motion: int, omega: int, robust: int,
+                     robust_min: int, s_tile: int, stream: int = 0) -> None:
+    _check(lib().hmfsr_merge_maps(ctypes.byref(desc), ctypes.byref(tuning), frames, motion,
+                                  omega or None, robust or None, robust_min or None,
+                                  s_tile or None, stream or None), "hmfsr_merge_maps")
+
+
+def hmfsr_version() -> int:
+    return int(lib().hmfsr_version())
+
+
+def hmfsr_release() -> None:
+    lib().hmfsr_release()

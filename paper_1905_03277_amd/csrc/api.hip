@@ -1,0 +1,227 @@
+// C ABI entry points: validation, per-device workspace, dispatch.
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hmfsr_internal.h"
+
+namespace hmfsr {
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct DeviceState {
+  int checked = 0;       // 0 unknown, 1 gfx950, -1 unsupported
+  void* workspace = nullptr;
+  size_t workspace_bytes = 0;
+};
+
+std::mutex g_mutex;
+DeviceState g_dev[kMaxDevices];
+
+bool finite(float v) { return isfinite(v) != 0; }
+
+// Colours of the 2x2 mosaic read row by row: 0 R, 1 G, 2 B.
+bool cfa_colours(int cfa, int out[4]) {
+  static const int table[4][4] = {{0, 1, 1, 2}, {1, 0, 2, 1}, {1, 2, 0, 1}, {2, 1, 1, 0}};
+  if (cfa < 0 || cfa > 3) return false;
+  for (int k = 0; k < 4; ++k) out[k] = table[cfa][k];
+  return true;
+}
+
+hmfsr_status validate(const hmfsr_desc* d, const hmfsr_tuning* t) {
+  if (!d || !t) return HMFSR_E_INVALID;
+  if (d->n_frames < 1 || d->n_frames > 4096) return HMFSR_E_INVALID;
+  if (d->ref_frame < 0 || d->ref_frame >= d->n_frames) return HMFSR_E_INVALID;
+  if (d->height < 4 || d->width < 4 || d->height > 32768 || d->width > 32768) return HMFSR_E_INVALID;
+  if ((d->height & 1) || (d->width & 1)) return HMFSR_E_INVALID;
+  if (!finite(d->black_level) || !finite(d->white_level) || !(d->black_level < d->white_level))
+    return HMFSR_E_INVALID;
+  if (!finite(d->noise_a) || !finite(d->noise_b) || d->noise_a < 0.f || !(d->noise_b > 0.f))
+    return HMFSR_E_INVALID;
+  if (d->tile_size < 2 || d->tile_size > 256 || (d->tile_size & 1)) return HMFSR_E_INVALID;
+  if (!finite(d->scale) || !(d->scale >= 1.f) || d->scale > 8.f) return HMFSR_E_INVALID;
+  const double s = (double)d->scale;
+  if (d->out_height != (int32_t)floor((double)d->height * s + 0.5) ||
+      d->out_width != (int32_t)floor((double)d->width * s + 0.5))
+    return HMFSR_E_INVALID;
+  const float vals[10] = {t->k_detail, t->k_denoise, t->d_th, t->d_tr, t->k_stretch,
+                          t->k_shrink, t->s, t->t, t->s_motion, t->m_th};
+  for (float v : vals)
+    if (!finite(v)) return HMFSR_E_INVALID;
+  if (!(t->k_detail > 0.f) || !(t->k_denoise > 0.f) || !(t->d_tr > 0.f) || !(t->k_stretch > 0.f) ||
+      !(t->k_shrink > 0.f) || t->s < 0.f || t->s_motion < 0.f || t->m_th < 0.f)
+    return HMFSR_E_INVALID;
+  int cols[4];
+  if (!cfa_colours(d->cfa, cols)) return HMFSR_E_UNSUPPORTED;
+  return HMFSR_OK;
+}
+
+Geometry make_geometry(const hmfsr_desc* d) {
+  Geometry g;
+  g.n = d->n_frames;
+  g.H = d->height;
+  g.W = d->width;
+  g.h = g.H / 2;
+  g.w = g.W / 2;
+  g.ref = d->ref_frame;
+  g.T = d->tile_size;
+  g.TY = (g.H + g.T - 1) / g.T;
+  g.TX = (g.W + g.T - 1) / g.T;
+  g.OH = d->out_height;
+  g.OW = d->out_width;
+  cfa_colours(d->cfa, g.colour);
+  int ng = 0;
+  for (int k = 0; k < 4; ++k) {
+    if (g.colour[k] == 0) g.red_pos = k;
+    if (g.colour[k] == 2) g.blue_pos = k;
+    if (g.colour[k] == 1) g.green_pos[ng++] = k;
+  }
+  g.black = (double)d->black_level;
+  g.range = (double)d->white_level - (double)d->black_level;
+  g.scale = (double)d->scale;
+  g.noise_a = (double)d->noise_a;
+  g.noise_b = (double)d->noise_b;
+  return g;
+}
+
+TuningD make_tuning(const hmfsr_tuning* t) {
+  TuningD r;
+  r.k_detail = t->k_detail;
+  r.k_denoise = t->k_denoise;
+  r.d_th = t->d_th;
+  r.d_tr = t->d_tr;
+  r.k_stretch = t->k_stretch;
+  r.k_shrink = t->k_shrink;
+  r.s2 = t->s;
+  r.t = t->t;
+  r.s1 = t->s_motion;
+  r.m_th = t->m_th;
+  return r;
+}
+
+// Current device, checked to be gfx950 (cached).
+hmfsr_status current_device(int* dev_out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return HMFSR_E_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return HMFSR_E_UNSUPPORTED;
+  DeviceState& st = g_dev[dev];
+  if (st.checked == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return HMFSR_E_HIP;
+    st.checked = strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+  }
+  if (st.checked < 0) return HMFSR_E_UNSUPPORTED;
+  *dev_out = dev;
+  return HMFSR_OK;
+}
+
+// Workspace of at least `bytes` on `dev`; caller holds g_mutex. Growing a
+// workspace frees the old one only after the stream that may still use it
+// has drained.
+hmfsr_status workspace(int dev, size_t bytes, hipStream_t stream, void** out) {
+  DeviceState& st = g_dev[dev];
+  if (st.workspace_bytes < bytes) {
+    if (st.workspace) {
+      if (hipStreamSynchronize(stream) != hipSuccess) return HMFSR_E_HIP;
+      hipFree(st.workspace);
+      st.workspace = nullptr;
+      st.workspace_bytes = 0;
+    }
+    if (hipMalloc(&st.workspace, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      st.workspace = nullptr;
+      return HMFSR_E_NOMEM;
+    }
+    st.workspace_bytes = bytes;
+  }
+  *out = st.workspace;
+  return HMFSR_OK;
+}
+
+}  // namespace
+}  // namespace hmfsr
+
+using namespace hmfsr;
+
+extern "C" {
+
+hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, const uint16_t* frames,
+                         const float* motion, float* out, void* stream) {
+  hmfsr_status st = validate(desc, tuning);
+  if (st != HMFSR_OK) return st;
+  if (!frames || !motion || !out) return HMFSR_E_INVALID;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  int dev = 0;
+  if ((st = current_device(&dev)) != HMFSR_OK) return st;
+  const Geometry g = make_geometry(desc);
+  const TuningD t = make_tuning(tuning);
+  void* ws = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = workspace(dev, maps_bytes(g), s, &ws)) != HMFSR_OK) return st;
+  const Maps m = maps_carve(ws, g);
+  if (launch_maps(g, t, frames, motion, m, s) != hipSuccess) return HMFSR_E_HIP;
+  if (launch_accumulate(g, frames, motion, m, out, s) != hipSuccess) return HMFSR_E_HIP;
+  return HMFSR_OK;
+}
+
+hmfsr_status hmfsr_merge_maps(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
+                              const uint16_t* frames, const float* motion, double* omega,
+                              float* robust, float* robust_min, float* s_tile, void* stream) {
+  hmfsr_status st = validate(desc, tuning);
+  if (st != HMFSR_OK) return st;
+  if (!frames || !motion) return HMFSR_E_INVALID;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  int dev = 0;
+  if ((st = current_device(&dev)) != HMFSR_OK) return st;
+  const Geometry g = make_geometry(desc);
+  const TuningD t = make_tuning(tuning);
+  void* ws = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = workspace(dev, maps_bytes(g), s, &ws)) != HMFSR_OK) return st;
+  const Maps m = maps_carve(ws, g);
+  if (launch_maps(g, t, frames, motion, m, s) != hipSuccess) return HMFSR_E_HIP;
+  const size_t plane = (size_t)g.h * g.w;
+  struct Copy { void* dst; const void* src; size_t bytes; } copies[4] = {
+      {omega, m.omega, 3 * plane * g.n * sizeof(double)},
+      {robust, m.robust, plane * g.n * sizeof(float)},
+      {robust_min, m.rmin, plane * g.n * sizeof(float)},
+      {s_tile, m.s_tile, (size_t)g.TY * g.TX * g.n * sizeof(float)}};
+  for (const Copy& c : copies) {
+    if (!c.dst) continue;
+    if (hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return HMFSR_E_HIP;
+  }
+  return HMFSR_OK;
+}
+
+const char* hmfsr_strerror(hmfsr_status status) {
+  switch (status) {
+    case HMFSR_OK: return "HMFSR_OK";
+    case HMFSR_E_INVALID: return "HMFSR_E_INVALID: invalid descriptor, tuning or pointer";
+    case HMFSR_E_UNSUPPORTED: return "HMFSR_E_UNSUPPORTED: unknown CFA or device is not gfx950";
+    case HMFSR_E_HIP: return "HMFSR_E_HIP: HIP runtime or launch error";
+    case HMFSR_E_NOMEM: return "HMFSR_E_NOMEM: workspace allocation failed";
+  }
+  return "HMFSR: unknown status";
+}
+
+int32_t hmfsr_version(void) { return HMFSR_VERSION; }
+
+void hmfsr_release(void) {
+  std::lock_guard<std::mutex> lock(g_mutex);
+  int cur = 0;
+  const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+  for (int d = 0; d < kMaxDevices; ++d) {
+    if (!g_dev[d].workspace) continue;
+    if (hipSetDevice(d) == hipSuccess) hipFree(g_dev[d].workspace);
+    g_dev[d].workspace = nullptr;
+    g_dev[d].workspace_bytes = 0;
+  }
+  if (have_cur) hipSetDevice(cur);
+}
+
+}  // extern "C"

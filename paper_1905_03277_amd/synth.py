@@ -50,6 +50,10 @@ _CFA_COLOURS = {
 SEED_BASE = 190503277
 
 
+def _f32(v) -> float:
+    return float(np.float32(v))
+
+
 @dataclass
 class Tuning:
     """Tuning scalars of the merge (supplement S.1/S.2 names)."""
@@ -63,6 +67,11 @@ class Tuning:
     t: float
     s_motion: float   # paper s_1 (local motion above the threshold)
     m_th: float       # paper M_th, in pixels
+
+    def __post_init__(self):
+        # The C ABI carries these as float32: keep the canonical values rounded.
+        for f in dataclasses.fields(self):
+            setattr(self, f.name, _f32(getattr(self, f.name)))
 
     def as_list(self):
         return [self.k_detail, self.k_denoise, self.d_th, self.d_tr, self.k_stretch,
@@ -98,6 +107,8 @@ class Desc:
     out_width: int = 0
 
     def __post_init__(self):
+        for name in ("black_level", "white_level", "noise_a", "noise_b", "scale"):
+            setattr(self, name, _f32(getattr(self, name)))
         if self.out_height == 0:
             self.out_height = int(math.floor(self.height * self.scale + 0.5))
         if self.out_width == 0:

@@ -1,0 +1,69 @@
+"""Torch-tensor front end of libhmfsr: shape/dtype checks and marshalling.
+
+PyTorch supplies device memory and the current stream; the merge itself runs
+in the library's HIP kernels. Tensors must live on a ROCm device.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import binding
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _check_inputs(frames: torch.Tensor, motion: torch.Tensor, desc):
+    if not frames.is_cuda or not motion.is_cuda:
+        raise ValueError("frames and motion must be device tensors (no CPU path exists)")
+    if frames.dtype not in (torch.uint16, torch.int16):
+        raise ValueError(f"frames must be uint16 (or an int16 view), got {frames.dtype}")
+    if motion.dtype != torch.float32:
+        raise ValueError(f"motion must be float32, got {motion.dtype}")
+    n, h, w = desc.n_frames, desc.height, desc.width
+    ty, tx = -(-h // desc.tile_size), -(-w // desc.tile_size)
+    if tuple(frames.shape) != (n, h, w):
+        raise ValueError(f"frames shape {tuple(frames.shape)} != {(n, h, w)}")
+    if tuple(motion.shape) != (n, ty, tx, 2):
+        raise ValueError(f"motion shape {tuple(motion.shape)} != {(n, ty, tx, 2)}")
+    if not frames.is_contiguous() or not motion.is_contiguous():
+        raise ValueError("frames and motion must be contiguous")
+    if frames.device != motion.device:
+        raise ValueError("frames and motion must be on one device")
+
+
+def merge(frames: torch.Tensor, motion: torch.Tensor, desc, tuning,
+          out: torch.Tensor | None = None) -> torch.Tensor:
+    """Merge one burst; returns float32 [3][OH][OW] on the frames' device."""
+    _check_inputs(frames, motion, desc)
+    shape = (3, desc.out_height, desc.out_width)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=frames.device)
+    elif tuple(out.shape) != shape or out.dtype != torch.float32 or not out.is_contiguous() \
+            or out.device != frames.device:
+        raise ValueError("out must be a contiguous float32 tensor of shape [3][OH][OW]")
+    with torch.cuda.device(frames.device):
+        binding.hmfsr_merge(binding.make_desc(desc), binding.make_tuning(tuning),
+                            frames.data_ptr(), motion.data_ptr(), out.data_ptr(),
+                            _stream(frames.device))
+    return out
+
+
+def merge_maps(frames: torch.Tensor, motion: torch.Tensor, desc, tuning) -> dict:
+    """Per-frame intermediate maps: omega [N][3][h][w] f64, robust and
+    robust_min [N][h][w] f32, s_tile [N][TY][TX] f32."""
+    _check_inputs(frames, motion, desc)
+    dev = frames.device
+    n, h, w = desc.n_frames, desc.height // 2, desc.width // 2
+    ty, tx = -(-desc.height // desc.tile_size), -(-desc.width // desc.tile_size)
+    res = dict(omega=torch.empty((n, 3, h, w), dtype=torch.float64, device=dev),
+               robust=torch.empty((n, h, w), dtype=torch.float32, device=dev),
+               robust_min=torch.empty((n, h, w), dtype=torch.float32, device=dev),
+               s_tile=torch.empty((n, ty, tx), dtype=torch.float32, device=dev))
+    with torch.cuda.device(dev):
+        binding.hmfsr_merge_maps(binding.make_desc(desc), binding.make_tuning(tuning),
+                                 frames.data_ptr(), motion.data_ptr(), res["omega"].data_ptr(),
+                                 res["robust"].data_ptr(), res["robust_min"].data_ptr(),
+                                 res["s_tile"].data_ptr(), _stream(dev))
+    return res

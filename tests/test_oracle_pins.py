@@ -211,8 +211,8 @@ def test_ramp_structure_tensor_and_kernel_orientation():
     # D = clamp(1 - alpha / D_tr + D_th) = 0 for this steep ramp, so
     # k1 = (k_detail * k_stretch * 2)^2 and k2 = (k_detail / (k_shrink * 2))^2
     assert np.all(parts["D"][core] == 0.0)
-    k1 = (0.2755 * 4.0 * 2.0) ** 2
-    k2 = (0.2755 / (2.0 * 2.0)) ** 2
+    k1 = (TUN.k_detail * 4.0 * 2.0) ** 2
+    k2 = (TUN.k_detail / (2.0 * 2.0)) ** 2
     np.testing.assert_allclose(oyy[core], k1, rtol=1e-12)
     np.testing.assert_allclose(oxx[core], k2, rtol=1e-12)
     np.testing.assert_allclose(oxy[core], 0.0, atol=1e-15)
@@ -260,7 +260,7 @@ def test_large_d_th_gives_isotropic_kernel():
     f, m = b.numpy()
     tun = TUN.replace(d_th=1e6)
     maps = om.prepare(f, m, b.desc, tun)
-    iso = (0.2755 * 3.64) ** 2
+    iso = (TUN.k_detail * TUN.k_denoise) ** 2
     np.testing.assert_allclose(maps["omega"][:, 0], iso, rtol=1e-12)
     np.testing.assert_allclose(maps["omega"][:, 2], iso, rtol=1e-12)
     np.testing.assert_allclose(maps["omega"][:, 1], 0.0, atol=1e-15)
@@ -346,13 +346,13 @@ def test_robustness_of_two_flat_frames_hand_value():
     maps = om.prepare(f, m, desc, TUN)
     x_ref = 2016 / 4031
     dms = -95 / 4031
-    var_rb = 1e-3 * x_ref + 1e-6
+    var_rb = desc.noise_a * x_ref + desc.noise_b
     var_g = var_rb / 2
     d_rb = dms ** 3 / (dms ** 2 + 2 * var_rb / 9)
     d_g = dms ** 3 / (dms ** 2 + 2 * var_g / 9)
     r = (2 * d_rb ** 2 + d_g ** 2) / (2 * var_rb + var_g)
     assert abs(r - 0.9814682) < 1e-6
-    expect = 2 * math.exp(-r) - 0.12
+    expect = 2 * math.exp(-r) - TUN.t
     assert abs(expect - 0.6295209) < 1e-6
     np.testing.assert_allclose(maps["r"][1], expect, rtol=1e-12)
 
