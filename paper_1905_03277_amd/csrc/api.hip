@@ -1,5 +1,6 @@
 // C ABI entry points: validation, per-device workspace, dispatch.
 #include <math.h>
+#include <stdint.h>
 #include <string.h>
 
 #include <mutex>
@@ -80,27 +81,49 @@ Geometry make_geometry(const hmfsr_desc* d) {
     if (g.colour[k] == 2) g.blue_pos = k;
     if (g.colour[k] == 1) g.green_pos[ng++] = k;
   }
-  g.black = (double)d->black_level;
-  g.range = (double)d->white_level - (double)d->black_level;
   g.scale = (double)d->scale;
-  g.noise_a = (double)d->noise_a;
-  g.noise_b = (double)d->noise_b;
   return g;
 }
 
-TuningD make_tuning(const hmfsr_tuning* t) {
-  TuningD r;
-  r.k_detail = t->k_detail;
-  r.k_denoise = t->k_denoise;
-  r.d_th = t->d_th;
-  r.d_tr = t->d_tr;
-  r.k_stretch = t->k_stretch;
-  r.k_shrink = t->k_shrink;
-  r.s2 = t->s;
+double range_of(const hmfsr_desc* d) { return (double)d->white_level - (double)d->black_level; }
+
+OmegaConsts make_omega(const hmfsr_desc* d, const hmfsr_tuning* t) {
+  OmegaConsts c;
+  const double kd = t->k_detail;
+  c.kd_st = kd * (double)t->k_stretch;
+  c.kd_sh = kd / (double)t->k_shrink;
+  c.kd_dn = kd * (double)t->k_denoise;
+  c.d_th = t->d_th;
+  c.inv_16_range_dtr = 1.0 / (16.0 * range_of(d) * (double)t->d_tr);
+  return c;
+}
+
+PriorConsts make_prior(const hmfsr_tuning* t) {
+  PriorConsts p;
+  p.m_th = t->m_th;
+  p.s1 = t->s_motion;
+  p.s2 = t->s;
+  return p;
+}
+
+RobustConsts make_robust(const hmfsr_desc* d, const hmfsr_tuning* t) {
+  RobustConsts r;
+  const double range = range_of(d);
+  r.black = d->black_level;
+  r.a_r = (float)((double)d->noise_a * range);
+  r.b_r = (float)((double)d->noise_b * range * range);
   r.t = t->t;
-  r.s1 = t->s_motion;
-  r.m_th = t->m_th;
   return r;
+}
+
+MergeConsts make_merge(const hmfsr_desc* d, const hmfsr_tuning* t, const Geometry& g) {
+  MergeConsts m;
+  m.om = make_omega(d, t);
+  m.black = d->black_level;
+  m.inv_range = (float)(1.0 / range_of(d));
+  m.col4 = 0;
+  for (int k = 0; k < 4; ++k) m.col4 |= g.colour[k] << (2 * k);
+  return m;
 }
 
 // Current device, checked to be gfx950 (cached).
@@ -154,17 +177,21 @@ hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, con
   hmfsr_status st = validate(desc, tuning);
   if (st != HMFSR_OK) return st;
   if (!frames || !motion || !out) return HMFSR_E_INVALID;
+  if (((uintptr_t)frames & 3) || ((uintptr_t)motion & 3) || ((uintptr_t)out & 3)) return HMFSR_E_INVALID;
   std::lock_guard<std::mutex> lock(g_mutex);
   int dev = 0;
   if ((st = current_device(&dev)) != HMFSR_OK) return st;
   const Geometry g = make_geometry(desc);
-  const TuningD t = make_tuning(tuning);
   void* ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
-  if ((st = workspace(dev, maps_bytes(g), s, &ws)) != HMFSR_OK) return st;
-  const Maps m = maps_carve(ws, g);
-  if (launch_maps(g, t, frames, motion, m, s) != hipSuccess) return HMFSR_E_HIP;
-  if (launch_accumulate(g, frames, motion, m, out, s) != hipSuccess) return HMFSR_E_HIP;
+  if ((st = workspace(dev, work_bytes(g), s, &ws)) != HMFSR_OK) return st;
+  const Work w = work_carve(ws, g);
+  if (launch_prior(g, make_prior(tuning), motion, w.s_tile, s) != hipSuccess) return HMFSR_E_HIP;
+  if (launch_robust(g, make_robust(desc, tuning), frames, motion, w.s_tile, w.rmin, nullptr, s) !=
+      hipSuccess)
+    return HMFSR_E_HIP;
+  if (launch_merge(g, make_merge(desc, tuning, g), frames, motion, w.rmin, out, s) != hipSuccess)
+    return HMFSR_E_HIP;
   return HMFSR_OK;
 }
 
@@ -174,27 +201,31 @@ hmfsr_status hmfsr_merge_maps(const hmfsr_desc* desc, const hmfsr_tuning* tuning
   hmfsr_status st = validate(desc, tuning);
   if (st != HMFSR_OK) return st;
   if (!frames || !motion) return HMFSR_E_INVALID;
+  if (((uintptr_t)frames & 3) || ((uintptr_t)motion & 3)) return HMFSR_E_INVALID;
   std::lock_guard<std::mutex> lock(g_mutex);
   int dev = 0;
   if ((st = current_device(&dev)) != HMFSR_OK) return st;
   const Geometry g = make_geometry(desc);
-  const TuningD t = make_tuning(tuning);
   void* ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
-  if ((st = workspace(dev, maps_bytes(g), s, &ws)) != HMFSR_OK) return st;
-  const Maps m = maps_carve(ws, g);
-  if (launch_maps(g, t, frames, motion, m, s) != hipSuccess) return HMFSR_E_HIP;
+  if ((st = workspace(dev, work_bytes(g), s, &ws)) != HMFSR_OK) return st;
+  const Work w = work_carve(ws, g);
   const size_t plane = (size_t)g.h * g.w;
-  struct Copy { void* dst; const void* src; size_t bytes; } copies[4] = {
-      {omega, m.omega, 3 * plane * g.n * sizeof(double)},
-      {robust, m.robust, plane * g.n * sizeof(float)},
-      {robust_min, m.rmin, plane * g.n * sizeof(float)},
-      {s_tile, m.s_tile, (size_t)g.TY * g.TX * g.n * sizeof(float)}};
-  for (const Copy& c : copies) {
-    if (!c.dst) continue;
-    if (hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
-      return HMFSR_E_HIP;
+  if (omega && launch_omega_map(g, make_omega(desc, tuning), frames, omega, s) != hipSuccess)
+    return HMFSR_E_HIP;
+  if (launch_prior(g, make_prior(tuning), motion, w.s_tile, s) != hipSuccess) return HMFSR_E_HIP;
+  float* rmin = robust_min ? robust_min : w.rmin;
+  if (launch_robust(g, make_robust(desc, tuning), frames, motion, w.s_tile, rmin, robust, s) !=
+      hipSuccess)
+    return HMFSR_E_HIP;
+  // the base frame's robustness is 1 by definition
+  for (float* m : {robust, robust_min}) {
+    if (!m) continue;
+    if (launch_fill(m + g.ref * plane, 1.0f, plane, s) != hipSuccess) return HMFSR_E_HIP;
   }
+  if (s_tile && hipMemcpyAsync(s_tile, w.s_tile, (size_t)g.TY * g.TX * g.n * sizeof(float),
+                               hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return HMFSR_E_HIP;
   return HMFSR_OK;
 }
 

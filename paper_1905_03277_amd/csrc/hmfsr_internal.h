@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/hmfsr.h"
+#include "omega.h"
 
 namespace hmfsr {
 
@@ -18,34 +19,47 @@ struct Geometry {
   int colour[4];    // colour (0 R, 1 G, 2 B) of Bayer parity (r & 1) * 2 + (c & 1)
   int green_pos[2]; // the two green parity indices, ascending
   int red_pos, blue_pos;
-  double black, range;  // x = (raw - black) / range
   double scale;
-  double noise_a, noise_b;
 };
 
-// Tuning in the precision each stage uses.
-struct TuningD {
-  double k_detail, k_denoise, d_th, d_tr, k_stretch, k_shrink;
-  double s2, t, s1, m_th;
+// Motion prior thresholds (eq. 7-8).
+struct PriorConsts {
+  double m_th;
+  float s1, s2;
 };
 
-// Device-side intermediate maps of the materialised pipeline.
-struct Maps {
-  double* omega;   // [n][3][h][w]
-  double* mu;      // [n][3][h][w] 3x3 guide mean
-  double* sd;      // [n][3][h][w] 3x3 guide population sigma
-  float* s_tile;   // [n][TY][TX]
-  float* robust;   // [n][h][w]
-  float* rmin;     // [n][h][w]
+// Robustness constants in raw units (eq. 5-6).
+struct RobustConsts {
+  float black;
+  float a_r;  // noise_a * range: variance slope per raw unit of brightness
+  float b_r;  // noise_b * range^2
+  float t;
 };
 
-size_t maps_bytes(const Geometry& g);
-Maps maps_carve(void* base, const Geometry& g);
+// Accumulation constants.
+struct MergeConsts {
+  OmegaConsts om;
+  float black, inv_range;
+  int col4;  // colour of parity k in bits 2k..2k+1
+};
 
-// Enqueue the whole materialised pipeline (maps + accumulation) on `stream`.
-hipError_t launch_maps(const Geometry& g, const TuningD& t, const uint16_t* frames,
-                       const float* motion, const Maps& m, hipStream_t stream);
-hipError_t launch_accumulate(const Geometry& g, const uint16_t* frames, const float* motion,
-                             const Maps& m, float* out, hipStream_t stream);
+// Workspace of the merge: per-(frame, tile) rejection strength and R_hat.
+struct Work {
+  float* s_tile;  // [n][TY][TX]
+  float* rmin;    // [n][h][w]
+};
+size_t work_bytes(const Geometry& g);
+Work work_carve(void* base, const Geometry& g);
+
+hipError_t launch_prior(const Geometry& g, const PriorConsts& pc, const float* motion, float* s_tile,
+                        hipStream_t stream);
+hipError_t launch_robust(const Geometry& g, const RobustConsts& rc, const uint16_t* frames,
+                         const float* motion, const float* s_tile, float* rmin, float* robust,
+                         hipStream_t stream);
+hipError_t launch_merge(const Geometry& g, const MergeConsts& mc, const uint16_t* frames,
+                        const float* motion, const float* rmin, float* out, hipStream_t stream);
+hipError_t launch_fill(float* p, float v, size_t n, hipStream_t stream);
+hipError_t launch_omega_map(const Geometry& g, const OmegaConsts& oc, const uint16_t* frames,
+                            double* omega, hipStream_t stream);
 
 }  // namespace hmfsr

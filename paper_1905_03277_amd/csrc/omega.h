@@ -1,0 +1,73 @@
+// Kernel covariance Omega of one half-resolution pixel (Sec. 5.1.2, eq. 3-4,
+// supplement S.1), evaluated from raw 2x2-quad sums so that the structure
+// tensor is exact.
+//
+// With L the sum of the four raw values of a quad, the luma of the quad is
+// (L - 4 black) / (4 range). The cell gradient of eq. (3) (horizontal and
+// vertical differences averaged over the 2x2 luma cell) is then
+// g = gi / (8 range) with gi an integer built from L differences (black
+// cancels), and the tensor (mean of the four cell outer products) is
+// T = Ti / (256 range^2) with Ti a sum of integer products, exact in float64.
+// The eigen-analysis is scale-invariant except for sqrt(lambda1), which enters
+// D; that factor is folded into `inv_16_range_dtr`.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace hmfsr {
+
+struct OmegaConsts {
+  double kd_st;             // k_detail * k_stretch
+  double kd_sh;             // k_detail / k_shrink
+  double kd_dn;             // k_detail * k_denoise
+  double d_th;
+  double inv_16_range_dtr;  // 1 / (16 * range * d_tr)
+};
+
+// l[a][b]: quad sums of the 3x3 half-res window around the pixel (edge-clamped).
+__device__ __forceinline__ void omega_from_quads(const int (&l)[3][3], const OmegaConsts& c,
+                                                 double& oxx, double& oxy, double& oyy) {
+  double txx = 0.0, txy = 0.0, tyy = 0.0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int gxi = (l[a][b + 1] - l[a][b]) + (l[a + 1][b + 1] - l[a + 1][b]);
+      const int gyi = (l[a + 1][b] - l[a][b]) + (l[a + 1][b + 1] - l[a][b + 1]);
+      const double gx = (double)gxi, gy = (double)gyi;
+      txx += gx * gx;
+      txy += gx * gy;
+      tyy += gy * gy;
+    }
+  }
+  // Closed-form eigen-analysis: lambda1,2 = tr/2 +- rad; lambda1 - lambda2 = 2 rad.
+  const double half = 0.5 * (txx - tyy);
+  const double rad = sqrt(half * half + txy * txy);
+  const double tr = txx + tyy;
+  double ex, ey;  // dominant eigenvector (gradient direction), unnormalised
+  if (txy == 0.0 && txx == tyy) {
+    ex = 1.0;
+    ey = 0.0;
+  } else if (half >= 0.0) {
+    ex = half + rad;
+    ey = txy;
+  } else {
+    ex = txy;
+    ey = rad - half;
+  }
+  const double inv_n2 = 1.0 / (ex * ex + ey * ey);
+  const double gx2 = ex * ex * inv_n2, gy2 = ey * ey * inv_n2, gxy = ex * ey * inv_n2;
+
+  const double A = tr > 0.0 ? 1.0 + sqrt(2.0 * rad / tr) : 1.0;
+  double D = 1.0 - sqrt(0.5 * tr + rad) * c.inv_16_range_dtr + c.d_th;
+  D = D < 0.0 ? 0.0 : (D > 1.0 ? 1.0 : D);
+  const double k1s = (1.0 - D) * (c.kd_st * A) + D * c.kd_dn;
+  const double k2s = (1.0 - D) * (c.kd_sh / A) + D * c.kd_dn;
+  const double k1 = k1s * k1s, k2 = k2s * k2s;
+  // eq. (4): variance k1 along the edge (perpendicular to the gradient), k2 across it.
+  oxx = k1 * gy2 + k2 * gx2;
+  oxy = (k2 - k1) * gxy;
+  oyy = k1 * gx2 + k2 * gy2;
+}
+
+}  // namespace hmfsr

@@ -45,8 +45,9 @@ def test_config1_maps_match_oracle():
     scale = np.abs(ref["omega"]).max()
     assert np.abs(om_gpu - ref["omega"]).max() <= 1e-12 * scale
     np.testing.assert_array_equal(maps["s_tile"].cpu().numpy()[1:], ref["s_tiles"][1:])
-    np.testing.assert_allclose(maps["robust"].cpu().numpy(), ref["r"], rtol=0, atol=2e-7)
-    np.testing.assert_allclose(maps["robust_min"].cpu().numpy(), ref["r_hat"], rtol=0, atol=2e-7)
+    # the robustness chain runs in float32 (raw units): agreement to ~1e-5
+    np.testing.assert_allclose(maps["robust"].cpu().numpy(), ref["r"], rtol=0, atol=5e-5)
+    np.testing.assert_allclose(maps["robust_min"].cpu().numpy(), ref["r_hat"], rtol=0, atol=5e-5)
 
 
 SMALL = [
