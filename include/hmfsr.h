@@ -69,7 +69,7 @@ typedef enum {
  *               noise model of the normalised raw values: variance
  *               a * x + b (Sec. 5.2.2, heteroscedastic Gaussian); a >= 0, b > 0.
  *  tile_size    T_s, edge of the square alignment tiles in pixels (S.2 gives
- *               16, 32 or 64); even, 2..256.
+ *               16, 32 or 64); even, 8..256.
  *  scale        output magnification s >= 1 (Sec. 7.1: 1x to 3x); <= 8.
  *  out_height, out_width
  *               must equal floor(height * scale + 0.5), floor(width * scale + 0.5).
@@ -108,7 +108,8 @@ typedef struct {
 
 /*
  * hmfsr_merge -- merge one burst (Sec. 5, eq. 1-9).
- *  frames  DEVICE uint16 [n_frames][height][width], row-major raw CFA values.
+ *  frames  DEVICE uint16 [n_frames][height][width], row-major raw CFA values,
+ *          4-byte aligned.
  *  motion  DEVICE float32 [n_frames][TY][TX][2], TY = ceil(height/T_s),
  *          TX = ceil(width/T_s): displacement (vx, vy) in pixels of base tile
  *          (ty, tx) in frame n, i.e. base position X is seen at X + v in
@@ -124,8 +125,8 @@ hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
 
 /*
  * hmfsr_merge_maps -- the per-frame intermediate maps of the merge, for
- * inspection (the paper's robustness-mask and kernel visualisations,
- * Fig. 9 and 7). Same inputs as hmfsr_merge; h = height/2, w = width/2.
+ * inspection (the paper visualises the accumulated robustness mask and the
+ * kernel shapes). Same inputs as hmfsr_merge; h = height/2, w = width/2.
  *  omega     DEVICE float64 [n_frames][3][h][w]: kernel covariance
  *            (Oxx, Oxy, Oyy) per half-resolution pixel (eq. 4, S.1).
  *  robust    DEVICE float32 [n_frames][h][w]: R of eq. (5) on the base

@@ -1,6 +1,7 @@
 // C ABI entry points: validation, per-device workspace, dispatch.
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -43,7 +44,7 @@ hmfsr_status validate(const hmfsr_desc* d, const hmfsr_tuning* t) {
     return HMFSR_E_INVALID;
   if (!finite(d->noise_a) || !finite(d->noise_b) || d->noise_a < 0.f || !(d->noise_b > 0.f))
     return HMFSR_E_INVALID;
-  if (d->tile_size < 2 || d->tile_size > 256 || (d->tile_size & 1)) return HMFSR_E_INVALID;
+  if (d->tile_size < 8 || d->tile_size > 256 || (d->tile_size & 1)) return HMFSR_E_INVALID;
   if (!finite(d->scale) || !(d->scale >= 1.f) || d->scale > 8.f) return HMFSR_E_INVALID;
   const double s = (double)d->scale;
   if (d->out_height != (int32_t)floor((double)d->height * s + 0.5) ||
@@ -126,6 +127,17 @@ MergeConsts make_merge(const hmfsr_desc* d, const hmfsr_tuning* t, const Geometr
   return m;
 }
 
+// Tile shape of the merge kernel: HMFSR_MERGE_VARIANT overrides the default.
+int merge_variant(const Geometry& g) {
+  (void)g;
+  const char* env = getenv("HMFSR_MERGE_VARIANT");
+  if (env) {
+    const int v = atoi(env);
+    if (v >= 0 && v < kNumMergeVariants) return v;
+  }
+  return 0;
+}
+
 // Current device, checked to be gfx950 (cached).
 hmfsr_status current_device(int* dev_out) {
   int dev = 0;
@@ -190,7 +202,8 @@ hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, con
   if (launch_robust(g, make_robust(desc, tuning), frames, motion, w.s_tile, w.rmin, nullptr, s) !=
       hipSuccess)
     return HMFSR_E_HIP;
-  if (launch_merge(g, make_merge(desc, tuning, g), frames, motion, w.rmin, out, s) != hipSuccess)
+  if (launch_merge(merge_variant(g), g, make_merge(desc, tuning, g), frames, motion, w.rmin, out, s) !=
+      hipSuccess)
     return HMFSR_E_HIP;
   return HMFSR_OK;
 }

@@ -1,0 +1,23 @@
+// Small device helpers shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace hmfsr {
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Minimum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Row of flat index k in a row-major window of width w, given inv = 1/w
+// rounded to float. (k + 1/2) / w lies at least 1/(2w) from an integer while
+// the float product errs by under (k / w) * 2^-22, so the floor is exact for
+// every k < 2^16.
+__device__ __forceinline__ int split_row(int k, float inv) { return (int)(((float)k + 0.5f) * inv); }
+
+}  // namespace hmfsr

@@ -56,7 +56,14 @@ hipError_t launch_prior(const Geometry& g, const PriorConsts& pc, const float* m
 hipError_t launch_robust(const Geometry& g, const RobustConsts& rc, const uint16_t* frames,
                          const float* motion, const float* s_tile, float* rmin, float* robust,
                          hipStream_t stream);
-hipError_t launch_merge(const Geometry& g, const MergeConsts& mc, const uint16_t* frames,
+// Compiled tile shapes of the merge kernel (64 columns x rows, threads).
+struct MergeVariant {
+  const char* name;
+  int rows, threads;
+};
+extern const MergeVariant kMergeVariants[];
+extern const int kNumMergeVariants;
+hipError_t launch_merge(int variant, const Geometry& g, const MergeConsts& mc, const uint16_t* frames,
                         const float* motion, const float* rmin, float* out, hipStream_t stream);
 hipError_t launch_fill(float* p, float v, size_t n, hipStream_t stream);
 hipError_t launch_omega_map(const Geometry& g, const OmegaConsts& oc, const uint16_t* frames,

@@ -24,16 +24,37 @@ struct OmegaConsts {
   double inv_16_range_dtr;  // 1 / (16 * range * d_tr)
 };
 
-// l[a][b]: quad sums of the 3x3 half-res window around the pixel (edge-clamped).
-__device__ __forceinline__ void omega_from_quads(const int (&l)[3][3], const OmegaConsts& c,
+// 1 / d to float64 accuracy: hardware reciprocal refined by two Newton steps.
+__device__ __forceinline__ double recip64(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
+// sqrt(x) for x >= 0 to ~1e-15 relative: hardware reciprocal square root
+// refined by two Newton steps (the correctly rounded library square root
+// costs twice as many instructions, and nothing here needs the last bit).
+__device__ __forceinline__ double sqrt64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x, y * y, 1.5);
+  y = y * fma(-0.5 * x, y * y, 1.5);
+  return x > 0.0 ? x * y : 0.0;
+}
+
+// l[a][b]: quad sums of the 3x3 half-res window around the pixel (edge-clamped),
+// as int or as float holding integers (differences stay exact below 2^24).
+template <typename Q>
+__device__ __forceinline__ void omega_from_quads(const Q (&l)[3][3], const OmegaConsts& c,
                                                  double& oxx, double& oxy, double& oyy) {
   double txx = 0.0, txy = 0.0, tyy = 0.0;
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      const int gxi = (l[a][b + 1] - l[a][b]) + (l[a + 1][b + 1] - l[a + 1][b]);
-      const int gyi = (l[a + 1][b] - l[a][b]) + (l[a + 1][b + 1] - l[a][b + 1]);
+      const Q gxi = (l[a][b + 1] - l[a][b]) + (l[a + 1][b + 1] - l[a + 1][b]);
+      const Q gyi = (l[a + 1][b] - l[a][b]) + (l[a + 1][b + 1] - l[a][b + 1]);
       const double gx = (double)gxi, gy = (double)gyi;
       txx += gx * gx;
       txy += gx * gy;
@@ -42,7 +63,7 @@ __device__ __forceinline__ void omega_from_quads(const int (&l)[3][3], const Ome
   }
   // Closed-form eigen-analysis: lambda1,2 = tr/2 +- rad; lambda1 - lambda2 = 2 rad.
   const double half = 0.5 * (txx - tyy);
-  const double rad = sqrt(half * half + txy * txy);
+  const double rad = sqrt64(half * half + txy * txy);
   const double tr = txx + tyy;
   double ex, ey;  // dominant eigenvector (gradient direction), unnormalised
   if (txy == 0.0 && txx == tyy) {
@@ -55,14 +76,14 @@ __device__ __forceinline__ void omega_from_quads(const int (&l)[3][3], const Ome
     ex = txy;
     ey = rad - half;
   }
-  const double inv_n2 = 1.0 / (ex * ex + ey * ey);
+  const double inv_n2 = recip64(ex * ex + ey * ey);
   const double gx2 = ex * ex * inv_n2, gy2 = ey * ey * inv_n2, gxy = ex * ey * inv_n2;
 
-  const double A = tr > 0.0 ? 1.0 + sqrt(2.0 * rad / tr) : 1.0;
-  double D = 1.0 - sqrt(0.5 * tr + rad) * c.inv_16_range_dtr + c.d_th;
+  const double A = tr > 0.0 ? 1.0 + sqrt64(2.0 * rad * recip64(tr)) : 1.0;
+  double D = 1.0 - sqrt64(0.5 * tr + rad) * c.inv_16_range_dtr + c.d_th;
   D = D < 0.0 ? 0.0 : (D > 1.0 ? 1.0 : D);
   const double k1s = (1.0 - D) * (c.kd_st * A) + D * c.kd_dn;
-  const double k2s = (1.0 - D) * (c.kd_sh / A) + D * c.kd_dn;
+  const double k2s = (1.0 - D) * (c.kd_sh * recip64(A)) + D * c.kd_dn;
   const double k1 = k1s * k1s, k2 = k2s * k2s;
   // eq. (4): variance k1 along the edge (perpendicular to the gradient), k2 across it.
   oxx = k1 * gy2 + k2 * gx2;

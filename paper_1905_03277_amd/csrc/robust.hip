@@ -3,15 +3,16 @@
 // (eq. 7-8, precomputed per tile) and the 5x5 minimum (eq. 9).
 //
 // One workgroup owns a 32x16 tile of the base half-res grid and loops over the
-// frames. The base frame's 3x3 guide mean and the noise-corrected sigma are
-// computed once into LDS; for each aligned frame the guide around the warped
-// footprint is staged into LDS, box-filtered, sampled bilinearly at u + v/2
-// for every robustness pixel of the tile plus a 2-pixel border, and the 5x5
-// minimum of the result is written to global memory.
+// frames. The robustness is evaluated on the tile plus a 2-pixel border (the
+// min-pool footprint); border pixels outside the grid repeat the edge pixel,
+// which is what the edge-clamped 5x5 minimum reads. The base frame's 3x3 guide
+// mean and noise-corrected sigma are computed once into LDS; for each aligned
+// frame the guide around the warped footprint is staged (edge-replicated),
+// box-filtered, and sampled bilinearly at u + v/2 for every robustness pixel.
 //
-// All colour statistics are kept in raw units (black level subtracted only
-// where the noise model needs brightness): the ratio d^2 / sigma^2 of eq. (5)
-// is scale-free.
+// Colour statistics are kept in raw units (the black level enters only the
+// noise model's brightness): the ratio d^2 / sigma^2 of eq. (5) is scale-free.
+#include "device_util.h"
 #include "hmfsr_internal.h"
 
 namespace hmfsr {
@@ -20,19 +21,12 @@ namespace {
 constexpr int RB_W = 32, RB_H = 16;              // output tile of R_hat (half-res px)
 constexpr int RR_W = RB_W + 4, RR_H = RB_H + 4;  // robustness region incl. the min-pool border
 constexpr int RR_N = RR_W * RR_H;
-constexpr int MU_CAP = 1000;                     // frame-n box-mean region
-constexpr int GU_CAP = 1150;                     // frame-n guide region
+constexpr int MU_CAP = 1000;                     // frame-n box-mean window
+constexpr int GU_CAP = 1150;                     // frame-n guide window
+constexpr int TT_X = RR_W / 4 + 2, TT_Y = RR_H / 4 + 2;  // alignment tiles spanned (T >= 8)
 constexpr int THREADS = 256;
 
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
-  return v;
-}
-
-// Guide pixel (I, J) of a frame in raw units: R, mean of the greens, B.
+// Guide pixel (I, J) of a frame in raw units: R, mean of the two greens, B.
 __device__ __forceinline__ void load_guide(const uint16_t* f, const Geometry& g, int I, int J,
                                            float& r, float& gr, float& b) {
   const uint32_t top = *(const uint32_t*)(f + (size_t)(2 * I) * g.W + 2 * J);
@@ -43,15 +37,9 @@ __device__ __forceinline__ void load_guide(const uint16_t* f, const Geometry& g,
   b = (float)q[g.blue_pos];
 }
 
-// Continuous half-res index u + v/2 of base pixel (I, J) in the aligned frame.
-// Clamping to [-1, w] x [-1, h] leaves the edge-clamped bilinear sample
-// unchanged and keeps non-finite vectors inside the staged buffers.
-__device__ __forceinline__ void warped_pos(const float* mv, const Geometry& g, int I, int J, int ty,
-                                           int tx, double& hx, double& hy) {
-  const float* v = mv + ((size_t)ty * g.TX + tx) * 2;
-  hx = fmin(fmax((double)J + (double)v[0] * 0.5, -1.0), (double)g.w);
-  hy = fmin(fmax((double)I + (double)v[1] * 0.5, -1.0), (double)g.h);
-}
+struct Bounds4 {
+  int x0, x1, y0, y1;  // range of the bilinear base corner floor(u + v/2)
+};
 
 __global__ __launch_bounds__(THREADS) void k_robust(const uint16_t* __restrict__ frames,
                                                     const float* __restrict__ motion,
@@ -64,32 +52,59 @@ __global__ __launch_bounds__(THREADS) void k_robust(const uint16_t* __restrict__
   __shared__ float sMu[3][MU_CAP];
   __shared__ float sR[RR_N];
   __shared__ float sTmp[RR_H * RB_W];
+  __shared__ int sTyR[RR_H], sTxR[RR_W];        // alignment tile of each region row / column
+  __shared__ int sRlo[TT_Y], sRhi[TT_Y], sClo[TT_X], sChi[TT_X];
+  __shared__ float2 sV[TT_X * TT_Y];
+  __shared__ float sS[TT_X * TT_Y];
+  __shared__ Bounds4 sTB[TT_X * TT_Y];
   __shared__ int sRed[4];
 
   const int tid = threadIdx.x;
   const int I0 = blockIdx.y * RB_H, J0 = blockIdx.x * RB_W;
-  // robustness region (clamped to the grid): rows [ra0, ra1), cols [ca0, ca1)
-  const int ra0 = max(I0 - 2, 0), ra1 = min(I0 + RB_H + 2, g.h);
-  const int ca0 = max(J0 - 2, 0), ca1 = min(J0 + RB_W + 2, g.w);
-  const int rw = ca1 - ca0, rh = ra1 - ra0, rn = rw * rh;
+  const int ra0 = I0 - 2, ca0 = J0 - 2;  // region origin (may be outside the grid)
   const size_t plane = (size_t)g.h * g.w;
+
+  if (tid < RR_W) sTxR[tid] = min(2 * clampi(ca0 + tid, 0, g.w - 1) / g.T, g.TX - 1);
+  if (tid >= 64 && tid < 64 + RR_H) {
+    const int r = tid - 64;
+    sTyR[r] = min(2 * clampi(ra0 + r, 0, g.h - 1) / g.T, g.TY - 1);
+  }
+  __syncthreads();
+  const int txA = sTxR[0], tyA = sTyR[0];
+  const int ntx = sTxR[RR_W - 1] - txA + 1, nty = sTyR[RR_H - 1] - tyA + 1, ntiles = ntx * nty;
+  if (tid < RR_W) {
+    const int t = sTxR[tid] - txA;
+    if (tid == 0 || sTxR[tid - 1] != sTxR[tid]) sClo[t] = tid;
+    if (tid == RR_W - 1 || sTxR[tid + 1] != sTxR[tid]) sChi[t] = tid;
+  }
+  if (tid >= 64 && tid < 64 + RR_H) {
+    const int r = tid - 64, t = sTyR[r] - tyA;
+    if (r == 0 || sTyR[r - 1] != sTyR[r]) sRlo[t] = r;
+    if (r == RR_H - 1 || sTyR[r + 1] != sTyR[r]) sRhi[t] = r;
+  }
 
   // ---- base frame statistics, once ------------------------------------
   {
     const uint16_t* f = frames + (size_t)g.ref * g.H * g.W;
-    const int gr0 = max(ra0 - 1, 0), gr1 = min(ra1, g.h - 1);
-    const int gc0 = max(ca0 - 1, 0), gc1 = min(ca1, g.w - 1);
+    // guide rows/cols around the clamped region, edge-replicated one step further
+    const int gr0 = clampi(ra0, 0, g.h - 1) - 1, gr1 = clampi(ra0 + RR_H - 1, 0, g.h - 1) + 1;
+    const int gc0 = clampi(ca0, 0, g.w - 1) - 1, gc1 = clampi(ca0 + RR_W - 1, 0, g.w - 1) + 1;
     const int gw = gc1 - gc0 + 1, gn = gw * (gr1 - gr0 + 1);
+    const float ginv = 1.f / (float)gw;
     for (int k = tid; k < gn; k += THREADS) {
+      const int rr = split_row(k, ginv);
       float r, gg, b;
-      load_guide(f, g, gr0 + k / gw, gc0 + k % gw, r, gg, b);
+      load_guide(f, g, clampi(gr0 + rr, 0, g.h - 1), clampi(gc0 + k - rr * gw, 0, g.w - 1), r, gg, b);
       sGuide[0][k] = r;
       sGuide[1][k] = gg;
       sGuide[2][k] = b;
     }
     __syncthreads();
-    for (int k = tid; k < rn; k += THREADS) {
-      const int I = ra0 + k / rw, J = ca0 + k % rw;
+    const float rinv = 1.f / (float)RR_W;
+    for (int k = tid; k < RR_N; k += THREADS) {
+      const int rr = split_row(k, rinv), cc = k - rr * RR_W;
+      const int I = clampi(ra0 + rr, 0, g.h - 1), J = clampi(ca0 + cc, 0, g.w - 1);
+      const int o = (I - 1 - gr0) * gw + (J - 1 - gc0);
       float den = 0.f;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -99,18 +114,17 @@ __global__ __launch_bounds__(THREADS) void k_robust(const uint16_t* __restrict__
         for (int a = 0; a < 3; ++a)
 #pragma unroll
           for (int b = 0; b < 3; ++b) {
-            const int ii = clampi(I + a - 1, 0, g.h - 1) - gr0, jj = clampi(J + b - 1, 0, g.w - 1) - gc0;
-            v[a * 3 + b] = sGuide[c][ii * gw + jj];
+            v[a * 3 + b] = sGuide[c][o + a * gw + b];
             s += v[a * 3 + b];
           }
-        const float mu = s / 9.f;
+        const float mu = s * (1.f / 9.f);
         float var_ms = 0.f;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) var_ms += (v[q] - mu) * (v[q] - mu);
-        var_ms /= 9.f;
+        for (int q = 0; q < 9; ++q) var_ms = fmaf(v[q] - mu, v[q] - mu, var_ms);
+        var_ms *= (1.f / 9.f);
         // noise model in raw units at the base brightness; the guide green is
         // the mean of two greens, so its variance is halved.
-        float var_md = rc.a_r * fmaxf(mu - rc.black, 0.f) + rc.b_r;
+        float var_md = fmaf(rc.a_r, fmaxf(mu - rc.black, 0.f), rc.b_r);
         if (c == 1) var_md *= 0.5f;
         sMuRef[c][k] = mu;
         den += fmaxf(var_ms, var_md);  // sigma = max(sigma_ms, sigma_md), eq. (6)
@@ -120,133 +134,142 @@ __global__ __launch_bounds__(THREADS) void k_robust(const uint16_t* __restrict__
   }
 
   // ---- aligned frames -------------------------------------------------
-  const int tyA = min(2 * ra0 / g.T, g.TY - 1), tyB = min(2 * (ra1 - 1) / g.T, g.TY - 1);
-  const int txA = min(2 * ca0 / g.T, g.TX - 1), txB = min(2 * (ca1 - 1) / g.T, g.TX - 1);
+  const float vlim = (float)(max(g.W, g.H) + 16);
   for (int n = 0; n < g.n; ++n) {
     if (n == g.ref) continue;
     const uint16_t* f = frames + (size_t)n * g.H * g.W;
-    const float* mv = motion + (size_t)n * g.TY * g.TX * 2;
-    const float* st = s_tile + (size_t)n * g.TY * g.TX;
-    // Segments: the whole region when its warped footprint fits the LDS
-    // buffers, otherwise one alignment tile at a time.
-    int seg = -1;
-    const int nseg_tiles = (tyB - tyA + 1) * (txB - txA + 1);
+    __syncthreads();
+    if (tid < ntiles) {
+      const int ky = tid / ntx, kx = tid - ky * ntx;
+      const size_t t = ((size_t)n * g.TY + tyA + ky) * g.TX + txA + kx;
+      const float* p = motion + 2 * t;
+      // clamping keeps non-finite or huge vectors finite and changes no result
+      sV[tid] = make_float2(fminf(fmaxf(p[0], -vlim), vlim), fminf(fmaxf(p[1], -vlim), vlim));
+      sS[tid] = s_tile[t];
+    }
+    if (tid < 4) sRed[tid] = 0x7fffffff;
+    __syncthreads();
+    // footprint of each alignment tile (monotonic in the pixel position)
+    if (tid < ntiles) {
+      const int ky = tid / ntx, kx = tid - ky * ntx;
+      const float2 v = sV[tid];
+      Bounds4 b;
+      b.x0 = (int)floor((double)clampi(ca0 + sClo[kx], 0, g.w - 1) + (double)v.x * 0.5);
+      b.x1 = (int)floor((double)clampi(ca0 + sChi[kx], 0, g.w - 1) + (double)v.x * 0.5);
+      b.y0 = (int)floor((double)clampi(ra0 + sRlo[ky], 0, g.h - 1) + (double)v.y * 0.5);
+      b.y1 = (int)floor((double)clampi(ra0 + sRhi[ky], 0, g.h - 1) + (double)v.y * 0.5);
+      sTB[tid] = b;
+      atomicMin(&sRed[0], b.x0); atomicMin(&sRed[1], -b.x1);
+      atomicMin(&sRed[2], b.y0); atomicMin(&sRed[3], -b.y1);
+    }
+    __syncthreads();
     bool whole = true;
+    int seg = 0;
     while (true) {
-      const int sty = whole ? -1 : tyA + seg / (txB - txA + 1);
-      const int stx = whole ? -1 : txA + seg % (txB - txA + 1);
-      // bounds of the bilinear corners over the segment's pixels
-      __syncthreads();
-      if (tid < 4) sRed[tid] = 0x7fffffff;
-      __syncthreads();
-      int b0 = 0x7fffffff, b1 = 0x7fffffff, b2 = 0x7fffffff, b3 = 0x7fffffff;
-      for (int k = tid; k < rn; k += THREADS) {
-        const int I = ra0 + k / rw, J = ca0 + k % rw;
-        const int ty = min(2 * I / g.T, g.TY - 1), tx = min(2 * J / g.T, g.TX - 1);
-        if (!whole && (ty != sty || tx != stx)) continue;
-        double hx, hy;
-        warped_pos(mv, g, I, J, ty, tx, hx, hy);
-        const int x0 = (int)floor(hx), y0 = (int)floor(hy);
-        b0 = min(b0, x0); b1 = min(b1, -x0); b2 = min(b2, y0); b3 = min(b3, -y0);
+      Bounds4 bd;
+      if (whole) {
+        bd.x0 = sRed[0]; bd.x1 = -sRed[1]; bd.y0 = sRed[2]; bd.y1 = -sRed[3];
+      } else {
+        bd = sTB[seg];
       }
-      b0 = wave_min(b0); b1 = wave_min(b1); b2 = wave_min(b2); b3 = wave_min(b3);
-      if ((tid & 63) == 0) {
-        atomicMin(&sRed[0], b0); atomicMin(&sRed[1], b1);
-        atomicMin(&sRed[2], b2); atomicMin(&sRed[3], b3);
-      }
-      __syncthreads();
-      const int xmin = sRed[0], xmax = -sRed[1], ymin = sRed[2], ymax = -sRed[3];
-      bool empty = xmin > xmax;
-      // box-mean region (bilinear corners) and guide region (box border), clamped
-      const int mc0 = clampi(xmin, 0, g.w - 1), mc1 = clampi(xmax + 1, 0, g.w - 1);
-      const int mr0 = clampi(ymin, 0, g.h - 1), mr1 = clampi(ymax + 1, 0, g.h - 1);
-      const int gc0 = max(mc0 - 1, 0), gc1 = min(mc1 + 1, g.w - 1);
-      const int gr0 = max(mr0 - 1, 0), gr1 = min(mr1 + 1, g.h - 1);
-      const int mw = mc1 - mc0 + 1, mn = mw * (mr1 - mr0 + 1);
+      // box-mean window: every bilinear corner (unclamped; entries outside the
+      // grid repeat the edge); guide window: their clamped 3x3 neighbourhoods.
+      const int mc0 = bd.x0, mw = bd.x1 - bd.x0 + 2;
+      const int mr0 = bd.y0, mh = bd.y1 - bd.y0 + 2;
+      const int gc0 = clampi(mc0, 0, g.w - 1) - 1, gc1 = clampi(mc0 + mw - 1, 0, g.w - 1) + 1;
+      const int gr0 = clampi(mr0, 0, g.h - 1) - 1, gr1 = clampi(mr0 + mh - 1, 0, g.h - 1) + 1;
       const int gw = gc1 - gc0 + 1, gn = gw * (gr1 - gr0 + 1);
-      if (!empty && whole && (mn > MU_CAP || gn > GU_CAP)) {
-        whole = false;  // fall back to one alignment tile per pass
+      if (whole && (mw * mh > MU_CAP || gn > GU_CAP)) {
+        whole = false;  // uniform decision: one alignment tile per pass
         seg = 0;
         continue;
       }
-      if (!empty) {
+      {
+        const float ginv = 1.f / (float)gw;
         for (int k = tid; k < gn; k += THREADS) {
+          const int rr = split_row(k, ginv);
           float r, gg, b;
-          load_guide(f, g, gr0 + k / gw, gc0 + k % gw, r, gg, b);
+          load_guide(f, g, clampi(gr0 + rr, 0, g.h - 1), clampi(gc0 + k - rr * gw, 0, g.w - 1), r, gg, b);
           sGuide[0][k] = r;
           sGuide[1][k] = gg;
           sGuide[2][k] = b;
         }
-        __syncthreads();
-        for (int k = tid; k < mn; k += THREADS) {
-          const int I = mr0 + k / mw, J = mc0 + k % mw;
+      }
+      __syncthreads();
+      {
+        const float minv = 1.f / (float)mw;
+        for (int k = tid; k < mw * mh; k += THREADS) {
+          const int rr = split_row(k, minv), cc = k - rr * mw;
+          const int I = clampi(mr0 + rr, 0, g.h - 1), J = clampi(mc0 + cc, 0, g.w - 1);
+          const int o = (I - 1 - gr0) * gw + (J - 1 - gc0);
           float s0 = 0.f, s1 = 0.f, s2 = 0.f;
 #pragma unroll
           for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-              const int q = (clampi(I + a - 1, 0, g.h - 1) - gr0) * gw + clampi(J + b - 1, 0, g.w - 1) - gc0;
+              const int q = o + a * gw + b;
               s0 += sGuide[0][q];
               s1 += sGuide[1][q];
               s2 += sGuide[2][q];
             }
-          sMu[0][k] = s0 / 9.f;
-          sMu[1][k] = s1 / 9.f;
-          sMu[2][k] = s2 / 9.f;
+          sMu[0][k] = s0 * (1.f / 9.f);
+          sMu[1][k] = s1 * (1.f / 9.f);
+          sMu[2][k] = s2 * (1.f / 9.f);
         }
-        __syncthreads();
-        for (int k = tid; k < rn; k += THREADS) {
-          const int I = ra0 + k / rw, J = ca0 + k % rw;
-          const int ty = min(2 * I / g.T, g.TY - 1), tx = min(2 * J / g.T, g.TX - 1);
-          if (!whole && (ty != sty || tx != stx)) continue;
-          double hx, hy;
-          warped_pos(mv, g, I, J, ty, tx, hx, hy);
+      }
+      __syncthreads();
+      {
+        const float rinv = 1.f / (float)RR_W;
+        for (int k = tid; k < RR_N; k += THREADS) {
+          const int rr = split_row(k, rinv), cc = k - rr * RR_W;
+          const int kt = (sTyR[rr] - tyA) * ntx + (sTxR[cc] - txA);
+          if (!whole && kt != seg) continue;
+          const int I = clampi(ra0 + rr, 0, g.h - 1), J = clampi(ca0 + cc, 0, g.w - 1);
+          const float2 v = sV[kt];
+          const double hx = (double)J + (double)v.x * 0.5, hy = (double)I + (double)v.y * 0.5;
           const double fhx = floor(hx), fhy = floor(hy);
           const float fx = (float)(hx - fhx), fy = (float)(hy - fhy);
-          const int x0 = (int)fhx, y0 = (int)fhy;
-          const int xa = clampi(x0, 0, g.w - 1) - mc0, xb = clampi(x0 + 1, 0, g.w - 1) - mc0;
-          const int ya = (clampi(y0, 0, g.h - 1) - mr0) * mw, yb = (clampi(y0 + 1, 0, g.h - 1) - mr0) * mw;
+          const int ya = ((int)fhy - mr0) * mw + ((int)fhx - mc0);
           float num = 0.f;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const float top = (1.f - fx) * sMu[c][ya + xa] + fx * sMu[c][ya + xb];
-            const float bot = (1.f - fx) * sMu[c][yb + xa] + fx * sMu[c][yb + xb];
-            const float mu_al = (1.f - fy) * top + fy * bot;
+            const float m00 = sMu[c][ya], m01 = sMu[c][ya + 1];
+            const float m10 = sMu[c][ya + mw], m11 = sMu[c][ya + mw + 1];
+            const float top = fmaf(fx, m01 - m00, m00), bot = fmaf(fx, m11 - m10, m10);
+            const float mu_al = fmaf(fy, bot - top, top);
             const float mu_ref = sMuRef[c][k];
-            float var = rc.a_r * fmaxf(mu_ref - rc.black, 0.f) + rc.b_r;
+            float var = fmaf(rc.a_r, fmaxf(mu_ref - rc.black, 0.f), rc.b_r);
             if (c == 1) var *= 0.5f;
             const float dms = mu_ref - mu_al;
             const float dms2 = dms * dms;
-            const float d = dms * dms2 / (dms2 + var * (2.f / 9.f));  // Wiener shrinkage, eq. (6)
-            num += d * d;
+            // Wiener shrinkage of eq. (6): d = d_ms^3 / (d_ms^2 + d_md^2), d_md^2 = 2 var / 9
+            const float dd = dms * dms2 * __builtin_amdgcn_rcpf(fmaf(var, 2.f / 9.f, dms2));
+            num = fmaf(dd, dd, num);
           }
-          const float s = st[(size_t)ty * g.TX + tx];
-          float R = s * __expf(-num * sInvDen[k]) - rc.t;  // eq. (5)
+          const float R = sS[kt] * __expf(-num * sInvDen[k]) - rc.t;  // eq. (5)
           sR[k] = fminf(fmaxf(R, 0.f), 1.f);
         }
       }
-      if (whole) break;
-      if (++seg >= nseg_tiles) break;
+      if (whole || ++seg >= ntiles) break;
+      __syncthreads();
     }
     __syncthreads();
-    // eq. (9): 5x5 minimum, separable, over existing pixels
+    // eq. (9): 5x5 minimum, separable (the region repeats edge pixels)
     const int ow = min(RB_W, g.w - J0), oh = min(RB_H, g.h - I0);
-    for (int k = tid; k < rh * ow; k += THREADS) {
-      const int r = k / ow, J = J0 + k % ow;
-      float m = 1.f;
-#pragma unroll
-      for (int b = -2; b <= 2; ++b) m = fminf(m, sR[r * rw + clampi(J + b, 0, g.w - 1) - ca0]);
-      sTmp[r * RB_W + (J - J0)] = m;
+    for (int k = tid; k < RR_H * RB_W; k += THREADS) {
+      const int r = k >> 5, j = k & 31;  // RB_W == 32
+      const float* row = sR + r * RR_W + j;
+      sTmp[k] = fminf(fminf(fminf(row[0], row[1]), fminf(row[2], row[3])), row[4]);
     }
     __syncthreads();
-    for (int k = tid; k < oh * ow; k += THREADS) {
-      const int I = I0 + k / ow, j = k % ow;
-      float m = 1.f;
-#pragma unroll
-      for (int a = -2; a <= 2; ++a) m = fminf(m, sTmp[(clampi(I + a, 0, g.h - 1) - ra0) * RB_W + j]);
-      const size_t o = (size_t)n * plane + (size_t)I * g.w + J0 + j;
+    for (int k = tid; k < RB_H * RB_W; k += THREADS) {
+      const int i = k >> 5, j = k & 31;
+      if (i >= oh || j >= ow) continue;
+      const float* col = sTmp + i * RB_W + j;
+      const float m = fminf(fminf(fminf(col[0], col[RB_W]), fminf(col[2 * RB_W], col[3 * RB_W])), col[4 * RB_W]);
+      const size_t o = (size_t)n * plane + (size_t)(I0 + i) * g.w + J0 + j;
       rmin[o] = m;
-      if (robust) robust[o] = sR[(I - ra0) * rw + (J0 + j - ca0)];
+      if (robust) robust[o] = sR[(i + 2) * RR_W + j + 2];
     }
   }
 }

@@ -45,7 +45,7 @@ def _call(desc, tun, ptr=1):
 @pytest.mark.parametrize("field,value", [
     ("n_frames", 0), ("height", 63), ("width", 2), ("ref_frame", 4), ("ref_frame", -1),
     ("black_level", 5000.0), ("noise_b", 0.0), ("noise_a", -1e-3), ("tile_size", 15),
-    ("tile_size", 0), ("scale", 0.5), ("scale", float("nan")), ("out_height", 95),
+    ("tile_size", 0), ("tile_size", 6), ("scale", 0.5), ("scale", float("nan")), ("out_height", 95),
     ("out_width", 143),
 ])
 def test_invalid_descriptor_rejected(field, value):

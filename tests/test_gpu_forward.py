@@ -60,7 +60,7 @@ SMALL = [
     ("single_frame", 1, 64, 64, 1.5, 16, 0, 0, 1.5),
     ("two_frames", 2, 64, 64, 2.0, 16, 0, 1, 3.0),
     ("fifteen_frames", 15, 64, 80, 1.0, 16, 0, 0, 2.0),
-    ("tiny_4x4", 3, 4, 4, 1.0, 2, 0, 0, 0.5),
+    ("tiny_4x4", 3, 4, 4, 1.0, 8, 0, 0, 0.5),
     ("odd_scale", 3, 40, 60, 1.3, 8, 0, 0, 1.0),
     ("tile64", 3, 160, 130, 1.0, 64, 0, 0, 1.0),
 ]
@@ -161,3 +161,18 @@ def test_full_size_sampled_parity(config):
         worst = max(worst, st["max"])
         assert_parity(got, want, f"config {config} window ({oy},{ox})")
     print(f"config{config} worst window max-abs {worst:.3g}")
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_every_tile_shape_matches(variant, monkeypatch):
+    """Each compiled tile shape of the merge kernel gives the oracle's result,
+    including the per-alignment-tile fallback for a divergent motion field."""
+    monkeypatch.setenv("HMFSR_MERGE_VARIANT", str(variant))
+    b = synth.make_burst(5, 96, 160, seed=900 + variant, scale=1.5, tile_size=16)
+    f, m = b.numpy()
+    case("variant", v=variant)
+    assert_parity(gpu_merge(f, m, b.desc, b.tuning), om.merge(f, m, b.desc, b.tuning), "smooth")
+    m = m.copy()
+    m[2, 1, 2] += np.float32(9.0)        # one far-off tile forces the fallback path
+    m[3, 3, 5, 1] -= np.float32(12.0)
+    assert_parity(gpu_merge(f, m, b.desc, b.tuning), om.merge(f, m, b.desc, b.tuning), "divergent")
