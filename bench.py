@@ -19,23 +19,34 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks and unit counts.
 HBM_PEAK_GBS = 8000.0
 CUS, CLOCK_GHZ, LANES = 256, 2.4, 64
-ALU_PEAK_TOPS = CUS * LANES * CLOCK_GHZ / 1000.0   # non-packed vector lane-ops: 39.3 T/s
+ALU_PEAK_TOPS = CUS * LANES * CLOCK_GHZ / 1000.0   # vector lane-operations: 39.3 T/s
 
 
-def algorithmic_ops_per_pixel_frame(scale: float) -> float:
-    """Vector lane-operations the method needs per output pixel and frame:
-    181 for the nine-sample weighting and accumulation (eq. 1-2 with the
-    Omega / R bilinear reads) plus 224 per half-resolution pixel and frame for
-    the Omega chain (eq. 3-4, S.1) and the robustness chain (eq. 5-9),
-    amortised over the 4 s^2 output pixels each half-res pixel serves.
-    Divide, square root and exp count 4 (their issue cost)."""
-    return 181.0 + 224.0 / (4.0 * scale * scale)
+# Algorithmic vector operations of the method (see the op-count table in the
+# design notes): adds, multiplies, fmas, compares/min/max/selects count 1,
+# divide / square root / exp count 4 (their issue cost).
+OPS_SAMPLE = 161.0      # per output pixel and frame: nine-sample weights and accumulation
+OPS_OMEGA = 79.0        # per half-res pixel and frame: luma, structure tensor, eigen, S.1, Omega
+OPS_ROBUST = 98.0       # per half-res pixel and aligned frame: guide means, eq. 5-6, 5x5 min
 
 
-def algorithmic_bytes(desc) -> int:
-    """Each input byte read once, each output byte written once."""
+def algorithmic_ops(desc) -> dict:
+    """Algorithmic operation count of each kernel for one merge of `desc`."""
+    n, hp = desc.n_frames, (desc.height // 2) * (desc.width // 2)
+    pf = n * desc.out_height * desc.out_width
+    return {"k_merge": OPS_SAMPLE * pf + OPS_OMEGA * n * hp,
+            "k_robust": OPS_ROBUST * (n - 1) * hp}
+
+
+def algorithmic_bytes(desc) -> dict:
+    """Each input byte read once, each output byte written once, per kernel."""
     n, h, w = desc.n_frames, desc.height, desc.width
-    return 2 * n * h * w + 12 * desc.out_height * desc.out_width + 8 * n * desc.tiles_y * desc.tiles_x
+    hp = (h // 2) * (w // 2)
+    tiles = desc.tiles_y * desc.tiles_x
+    return {"k_merge": 2 * n * h * w + 8 * n * tiles + 4 * (n - 1) * hp
+            + 12 * desc.out_height * desc.out_width,
+            "k_robust": 2 * n * h * w + 12 * n * tiles + 4 * (n - 1) * hp,
+            "total": 2 * n * h * w + 8 * n * tiles + 12 * desc.out_height * desc.out_width}
 
 
 def cpu_baseline(burst, budget_s: float = 12.0):
@@ -115,12 +126,20 @@ def main():
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1) / args.steps
 
+    # per-kernel durations: a second pass with the library's event timing on
+    from paper_1905_03277_amd import binding
+    binding.hmfsr_profile_begin()
+    for _ in range(args.steps):
+        step()
+    stages = binding.hmfsr_profile_end()
+    kern_ms = {k: tot / max(cnt, 1) for k, (tot, cnt) in stages.items()}
+
     in_mp = d.n_frames * d.height * d.width / 1e6
     value = in_mp / (ms / 1e3)
-    pf = d.n_frames * d.out_height * d.out_width
-    ops = algorithmic_ops_per_pixel_frame(d.scale) * pf
-    achieved = ops / (ms / 1e3) / 1e12
-    bytes_ = algorithmic_bytes(d)
+    ops = algorithmic_ops(d)
+    byts = algorithmic_bytes(d)
+    dom = "k_merge"
+    achieved = ops[dom] / (kern_ms[dom] / 1e3) / 1e12
     line = {
         "metric": "merge input-Bayer MP/s at 12MP x 8 fwd",
         "value": round(value, 1),
@@ -139,10 +158,13 @@ def main():
                    "width": d.width, "scale": d.scale},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
                      "unit": "Top/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
-                     "kernel": "whole merge (all stages)"},
-        "hbm": {"algorithmic_bytes": bytes_, "achieved_GBs": round(bytes_ / (ms / 1e3) / 1e9, 1),
+                     "kernel": dom, "kernel_ms": round(kern_ms[dom], 4),
+                     "algorithmic_ops": ops[dom]},
+        "kernels_ms": {k: round(v, 4) for k, v in kern_ms.items()},
+        "hbm": {"algorithmic_bytes": byts["total"],
+                "achieved_GBs": round(byts["total"] / (ms / 1e3) / 1e9, 1),
                 "peak_GBs": HBM_PEAK_GBS,
-                "frac": round(bytes_ / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+                "frac": round(byts["total"] / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "wall_s_timed": round(wall, 3),
     }
     if not args.no_cpu_baseline:

@@ -140,6 +140,27 @@ hmfsr_status hmfsr_merge_maps(const hmfsr_desc* desc, const hmfsr_tuning* tuning
                               const uint16_t* frames, const float* motion, double* omega,
                               float* robust, float* robust_min, float* s_tile, void* stream);
 
+/*
+ * Per-stage GPU timing (the tracing aid of the library). Between
+ * hmfsr_profile_begin() and hmfsr_profile_end(), every kernel launch is
+ * bracketed by a pair of HIP events recorded on the call's own stream;
+ * hmfsr_profile_end() waits for the recorded events, adds up the elapsed
+ * times per stage and turns the recording off. Not meant for use while other
+ * threads issue merges.
+ */
+enum {
+  HMFSR_STAGE_PRIOR = 0,  /* motion prior per tile (eq. 7-8)           */
+  HMFSR_STAGE_ROBUST = 1, /* robustness and its 5x5 minimum (eq. 5-9)  */
+  HMFSR_STAGE_MERGE = 2,  /* kernel-regression accumulation (eq. 1-4)  */
+  HMFSR_NUM_STAGES = 8
+};
+typedef struct {
+  double ms_total[HMFSR_NUM_STAGES];  /* summed kernel time per stage, milliseconds */
+  int64_t launches[HMFSR_NUM_STAGES]; /* number of launches per stage             */
+} hmfsr_stage_times;
+hmfsr_status hmfsr_profile_begin(void);
+hmfsr_status hmfsr_profile_end(hmfsr_stage_times* out);
+
 /* Human-readable name of a status code (static storage). */
 const char* hmfsr_strerror(hmfsr_status status);
 

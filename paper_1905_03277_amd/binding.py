@@ -17,8 +17,12 @@ LIB_PATH = os.path.join(_HERE, "libhmfsr.so")
 HMFSR_OK, HMFSR_E_INVALID, HMFSR_E_UNSUPPORTED, HMFSR_E_HIP, HMFSR_E_NOMEM = 0, -1, -2, -3, -4
 
 # Every symbol include/hmfsr.h declares.
-EXPORTED = ("hmfsr_merge", "hmfsr_merge_maps", "hmfsr_strerror", "hmfsr_version",
-            "hmfsr_release")
+EXPORTED = ("hmfsr_merge", "hmfsr_merge_maps", "hmfsr_profile_begin", "hmfsr_profile_end",
+            "hmfsr_strerror", "hmfsr_version", "hmfsr_release")
+
+STAGE_PRIOR, STAGE_ROBUST, STAGE_MERGE = 0, 1, 2
+NUM_STAGES = 8
+STAGE_NAMES = {STAGE_PRIOR: "k_prior", STAGE_ROBUST: "k_robust", STAGE_MERGE: "k_merge"}
 
 
 class hmfsr_desc(ctypes.Structure):
@@ -35,6 +39,10 @@ class hmfsr_tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_float) for n in
                 ("k_detail", "k_denoise", "d_th", "d_tr", "k_stretch", "k_shrink", "s", "t",
                  "s_motion", "m_th")]
+
+
+class hmfsr_stage_times(ctypes.Structure):
+    _fields_ = [("ms_total", ctypes.c_double * NUM_STAGES), ("launches", ctypes.c_int64 * NUM_STAGES)]
 
 
 class HmfsrError(RuntimeError):
@@ -60,6 +68,10 @@ def lib() -> ctypes.CDLL:
         L.hmfsr_merge.restype = i32
         L.hmfsr_merge_maps.argtypes = [pd, pt, vp, vp, vp, vp, vp, vp, vp]
         L.hmfsr_merge_maps.restype = i32
+        L.hmfsr_profile_begin.argtypes = []
+        L.hmfsr_profile_begin.restype = i32
+        L.hmfsr_profile_end.argtypes = [ctypes.POINTER(hmfsr_stage_times)]
+        L.hmfsr_profile_end.restype = i32
         L.hmfsr_strerror.argtypes = [i32]
         L.hmfsr_strerror.restype = ctypes.c_char_p
         L.hmfsr_version.argtypes = []
@@ -99,6 +111,18 @@ def hmfsr_merge_maps(desc, tuning, frames: int, motion: int, omega: int, robust:
     _check(lib().hmfsr_merge_maps(ctypes.byref(desc), ctypes.byref(tuning), frames, motion,
                                   omega or None, robust or None, robust_min or None,
                                   s_tile or None, stream or None), "hmfsr_merge_maps")
+
+
+def hmfsr_profile_begin() -> None:
+    _check(lib().hmfsr_profile_begin(), "hmfsr_profile_begin")
+
+
+def hmfsr_profile_end() -> dict:
+    """{stage name: (total ms, launches)} of the launches since hmfsr_profile_begin."""
+    t = hmfsr_stage_times()
+    _check(lib().hmfsr_profile_end(ctypes.byref(t)), "hmfsr_profile_end")
+    return {STAGE_NAMES.get(i, f"stage{i}"): (t.ms_total[i], int(t.launches[i]))
+            for i in range(NUM_STAGES) if t.launches[i]}
 
 
 def hmfsr_version() -> int:

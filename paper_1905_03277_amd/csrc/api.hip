@@ -24,6 +24,37 @@ struct DeviceState {
 std::mutex g_mutex;
 DeviceState g_dev[kMaxDevices];
 
+// Optional per-stage timing: an event pair around every kernel launch.
+struct Timing {
+  bool on = false;
+  struct Pair { int stage; hipEvent_t a, b; };
+  std::vector<Pair> pairs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Timing g_timing;
+
+// Launch `fn` on `s`, bracketed by timing events when profiling is on.
+template <typename F>
+hipError_t timed(int stage, hipStream_t s, F fn) {
+  if (!g_timing.on) return fn();
+  hipEvent_t a = g_timing.get(), b = g_timing.get();
+  if (a) hipEventRecord(a, s);
+  const hipError_t err = fn();
+  if (b) hipEventRecord(b, s);
+  if (a && b) g_timing.pairs.push_back({stage, a, b});
+  return err;
+}
+
 bool finite(float v) { return isfinite(v) != 0; }
 
 // Colours of the 2x2 mosaic read row by row: 0 R, 1 G, 2 B.
@@ -135,7 +166,7 @@ int merge_variant(const Geometry& g) {
     const int v = atoi(env);
     if (v >= 0 && v < kNumMergeVariants) return v;
   }
-  return 0;
+  return 2;
 }
 
 // Current device, checked to be gfx950 (cached).
@@ -198,12 +229,19 @@ hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, con
   hipStream_t s = (hipStream_t)stream;
   if ((st = workspace(dev, work_bytes(g), s, &ws)) != HMFSR_OK) return st;
   const Work w = work_carve(ws, g);
-  if (launch_prior(g, make_prior(tuning), motion, w.s_tile, s) != hipSuccess) return HMFSR_E_HIP;
-  if (launch_robust(g, make_robust(desc, tuning), frames, motion, w.s_tile, w.rmin, nullptr, s) !=
-      hipSuccess)
+  const PriorConsts pc = make_prior(tuning);
+  const RobustConsts rc = make_robust(desc, tuning);
+  const MergeConsts mc = make_merge(desc, tuning, g);
+  const int variant = merge_variant(g);
+  if (timed(HMFSR_STAGE_PRIOR, s, [&] { return launch_prior(g, pc, motion, w.s_tile, s); }) != hipSuccess)
     return HMFSR_E_HIP;
-  if (launch_merge(merge_variant(g), g, make_merge(desc, tuning, g), frames, motion, w.rmin, out, s) !=
-      hipSuccess)
+  if (timed(HMFSR_STAGE_ROBUST, s, [&] {
+        return launch_robust(g, rc, frames, motion, w.s_tile, w.rmin, nullptr, s);
+      }) != hipSuccess)
+    return HMFSR_E_HIP;
+  if (timed(HMFSR_STAGE_MERGE, s, [&] {
+        return launch_merge(variant, g, mc, frames, motion, w.rmin, out, s);
+      }) != hipSuccess)
     return HMFSR_E_HIP;
   return HMFSR_OK;
 }
@@ -254,6 +292,38 @@ const char* hmfsr_strerror(hmfsr_status status) {
 }
 
 int32_t hmfsr_version(void) { return HMFSR_VERSION; }
+
+hmfsr_status hmfsr_profile_begin(void) {
+  std::lock_guard<std::mutex> lock(g_mutex);
+  for (auto& p : g_timing.pairs) {
+    g_timing.pool.push_back(p.a);
+    g_timing.pool.push_back(p.b);
+  }
+  g_timing.pairs.clear();
+  g_timing.on = true;
+  return HMFSR_OK;
+}
+
+hmfsr_status hmfsr_profile_end(hmfsr_stage_times* out) {
+  std::lock_guard<std::mutex> lock(g_mutex);
+  g_timing.on = false;
+  if (!out) return HMFSR_E_INVALID;
+  memset(out, 0, sizeof(*out));
+  hmfsr_status st = HMFSR_OK;
+  for (auto& p : g_timing.pairs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) {
+      st = HMFSR_E_HIP;
+    } else if (p.stage >= 0 && p.stage < HMFSR_NUM_STAGES) {
+      out->ms_total[p.stage] += ms;
+      out->launches[p.stage] += 1;
+    }
+    g_timing.pool.push_back(p.a);
+    g_timing.pool.push_back(p.b);
+  }
+  g_timing.pairs.clear();
+  return st;
+}
 
 void hmfsr_release(void) {
   std::lock_guard<std::mutex> lock(g_mutex);

@@ -22,7 +22,7 @@ constexpr int RB_W = 32, RB_H = 16;              // output tile of R_hat (half-r
 constexpr int RR_W = RB_W + 4, RR_H = RB_H + 4;  // robustness region incl. the min-pool border
 constexpr int RR_N = RR_W * RR_H;
 constexpr int MU_CAP = 1000;                     // frame-n box-mean window
-constexpr int GU_CAP = 1150;                     // frame-n guide window
+constexpr int GU_CAP = 1150;                     // frame-n guide window and row sums
 constexpr int TT_X = RR_W / 4 + 2, TT_Y = RR_H / 4 + 2;  // alignment tiles spanned (T >= 8)
 constexpr int THREADS = 256;
 
@@ -48,8 +48,8 @@ __global__ __launch_bounds__(THREADS) void k_robust(const uint16_t* __restrict__
                                                     float* __restrict__ robust) {
   __shared__ float sMuRef[3][RR_N];
   __shared__ float sInvDen[RR_N];
-  __shared__ float sGuide[3][GU_CAP];
-  __shared__ float sMu[3][MU_CAP];
+  __shared__ float sGuide[3][GU_CAP];  // guide, then the box means
+  __shared__ float sHs[3][GU_CAP];     // horizontal 3-sums
   __shared__ float sR[RR_N];
   __shared__ float sTmp[RR_H * RB_W];
   __shared__ int sTyR[RR_H], sTxR[RR_W];        // alignment tile of each region row / column
@@ -179,7 +179,8 @@ __global__ __launch_bounds__(THREADS) void k_robust(const uint16_t* __restrict__
       const int gc0 = clampi(mc0, 0, g.w - 1) - 1, gc1 = clampi(mc0 + mw - 1, 0, g.w - 1) + 1;
       const int gr0 = clampi(mr0, 0, g.h - 1) - 1, gr1 = clampi(mr0 + mh - 1, 0, g.h - 1) + 1;
       const int gw = gc1 - gc0 + 1, gn = gw * (gr1 - gr0 + 1);
-      if (whole && (mw * mh > MU_CAP || gn > GU_CAP)) {
+      const int gh = gr1 - gr0 + 1;
+      if (whole && (mw * mh > MU_CAP || gn > GU_CAP || gh * mw > GU_CAP)) {
         whole = false;  // uniform decision: one alignment tile per pass
         seg = 0;
         continue;
@@ -196,25 +197,25 @@ __global__ __launch_bounds__(THREADS) void k_robust(const uint16_t* __restrict__
         }
       }
       __syncthreads();
+      // 3x3 box mean, separable: row sums over the guide rows, then column sums
+      {
+        const float minv = 1.f / (float)mw;
+        for (int k = tid; k < gh * mw; k += THREADS) {
+          const int rr = split_row(k, minv), cc = k - rr * mw;
+          const int q = rr * gw + clampi(mc0 + cc, 0, g.w - 1) - 1 - gc0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) sHs[c][k] = (sGuide[c][q] + sGuide[c][q + 1]) + sGuide[c][q + 2];
+        }
+      }
+      __syncthreads();
       {
         const float minv = 1.f / (float)mw;
         for (int k = tid; k < mw * mh; k += THREADS) {
           const int rr = split_row(k, minv), cc = k - rr * mw;
-          const int I = clampi(mr0 + rr, 0, g.h - 1), J = clampi(mc0 + cc, 0, g.w - 1);
-          const int o = (I - 1 - gr0) * gw + (J - 1 - gc0);
-          float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+          const int q = (clampi(mr0 + rr, 0, g.h - 1) - 1 - gr0) * mw + cc;
 #pragma unroll
-          for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-              const int q = o + a * gw + b;
-              s0 += sGuide[0][q];
-              s1 += sGuide[1][q];
-              s2 += sGuide[2][q];
-            }
-          sMu[0][k] = s0 * (1.f / 9.f);
-          sMu[1][k] = s1 * (1.f / 9.f);
-          sMu[2][k] = s2 * (1.f / 9.f);
+          for (int c = 0; c < 3; ++c)
+            sGuide[c][k] = ((sHs[c][q] + sHs[c][q + mw]) + sHs[c][q + 2 * mw]) * (1.f / 9.f);
         }
       }
       __syncthreads();
@@ -233,8 +234,8 @@ __global__ __launch_bounds__(THREADS) void k_robust(const uint16_t* __restrict__
           float num = 0.f;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const float m00 = sMu[c][ya], m01 = sMu[c][ya + 1];
-            const float m10 = sMu[c][ya + mw], m11 = sMu[c][ya + mw + 1];
+            const float m00 = sGuide[c][ya], m01 = sGuide[c][ya + 1];
+            const float m10 = sGuide[c][ya + mw], m11 = sGuide[c][ya + mw + 1];
             const float top = fmaf(fx, m01 - m00, m00), bot = fmaf(fx, m11 - m10, m10);
             const float mu_al = fmaf(fy, bot - top, top);
             const float mu_ref = sMuRef[c][k];
