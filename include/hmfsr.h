@@ -141,6 +141,40 @@ hmfsr_status hmfsr_merge_maps(const hmfsr_desc* desc, const hmfsr_tuning* tuning
                               float* robust, float* robust_min, float* s_tile, void* stream);
 
 /*
+ * hmfsr_merge_batch -- merge many independent bursts (any mix of frame counts,
+ * sizes and scales) in one launch of a captured hipGraph.
+ *  n_bursts        1..65536
+ *  descs, tunings  HOST arrays [n_bursts], validated like hmfsr_merge's.
+ *  frames, motion, out
+ *                  HOST arrays [n_bursts] of DEVICE pointers with the
+ *                  layouts of hmfsr_merge.
+ * The graph holds a counter reset, the motion prior of every burst, one
+ * persistent robustness kernel and one persistent merge kernel per tile
+ * shape; persistent workgroups take (burst, tile) items from a global counter,
+ * most expensive bursts first. The first call for a set of shapes and buffers
+ * builds and instantiates the graph (synchronising `stream` once); later calls
+ * with the same descriptors and pointers replay it, uploading changed tuning
+ * values first (after synchronising `stream`). Results equal hmfsr_merge's
+ * for the same tile shape bit for bit.
+ */
+hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs,
+                               const hmfsr_tuning* tunings, const uint16_t* const* frames,
+                               const float* const* motion, float* const* out, void* stream);
+
+/*
+ * hmfsr_autotune -- time every compiled tile shape of the merge kernel on this
+ * burst (synchronising `stream`), remember the fastest for the burst's class
+ * (output scale <= 1, <= 1.5, <= 2, > 2 x frame count <= 4, <= 8, <= 15, > 15)
+ * and use it for later merges of that class. With HMFSR_TUNE_CACHE=<file> the
+ * table is read at first use and rewritten after each tuning. `out` receives
+ * the merge; `chosen` (host, nullable) the index of the chosen shape.
+ * HMFSR_MERGE_VARIANT=<index> overrides every choice.
+ */
+hmfsr_status hmfsr_autotune(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
+                            const uint16_t* frames, const float* motion, float* out, void* stream,
+                            int32_t* chosen);
+
+/*
  * Per-stage GPU timing (the tracing aid of the library). Between
  * hmfsr_profile_begin() and hmfsr_profile_end(), every kernel launch is
  * bracketed by a pair of HIP events recorded on the call's own stream;
@@ -152,6 +186,7 @@ enum {
   HMFSR_STAGE_PRIOR = 0,  /* motion prior per tile (eq. 7-8)           */
   HMFSR_STAGE_ROBUST = 1, /* robustness and its 5x5 minimum (eq. 5-9)  */
   HMFSR_STAGE_MERGE = 2,  /* kernel-regression accumulation (eq. 1-4)  */
+  HMFSR_STAGE_BATCH = 3,  /* one replay of a batched-merge graph       */
   HMFSR_NUM_STAGES = 8
 };
 typedef struct {

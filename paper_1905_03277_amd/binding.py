@@ -17,12 +17,14 @@ LIB_PATH = os.path.join(_HERE, "libhmfsr.so")
 HMFSR_OK, HMFSR_E_INVALID, HMFSR_E_UNSUPPORTED, HMFSR_E_HIP, HMFSR_E_NOMEM = 0, -1, -2, -3, -4
 
 # Every symbol include/hmfsr.h declares.
-EXPORTED = ("hmfsr_merge", "hmfsr_merge_maps", "hmfsr_profile_begin", "hmfsr_profile_end",
-            "hmfsr_strerror", "hmfsr_version", "hmfsr_release")
+EXPORTED = ("hmfsr_merge", "hmfsr_merge_maps", "hmfsr_merge_batch", "hmfsr_autotune",
+            "hmfsr_profile_begin", "hmfsr_profile_end", "hmfsr_strerror", "hmfsr_version",
+            "hmfsr_release")
 
-STAGE_PRIOR, STAGE_ROBUST, STAGE_MERGE = 0, 1, 2
+STAGE_PRIOR, STAGE_ROBUST, STAGE_MERGE, STAGE_BATCH = 0, 1, 2, 3
 NUM_STAGES = 8
-STAGE_NAMES = {STAGE_PRIOR: "k_prior", STAGE_ROBUST: "k_robust", STAGE_MERGE: "k_merge"}
+STAGE_NAMES = {STAGE_PRIOR: "k_prior", STAGE_ROBUST: "k_robust", STAGE_MERGE: "k_merge",
+               STAGE_BATCH: "batch_graph"}
 
 
 class hmfsr_desc(ctypes.Structure):
@@ -68,6 +70,11 @@ def lib() -> ctypes.CDLL:
         L.hmfsr_merge.restype = i32
         L.hmfsr_merge_maps.argtypes = [pd, pt, vp, vp, vp, vp, vp, vp, vp]
         L.hmfsr_merge_maps.restype = i32
+        L.hmfsr_merge_batch.argtypes = [i32, pd, pt, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                         ctypes.POINTER(vp), vp]
+        L.hmfsr_merge_batch.restype = i32
+        L.hmfsr_autotune.argtypes = [pd, pt, vp, vp, vp, vp, ctypes.POINTER(i32)]
+        L.hmfsr_autotune.restype = i32
         L.hmfsr_profile_begin.argtypes = []
         L.hmfsr_profile_begin.restype = i32
         L.hmfsr_profile_end.argtypes = [ctypes.POINTER(hmfsr_stage_times)]
@@ -111,6 +118,26 @@ def hmfsr_merge_maps(desc, tuning, frames: int, motion: int, omega: int, robust:
     _check(lib().hmfsr_merge_maps(ctypes.byref(desc), ctypes.byref(tuning), frames, motion,
                                   omega or None, robust or None, robust_min or None,
                                   s_tile or None, stream or None), "hmfsr_merge_maps")
+
+
+def hmfsr_merge_batch(descs, tunings, frames, motion, out, stream: int = 0) -> None:
+    """descs / tunings: sequences of hmfsr_desc / hmfsr_tuning; frames, motion,
+    out: sequences of device addresses."""
+    n = len(descs)
+    D = (hmfsr_desc * n)(*descs)
+    T = (hmfsr_tuning * n)(*tunings)
+    F = (ctypes.c_void_p * n)(*frames)
+    M = (ctypes.c_void_p * n)(*motion)
+    O = (ctypes.c_void_p * n)(*out)
+    _check(lib().hmfsr_merge_batch(n, D, T, F, M, O, stream or None), "hmfsr_merge_batch")
+
+
+def hmfsr_autotune(desc, tuning, frames: int, motion: int, out: int, stream: int = 0) -> int:
+    """Time every tile shape on this burst; returns the chosen shape's index."""
+    chosen = ctypes.c_int32(-1)
+    _check(lib().hmfsr_autotune(ctypes.byref(desc), ctypes.byref(tuning), frames, motion, out,
+                                stream or None, ctypes.byref(chosen)), "hmfsr_autotune")
+    return chosen.value
 
 
 def hmfsr_profile_begin() -> None:

@@ -1,59 +1,30 @@
-// C ABI entry points: validation, per-device workspace, dispatch.
+// C ABI entry points: validation, per-device workspace, single-burst dispatch,
+// inspection maps, profiling.
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
-#include <mutex>
-#include <string>
-#include <vector>
-
-#include "hmfsr_internal.h"
+#include "host.h"
 
 namespace hmfsr {
-namespace {
-
-constexpr int kMaxDevices = 64;
-
-struct DeviceState {
-  int checked = 0;       // 0 unknown, 1 gfx950, -1 unsupported
-  void* workspace = nullptr;
-  size_t workspace_bytes = 0;
-};
 
 std::mutex g_mutex;
 DeviceState g_dev[kMaxDevices];
-
-// Optional per-stage timing: an event pair around every kernel launch.
-struct Timing {
-  bool on = false;
-  struct Pair { int stage; hipEvent_t a, b; };
-  std::vector<Pair> pairs;
-  std::vector<hipEvent_t> pool;
-  hipEvent_t get() {
-    if (!pool.empty()) {
-      hipEvent_t e = pool.back();
-      pool.pop_back();
-      return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-  }
-};
 Timing g_timing;
 
-// Launch `fn` on `s`, bracketed by timing events when profiling is on.
-template <typename F>
-hipError_t timed(int stage, hipStream_t s, F fn) {
-  if (!g_timing.on) return fn();
-  hipEvent_t a = g_timing.get(), b = g_timing.get();
-  if (a) hipEventRecord(a, s);
-  const hipError_t err = fn();
-  if (b) hipEventRecord(b, s);
-  if (a && b) g_timing.pairs.push_back({stage, a, b});
-  return err;
+hipEvent_t Timing::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
 }
+
+namespace {
 
 bool finite(float v) { return isfinite(v) != 0; }
 
@@ -64,6 +35,10 @@ bool cfa_colours(int cfa, int out[4]) {
   for (int k = 0; k < 4; ++k) out[k] = table[cfa][k];
   return true;
 }
+
+double range_of(const hmfsr_desc* d) { return (double)d->white_level - (double)d->black_level; }
+
+}  // namespace
 
 hmfsr_status validate(const hmfsr_desc* d, const hmfsr_tuning* t) {
   if (!d || !t) return HMFSR_E_INVALID;
@@ -117,8 +92,6 @@ Geometry make_geometry(const hmfsr_desc* d) {
   return g;
 }
 
-double range_of(const hmfsr_desc* d) { return (double)d->white_level - (double)d->black_level; }
-
 OmegaConsts make_omega(const hmfsr_desc* d, const hmfsr_tuning* t) {
   OmegaConsts c;
   const double kd = t->k_detail;
@@ -158,18 +131,6 @@ MergeConsts make_merge(const hmfsr_desc* d, const hmfsr_tuning* t, const Geometr
   return m;
 }
 
-// Tile shape of the merge kernel: HMFSR_MERGE_VARIANT overrides the default.
-int merge_variant(const Geometry& g) {
-  (void)g;
-  const char* env = getenv("HMFSR_MERGE_VARIANT");
-  if (env) {
-    const int v = atoi(env);
-    if (v >= 0 && v < kNumMergeVariants) return v;
-  }
-  return 2;
-}
-
-// Current device, checked to be gfx950 (cached).
 hmfsr_status current_device(int* dev_out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return HMFSR_E_HIP;
@@ -179,15 +140,15 @@ hmfsr_status current_device(int* dev_out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return HMFSR_E_HIP;
     st.checked = strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+    st.cus = prop.multiProcessorCount;
   }
   if (st.checked < 0) return HMFSR_E_UNSUPPORTED;
   *dev_out = dev;
   return HMFSR_OK;
 }
 
-// Workspace of at least `bytes` on `dev`; caller holds g_mutex. Growing a
-// workspace frees the old one only after the stream that may still use it
-// has drained.
+// Growing a workspace frees the old one only after the stream that may still
+// use it has drained.
 hmfsr_status workspace(int dev, size_t bytes, hipStream_t stream, void** out) {
   DeviceState& st = g_dev[dev];
   if (st.workspace_bytes < bytes) {
@@ -208,7 +169,25 @@ hmfsr_status workspace(int dev, size_t bytes, hipStream_t stream, void** out) {
   return HMFSR_OK;
 }
 
-}  // namespace
+hmfsr_status run_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, const Geometry& g,
+                       const uint16_t* frames, const float* motion, float* out, const Work& w,
+                       int variant, hipStream_t s) {
+  const PriorConsts pc = make_prior(tuning);
+  const RobustConsts rc = make_robust(desc, tuning);
+  const MergeConsts mc = make_merge(desc, tuning, g);
+  if (timed(HMFSR_STAGE_PRIOR, s, [&] { return launch_prior(g, pc, motion, w.s_tile, s); }) != hipSuccess)
+    return HMFSR_E_HIP;
+  if (timed(HMFSR_STAGE_ROBUST, s, [&] {
+        return launch_robust(g, rc, frames, motion, w.s_tile, w.rmin, nullptr, s);
+      }) != hipSuccess)
+    return HMFSR_E_HIP;
+  if (timed(HMFSR_STAGE_MERGE, s, [&] {
+        return launch_merge(variant, g, mc, frames, motion, w.rmin, out, s);
+      }) != hipSuccess)
+    return HMFSR_E_HIP;
+  return HMFSR_OK;
+}
+
 }  // namespace hmfsr
 
 using namespace hmfsr;
@@ -228,22 +207,7 @@ hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, con
   void* ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
   if ((st = workspace(dev, work_bytes(g), s, &ws)) != HMFSR_OK) return st;
-  const Work w = work_carve(ws, g);
-  const PriorConsts pc = make_prior(tuning);
-  const RobustConsts rc = make_robust(desc, tuning);
-  const MergeConsts mc = make_merge(desc, tuning, g);
-  const int variant = merge_variant(g);
-  if (timed(HMFSR_STAGE_PRIOR, s, [&] { return launch_prior(g, pc, motion, w.s_tile, s); }) != hipSuccess)
-    return HMFSR_E_HIP;
-  if (timed(HMFSR_STAGE_ROBUST, s, [&] {
-        return launch_robust(g, rc, frames, motion, w.s_tile, w.rmin, nullptr, s);
-      }) != hipSuccess)
-    return HMFSR_E_HIP;
-  if (timed(HMFSR_STAGE_MERGE, s, [&] {
-        return launch_merge(variant, g, mc, frames, motion, w.rmin, out, s);
-      }) != hipSuccess)
-    return HMFSR_E_HIP;
-  return HMFSR_OK;
+  return run_merge(desc, tuning, g, frames, motion, out, work_carve(ws, g), merge_variant(g), s);
 }
 
 hmfsr_status hmfsr_merge_maps(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
@@ -330,10 +294,18 @@ void hmfsr_release(void) {
   int cur = 0;
   const bool have_cur = hipGetDevice(&cur) == hipSuccess;
   for (int d = 0; d < kMaxDevices; ++d) {
-    if (!g_dev[d].workspace) continue;
-    if (hipSetDevice(d) == hipSuccess) hipFree(g_dev[d].workspace);
-    g_dev[d].workspace = nullptr;
-    g_dev[d].workspace_bytes = 0;
+    DeviceState& st = g_dev[d];
+    if (!st.workspace && !st.batch_ws && !st.plan.exec && !st.capture_stream) continue;
+    if (hipSetDevice(d) != hipSuccess) continue;
+    if (st.plan.exec) hipGraphExecDestroy(st.plan.exec);
+    if (st.plan.graph) hipGraphDestroy(st.plan.graph);
+    st.plan = BatchPlan();
+    if (st.workspace) hipFree(st.workspace);
+    if (st.batch_ws) hipFree(st.batch_ws);
+    if (st.capture_stream) hipStreamDestroy(st.capture_stream);
+    st.workspace = st.batch_ws = nullptr;
+    st.workspace_bytes = st.batch_ws_bytes = 0;
+    st.capture_stream = nullptr;
   }
   if (have_cur) hipSetDevice(cur);
 }

@@ -1,0 +1,345 @@
+// Batched merge of many bursts of uneven frame count, size and scale in one
+// captured graph of persistent kernels, and the tile-shape autotuner.
+//
+// hmfsr_merge_batch lays out one workspace for every burst (rejection
+// strengths, R_hat), per-burst argument blocks and cost-ordered work lists,
+// then records into a hipGraph: a counter reset, the motion prior of every
+// (burst, frame, tile), one persistent robustness launch over all (burst,
+// tile) items and one persistent merge launch per tile shape. The graph is
+// kept and replayed while the bursts' shapes and buffers stay the same;
+// changed tuning values are uploaded before the replay.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+
+#include "host.h"
+
+namespace hmfsr {
+namespace {
+
+constexpr int kDefaultVariant = 2;  // 64x16 tile, 256 threads
+
+// ---- autotuner --------------------------------------------------------------
+// The best tile shape depends mostly on the output scale (footprint per output
+// pixel) and on the frame count (how long accumulators live per workgroup).
+struct TuneTable {
+  int v[4][4];
+  bool tuned[4][4];
+  bool loaded = false;
+};
+TuneTable g_tune;
+
+int scale_class(double s) { return s <= 1.0 ? 0 : (s <= 1.5 ? 1 : (s <= 2.0 ? 2 : 3)); }
+int frame_bucket(int n) { return n <= 4 ? 0 : (n <= 8 ? 1 : (n <= 15 ? 2 : 3)); }
+
+void tune_load() {
+  if (g_tune.loaded) return;
+  g_tune.loaded = true;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      g_tune.v[a][b] = kDefaultVariant;
+      g_tune.tuned[a][b] = false;
+    }
+  const char* path = getenv("HMFSR_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  int a, b, v;
+  while (fscanf(f, "%d %d %d", &a, &b, &v) == 3) {
+    if (a >= 0 && a < 4 && b >= 0 && b < 4 && v >= 0 && v < kNumMergeVariants) {
+      g_tune.v[a][b] = v;
+      g_tune.tuned[a][b] = true;
+    }
+  }
+  fclose(f);
+}
+
+void tune_save() {
+  const char* path = getenv("HMFSR_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "w");
+  if (!f) return;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      if (g_tune.tuned[a][b]) fprintf(f, "%d %d %d\n", a, b, g_tune.v[a][b]);
+  fclose(f);
+}
+
+// ---- batch layout -------------------------------------------------------------
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t counters = 0, args = 0, first = 0, ritems = 0, mitems = 0, work = 0, total = 0;
+  std::vector<size_t> burst_work;  // offset of each burst's Work inside the workspace
+};
+
+}  // namespace
+
+int merge_variant(const Geometry& g) {
+  const char* env = getenv("HMFSR_MERGE_VARIANT");
+  if (env) {
+    const int v = atoi(env);
+    if (v >= 0 && v < kNumMergeVariants) return v;
+  }
+  tune_load();
+  return g_tune.v[scale_class(g.scale)][frame_bucket(g.n)];
+}
+
+}  // namespace hmfsr
+
+using namespace hmfsr;
+
+extern "C" {
+
+hmfsr_status hmfsr_autotune(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
+                            const uint16_t* frames, const float* motion, float* out, void* stream,
+                            int32_t* chosen) {
+  hmfsr_status st = validate(desc, tuning);
+  if (st != HMFSR_OK) return st;
+  if (!frames || !motion || !out) return HMFSR_E_INVALID;
+  if (((uintptr_t)frames & 3) || ((uintptr_t)motion & 3) || ((uintptr_t)out & 3)) return HMFSR_E_INVALID;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  int dev = 0;
+  if ((st = current_device(&dev)) != HMFSR_OK) return st;
+  const Geometry g = make_geometry(desc);
+  void* ws = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = workspace(dev, work_bytes(g), s, &ws)) != HMFSR_OK) return st;
+  const Work w = work_carve(ws, g);
+  // robustness once, then every tile shape: one warm-up and three timed launches
+  if ((st = run_merge(desc, tuning, g, frames, motion, out, w, kDefaultVariant, s)) != HMFSR_OK) return st;
+  const MergeConsts mc = make_merge(desc, tuning, g);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return HMFSR_E_HIP;
+  int best = kDefaultVariant;
+  float best_ms = 1e30f;
+  for (int v = 0; v < kNumMergeVariants && st == HMFSR_OK; ++v) {
+    if (launch_merge(v, g, mc, frames, motion, w.rmin, out, s) != hipSuccess) st = HMFSR_E_HIP;
+    if (hipEventRecord(a, s) != hipSuccess) st = HMFSR_E_HIP;
+    for (int r = 0; r < 3 && st == HMFSR_OK; ++r)
+      if (launch_merge(v, g, mc, frames, motion, w.rmin, out, s) != hipSuccess) st = HMFSR_E_HIP;
+    float ms = 0.f;
+    if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&ms, a, b) != hipSuccess)
+      st = HMFSR_E_HIP;
+    if (st == HMFSR_OK && ms < best_ms) {
+      best_ms = ms;
+      best = v;
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  if (st != HMFSR_OK) return st;
+  // leave `out` holding the merge of the chosen shape
+  if (launch_merge(best, g, mc, frames, motion, w.rmin, out, s) != hipSuccess) return HMFSR_E_HIP;
+  tune_load();
+  g_tune.v[scale_class(g.scale)][frame_bucket(g.n)] = best;
+  g_tune.tuned[scale_class(g.scale)][frame_bucket(g.n)] = true;
+  tune_save();
+  if (chosen) *chosen = best;
+  return HMFSR_OK;
+}
+
+hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const hmfsr_tuning* tunings,
+                               const uint16_t* const* frames, const float* const* motion,
+                               float* const* out, void* stream) {
+  if (n_bursts < 1 || n_bursts > 65536 || !descs || !tunings || !frames || !motion || !out)
+    return HMFSR_E_INVALID;
+  hmfsr_status st;
+  for (int i = 0; i < n_bursts; ++i) {
+    if ((st = validate(&descs[i], &tunings[i])) != HMFSR_OK) return st;
+    if (!frames[i] || !motion[i] || !out[i]) return HMFSR_E_INVALID;
+    if (((uintptr_t)frames[i] & 3) || ((uintptr_t)motion[i] & 3) || ((uintptr_t)out[i] & 3))
+      return HMFSR_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lock(g_mutex);
+  int dev = 0;
+  if ((st = current_device(&dev)) != HMFSR_OK) return st;
+  DeviceState& ds = g_dev[dev];
+  hipStream_t s = (hipStream_t)stream;
+
+  // per-burst geometry, tile shape and work sizes
+  std::vector<Geometry> geo(n_bursts);
+  std::vector<int> var(n_bursts), mtx(n_bursts), mtiles(n_bursts), rtiles(n_bursts);
+  std::vector<double> cost(n_bursts);
+  Layout L;
+  size_t n_prior = 0, n_ritems = 0, n_mitems = 0;
+  for (int i = 0; i < n_bursts; ++i) {
+    geo[i] = make_geometry(&descs[i]);
+    var[i] = merge_variant(geo[i]);
+    const int rows = merge_tile_rows(var[i]);
+    mtx[i] = (geo[i].OW + 63) / 64;
+    mtiles[i] = mtx[i] * ((geo[i].OH + rows - 1) / rows);
+    rtiles[i] = geo[i].n > 1 ? robust_tiles_x(geo[i]) * robust_tiles_y(geo[i]) : 0;
+    cost[i] = (double)geo[i].n * geo[i].OH * geo[i].OW;
+    n_prior += (size_t)geo[i].n * geo[i].TY * geo[i].TX;
+    n_ritems += rtiles[i];
+    n_mitems += mtiles[i];
+  }
+  if (n_prior > 0x7fffffff || n_ritems > 0x7fffffff || n_mitems > 0x7fffffff) return HMFSR_E_INVALID;
+  size_t off = 0;
+  L.counters = off; off += 256;
+  L.args = off; off += align256(sizeof(BurstArgs) * n_bursts);
+  L.first = off; off += align256(sizeof(int) * n_bursts);
+  L.ritems = off; off += align256(sizeof(WorkItem) * n_ritems);
+  L.mitems = off; off += align256(sizeof(WorkItem) * n_mitems);
+  L.burst_work.resize(n_bursts);
+  for (int i = 0; i < n_bursts; ++i) {
+    L.burst_work[i] = off;
+    off += align256(work_bytes(geo[i]));
+  }
+  L.total = off;
+
+  // workspace (grown only; the old graph points into the old one)
+  if (ds.batch_ws_bytes < L.total) {
+    if (hipStreamSynchronize(s) != hipSuccess) return HMFSR_E_HIP;
+    if (ds.plan.exec) hipGraphExecDestroy(ds.plan.exec);
+    if (ds.plan.graph) hipGraphDestroy(ds.plan.graph);
+    ds.plan = BatchPlan();
+    if (ds.batch_ws) hipFree(ds.batch_ws);
+    ds.batch_ws = nullptr;
+    ds.batch_ws_bytes = 0;
+    if (hipMalloc(&ds.batch_ws, L.total) != hipSuccess) {
+      (void)hipGetLastError();
+      return HMFSR_E_NOMEM;
+    }
+    ds.batch_ws_bytes = L.total;
+  }
+  char* base = (char*)ds.batch_ws;
+
+  // argument blocks
+  std::vector<BurstArgs> args(n_bursts);
+  for (int i = 0; i < n_bursts; ++i) {
+    BurstArgs& a = args[i];
+    const Work w = work_carve(base + L.burst_work[i], geo[i]);
+    a.frames = frames[i];
+    a.motion = motion[i];
+    a.out = out[i];
+    a.s_tile = w.s_tile;
+    a.rmin = w.rmin;
+    a.g = geo[i];
+    a.mc = make_merge(&descs[i], &tunings[i], geo[i]);
+    a.rc = make_robust(&descs[i], &tunings[i]);
+    a.pc = make_prior(&tunings[i]);
+    a.merge_tiles_x = mtx[i];
+    a.robust_tiles_x = geo[i].n > 1 ? robust_tiles_x(geo[i]) : 1;
+  }
+
+  // same shapes and buffers as the captured graph: refresh arguments, replay
+  // (descriptors and tunings are plain int32 / float structs: memcmp is exact)
+  std::vector<const void*> ptrs;
+  for (int i = 0; i < n_bursts; ++i) {
+    ptrs.push_back(frames[i]);
+    ptrs.push_back(motion[i]);
+    ptrs.push_back(out[i]);
+  }
+  BatchPlan& P = ds.plan;
+  const bool same = P.exec && P.ws == ds.batch_ws && P.variants == var && P.ptrs == ptrs &&
+                    P.descs.size() == (size_t)n_bursts &&
+                    memcmp(P.descs.data(), descs, sizeof(hmfsr_desc) * n_bursts) == 0;
+  if (same) {
+    if (memcmp(P.tunings.data(), tunings, sizeof(hmfsr_tuning) * n_bursts) != 0) {
+      // the previous replay may still read the old arguments
+      if (hipStreamSynchronize(s) != hipSuccess) return HMFSR_E_HIP;
+      if (hipMemcpy(base + L.args, args.data(), sizeof(BurstArgs) * n_bursts, hipMemcpyHostToDevice) !=
+          hipSuccess)
+        return HMFSR_E_HIP;
+      P.tunings.assign(tunings, tunings + n_bursts);
+    }
+    return timed(HMFSR_STAGE_BATCH, s, [&] { return hipGraphLaunch(P.exec, s); }) == hipSuccess
+               ? HMFSR_OK
+               : HMFSR_E_HIP;
+  }
+
+  // work lists: most expensive bursts first, tiles in order within a burst
+  std::vector<int> order(n_bursts);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::vector<WorkItem> ritems;
+  ritems.reserve(n_ritems);
+  for (int i : order)
+    for (int t = 0; t < rtiles[i]; ++t) ritems.push_back({i, t});
+  // one merge list per tile shape, stored back to back
+  std::vector<WorkItem> mitems;
+  mitems.reserve(n_mitems);
+  std::vector<int> group_start(kNumMergeVariants + 1, 0);
+  for (int v = 0; v < kNumMergeVariants; ++v) {
+    group_start[v] = (int)mitems.size();
+    for (int i : order)
+      if (var[i] == v)
+        for (int t = 0; t < mtiles[i]; ++t) mitems.push_back({i, t});
+  }
+  group_start[kNumMergeVariants] = (int)mitems.size();
+  std::vector<int> first(n_bursts);
+  {
+    size_t acc = 0;
+    for (int i = 0; i < n_bursts; ++i) {
+      first[i] = (int)acc;
+      acc += (size_t)geo[i].n * geo[i].TY * geo[i].TX;
+    }
+  }
+
+  // rebuild: wait for any replay that reads the lists, upload, capture
+  if (hipStreamSynchronize(s) != hipSuccess) return HMFSR_E_HIP;
+  if (P.exec) hipGraphExecDestroy(P.exec);
+  if (P.graph) hipGraphDestroy(P.graph);
+  P = BatchPlan();
+  if (hipMemcpy(base + L.args, args.data(), sizeof(BurstArgs) * n_bursts, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(base + L.first, first.data(), sizeof(int) * n_bursts, hipMemcpyHostToDevice) != hipSuccess ||
+      (n_ritems && hipMemcpy(base + L.ritems, ritems.data(), sizeof(WorkItem) * n_ritems,
+                             hipMemcpyHostToDevice) != hipSuccess) ||
+      hipMemcpy(base + L.mitems, mitems.data(), sizeof(WorkItem) * n_mitems, hipMemcpyHostToDevice) !=
+          hipSuccess)
+    return HMFSR_E_HIP;
+  if (!ds.capture_stream && hipStreamCreateWithFlags(&ds.capture_stream, hipStreamNonBlocking) != hipSuccess)
+    return HMFSR_E_HIP;
+
+  const BurstArgs* d_args = (const BurstArgs*)(base + L.args);
+  const int* d_first = (const int*)(base + L.first);
+  const WorkItem* d_ritems = (const WorkItem*)(base + L.ritems);
+  const WorkItem* d_mitems = (const WorkItem*)(base + L.mitems);
+  int* d_counters = (int*)(base + L.counters);  // [0] robustness, [1 + v] merge shape v
+  const int cus = ds.cus > 0 ? ds.cus : 256;
+  hipStream_t cs = ds.capture_stream;
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return HMFSR_E_HIP;
+  hipError_t err = launch_fill_i32(d_counters, 0, 1 + kNumMergeVariants, cs);
+  if (err == hipSuccess) err = launch_prior_batch(d_args, d_first, n_bursts, (int)n_prior, cs);
+  if (err == hipSuccess && n_ritems) {
+    const int groups = (int)std::min<size_t>(n_ritems, (size_t)cus * robust_batch_blocks_per_cu());
+    err = launch_robust_batch(d_args, d_ritems, (int)n_ritems, d_counters, groups, cs);
+  }
+  for (int v = 0; v < kNumMergeVariants && err == hipSuccess; ++v) {
+    const int cnt = group_start[v + 1] - group_start[v];
+    if (cnt == 0) continue;
+    const int groups = (int)std::min<size_t>(cnt, (size_t)cus * merge_batch_blocks_per_cu(v));
+    err = launch_merge_batch(v, d_args, d_mitems + group_start[v], cnt, d_counters + 1 + v, groups, cs);
+  }
+  const hipError_t end = hipStreamEndCapture(cs, &graph);
+  if (err != hipSuccess || end != hipSuccess || !graph) {
+    if (graph) hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return HMFSR_E_HIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(graph);
+    return HMFSR_E_HIP;
+  }
+  P.graph = graph;
+  P.exec = exec;
+  P.ws = ds.batch_ws;
+  P.variants = var;
+  P.ptrs = ptrs;
+  P.descs.assign(descs, descs + n_bursts);
+  P.tunings.assign(tunings, tunings + n_bursts);
+  return timed(HMFSR_STAGE_BATCH, s, [&] { return hipGraphLaunch(P.exec, s); }) == hipSuccess
+             ? HMFSR_OK
+             : HMFSR_E_HIP;
+}
+
+}  // extern "C"

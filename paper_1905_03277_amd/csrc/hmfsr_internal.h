@@ -43,6 +43,27 @@ struct MergeConsts {
   int col4;  // colour of parity k in bits 2k..2k+1
 };
 
+// One burst of a batch, as the persistent kernels see it.
+struct BurstArgs {
+  const uint16_t* frames;
+  const float* motion;
+  float* out;
+  float* s_tile;  // workspace [n][TY][TX]
+  float* rmin;    // workspace [n][h][w]
+  Geometry g;
+  MergeConsts mc;
+  RobustConsts rc;
+  PriorConsts pc;
+  int merge_tiles_x;   // output tiles per row for the batch's tile shape
+  int robust_tiles_x;  // robustness tiles per row
+};
+
+// A (burst, tile) unit of work of a persistent launch.
+struct WorkItem {
+  int burst;
+  int tile;  // row-major tile index within the burst
+};
+
 // Workspace of the merge: per-(frame, tile) rejection strength and R_hat.
 struct Work {
   float* s_tile;  // [n][TY][TX]
@@ -65,6 +86,18 @@ extern const MergeVariant kMergeVariants[];
 extern const int kNumMergeVariants;
 hipError_t launch_merge(int variant, const Geometry& g, const MergeConsts& mc, const uint16_t* frames,
                         const float* motion, const float* rmin, float* out, hipStream_t stream);
+hipError_t launch_merge_batch(int variant, const BurstArgs* bursts, const WorkItem* items, int n_items,
+                              int* counter, int n_groups, hipStream_t stream);
+hipError_t launch_robust_batch(const BurstArgs* bursts, const WorkItem* items, int n_items,
+                               int* counter, int n_groups, hipStream_t stream);
+hipError_t launch_prior_batch(const BurstArgs* bursts, const int* first, int n_bursts, int total,
+                              hipStream_t stream);
+int merge_tile_rows(int variant);
+int merge_batch_blocks_per_cu(int variant);
+int robust_batch_blocks_per_cu();
+int robust_tiles_x(const Geometry& g);
+int robust_tiles_y(const Geometry& g);
+hipError_t launch_fill_i32(int* p, int v, size_t n, hipStream_t stream);
 hipError_t launch_fill(float* p, float v, size_t n, hipStream_t stream);
 hipError_t launch_omega_map(const Geometry& g, const OmegaConsts& oc, const uint16_t* frames,
                             double* omega, hipStream_t stream);

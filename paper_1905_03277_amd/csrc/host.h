@@ -1,0 +1,80 @@
+// Host-side state and helpers shared by the C ABI translation units.
+#pragma once
+
+#include <mutex>
+#include <vector>
+
+#include "hmfsr_internal.h"
+
+namespace hmfsr {
+
+constexpr int kMaxDevices = 64;
+
+// A captured batch graph and the signature it was built for.
+struct BatchPlan {
+  std::vector<hmfsr_desc> descs;
+  std::vector<const void*> ptrs;  // frames, motion, out of every burst
+  std::vector<int> variants;
+  void* ws = nullptr;             // batch workspace the graph's arguments point into
+  std::vector<hmfsr_tuning> tunings;  // the tunings of the uploaded argument blocks
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+struct DeviceState {
+  int checked = 0;  // 0 unknown, 1 gfx950, -1 unsupported
+  int cus = 0;      // compute units
+  void* workspace = nullptr;  // single-burst workspace
+  size_t workspace_bytes = 0;
+  void* batch_ws = nullptr;   // batch workspace
+  size_t batch_ws_bytes = 0;
+  hipStream_t capture_stream = nullptr;
+  BatchPlan plan;
+};
+
+extern std::mutex g_mutex;
+extern DeviceState g_dev[kMaxDevices];
+
+// Optional per-stage timing: an event pair around every kernel launch.
+struct Timing {
+  bool on = false;
+  struct Pair {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Pair> pairs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get();
+};
+extern Timing g_timing;
+
+// Launch `fn` on `s`, bracketed by timing events when profiling is on.
+template <typename F>
+hipError_t timed(int stage, hipStream_t s, F fn) {
+  if (!g_timing.on) return fn();
+  hipEvent_t a = g_timing.get(), b = g_timing.get();
+  if (a) hipEventRecord(a, s);
+  const hipError_t err = fn();
+  if (b) hipEventRecord(b, s);
+  if (a && b) g_timing.pairs.push_back({stage, a, b});
+  return err;
+}
+
+hmfsr_status validate(const hmfsr_desc* d, const hmfsr_tuning* t);
+Geometry make_geometry(const hmfsr_desc* d);
+PriorConsts make_prior(const hmfsr_tuning* t);
+RobustConsts make_robust(const hmfsr_desc* d, const hmfsr_tuning* t);
+MergeConsts make_merge(const hmfsr_desc* d, const hmfsr_tuning* t, const Geometry& g);
+OmegaConsts make_omega(const hmfsr_desc* d, const hmfsr_tuning* t);
+hmfsr_status current_device(int* dev_out);  // caller holds g_mutex
+hmfsr_status workspace(int dev, size_t bytes, hipStream_t stream, void** out);  // caller holds g_mutex
+
+// Merge tile shape for a burst: HMFSR_MERGE_VARIANT, else the autotuned
+// choice for the burst's (scale, frame count) class, else the default.
+int merge_variant(const Geometry& g);
+// The three kernels of one merge on `s` (workspace from `workspace`).
+hmfsr_status run_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, const Geometry& g,
+                       const uint16_t* frames, const float* motion, float* out, const Work& w,
+                       int variant, hipStream_t s);
+
+}  // namespace hmfsr

@@ -10,12 +10,9 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 
 // eq. (7)-(8): spread of the displacements over the 3x3 tile neighbourhood
 // (tiles outside the grid skipped) -> rejection strength s1 or s2.
-__global__ void k_prior(const float* __restrict__ motion, Geometry g, PriorConsts pc,
-                        float* __restrict__ s_tile) {
-  const int tx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int ty = blockIdx.y * blockDim.y + threadIdx.y;
-  const int n = blockIdx.z;
-  if (ty >= g.TY || tx >= g.TX) return;
+__device__ __forceinline__ void prior_one(const float* __restrict__ motion, const Geometry& g,
+                                          const PriorConsts& pc, float* __restrict__ s_tile, int n,
+                                          int ty, int tx) {
   const size_t idx = ((size_t)n * g.TY + ty) * g.TX + tx;
   if (n == g.ref) {
     s_tile[idx] = 0.0f;
@@ -38,6 +35,31 @@ __global__ void k_prior(const float* __restrict__ motion, Geometry g, PriorConst
   // M > M_th evaluated as M^2 > M_th^2, rounded operation by operation.
   const double m2 = __dadd_rn(__dmul_rn(mx, mx), __dmul_rn(my, my));
   s_tile[idx] = m2 > __dmul_rn(pc.m_th, pc.m_th) ? pc.s1 : pc.s2;
+}
+
+__global__ void k_prior(const float* __restrict__ motion, Geometry g, PriorConsts pc,
+                        float* __restrict__ s_tile) {
+  const int tx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ty = blockIdx.y * blockDim.y + threadIdx.y;
+  if (ty >= g.TY || tx >= g.TX) return;
+  prior_one(motion, g, pc, s_tile, blockIdx.z, ty, tx);
+}
+
+// Every (burst, frame, tile) of a batch; first[b] = first flat index of burst b.
+__global__ void k_prior_batch(const BurstArgs* __restrict__ bursts, const int* __restrict__ first,
+                              int n_bursts, int total) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  int lo = 0, hi = n_bursts - 1;  // last burst with first[b] <= i
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  const BurstArgs& b = bursts[lo];
+  const int k = i - first[lo];
+  const int per = b.g.TY * b.g.TX;
+  const int n = k / per, t = k - n * per;
+  prior_one(b.motion, b.g, b.pc, b.s_tile, n, t / b.g.TX, t % b.g.TX);
 }
 
 // Omega per half-res pixel of every frame (inspection output).
@@ -69,7 +91,18 @@ __global__ void k_fill(float* __restrict__ p, float v, size_t n) {
   if (i < n) p[i] = v;
 }
 
+__global__ void k_fill_i32(int* __restrict__ p, int v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 }  // namespace
+
+hipError_t launch_fill_i32(int* p, int v, size_t n, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, v, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill(float* p, float v, size_t n, hipStream_t stream) {
   if (n == 0) return hipSuccess;
@@ -94,6 +127,14 @@ hipError_t launch_prior(const Geometry& g, const PriorConsts& pc, const float* m
   const dim3 blk(16, 16);
   const dim3 grid((g.TX + 15) / 16, (g.TY + 15) / 16, g.n);
   hipLaunchKernelGGL(k_prior, grid, blk, 0, stream, motion, g, pc, s_tile);
+  return hipGetLastError();
+}
+
+hipError_t launch_prior_batch(const BurstArgs* bursts, const int* first, int n_bursts, int total,
+                              hipStream_t stream) {
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prior_batch, dim3((total + 255) / 256), dim3(256), 0, stream, bursts, first,
+                     n_bursts, total);
   return hipGetLastError();
 }
 

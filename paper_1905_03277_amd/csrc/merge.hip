@@ -58,30 +58,55 @@ struct Bounds {
   int jc0, jc1, ic0, ic1, hj0, hj1, hi0, hi1;
 };
 
+template <int MH>
+struct MergeSmem {
+  using CP = Caps<MH>;
+  double sX[MW], sY[MH];
+  int sTyRow[MH], sTxCol[MW];
+  int sRlo[CP::TY], sRhi[CP::TY], sClo[CP::TX], sChi[CP::TX];
+  RowInfo sRow[MH];
+  float2 sV[CP::VT];
+  Bounds sTB[CP::VT];
+  float sRaw[CP::RAW];
+  float sLum[CP::LUMA];
+  double sOm[3][CP::OM];
+  float sRh[CP::RH];
+  int sRed[8];
+  int sRh0[4];
+  int sItem;
+};
+
+// One 64 x MH output tile (tile_x, tile_y) of one burst.
 template <int MH, int THREADS>
-__global__ __launch_bounds__(THREADS, (MH / (THREADS / 64) <= 4) ? 4 : 2) void k_merge(const uint16_t* __restrict__ frames,
-                                                   const float* __restrict__ motion,
-                                                   const float* __restrict__ rmin, Geometry g,
-                                                   MergeConsts mc, float* __restrict__ out) {
+__device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
+                                           const float* __restrict__ motion,
+                                           const float* __restrict__ rmin, const Geometry& g,
+                                           const MergeConsts& mc, float* __restrict__ out, int tile_x,
+                                           int tile_y, MergeSmem<MH>& sm) {
   constexpr int WAVES = THREADS / 64;
   constexpr int PX = MH / WAVES;
   static_assert(PX * WAVES == MH, "tile rows must split evenly over the waves");
   using CP = Caps<MH>;
-  __shared__ double sX[MW], sY[MH];
-  __shared__ int sTyRow[MH], sTxCol[MW];
-  __shared__ int sRlo[CP::TY], sRhi[CP::TY], sClo[CP::TX], sChi[CP::TX];
-  __shared__ RowInfo sRow[MH];
-  __shared__ float2 sV[CP::VT];
-  __shared__ Bounds sTB[CP::VT];
-  __shared__ float sRaw[CP::RAW];
-  __shared__ float sLum[CP::LUMA];
-  __shared__ double sOm[3][CP::OM];
-  __shared__ float sRh[CP::RH];
-  __shared__ int sRed[8];
-  __shared__ int sRh0[4];
+  double* sX = sm.sX;
+  double* sY = sm.sY;
+  int* sTyRow = sm.sTyRow;
+  int* sTxCol = sm.sTxCol;
+  int* sRlo = sm.sRlo;
+  int* sRhi = sm.sRhi;
+  int* sClo = sm.sClo;
+  int* sChi = sm.sChi;
+  RowInfo* sRow = sm.sRow;
+  float2* sV = sm.sV;
+  Bounds* sTB = sm.sTB;
+  float* sRaw = sm.sRaw;
+  float* sLum = sm.sLum;
+  double(*sOm)[CP::OM] = sm.sOm;
+  float* sRh = sm.sRh;
+  int* sRed = sm.sRed;
+  int* sRh0 = sm.sRh0;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int C0 = blockIdx.x * MW, R0 = blockIdx.y * MH;
+  const int C0 = tile_x * MW, R0 = tile_y * MH;
   const int ncol = min(MW, g.OW - C0), nrow = min(MH, g.OH - R0);
 
   // ---- per-tile geometry ------------------------------------------------
@@ -432,11 +457,48 @@ __global__ __launch_bounds__(THREADS, (MH / (THREADS / 64) <= 4) ? 4 : 2) void k
 }
 
 template <int MH, int THREADS>
+__global__ __launch_bounds__(THREADS, (MH / (THREADS / 64) <= 4) ? 4 : 2) void k_merge(
+    const uint16_t* __restrict__ frames, const float* __restrict__ motion,
+    const float* __restrict__ rmin, Geometry g, MergeConsts mc, float* __restrict__ out) {
+  __shared__ MergeSmem<MH> sm;
+  merge_tile<MH, THREADS>(frames, motion, rmin, g, mc, out, blockIdx.x, blockIdx.y, sm);
+}
+
+// Persistent form: workgroups pull (burst, tile) items from a global counter
+// until the list is exhausted; every workgroup leaves the loop once the
+// counter passes the item count.
+template <int MH, int THREADS>
+__global__ __launch_bounds__(THREADS, (MH / (THREADS / 64) <= 4) ? 4 : 2) void k_merge_batch(
+    const BurstArgs* __restrict__ bursts, const WorkItem* __restrict__ items, int n_items,
+    int* __restrict__ counter) {
+  __shared__ MergeSmem<MH> sm;
+  while (true) {
+    __syncthreads();
+    if (threadIdx.x == 0) sm.sItem = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = sm.sItem;
+    if (it >= n_items) break;
+    const WorkItem w = items[it];
+    const BurstArgs& b = bursts[w.burst];
+    const int tx = w.tile % b.merge_tiles_x, ty = w.tile / b.merge_tiles_x;
+    merge_tile<MH, THREADS>(b.frames, b.motion, b.rmin, b.g, b.mc, b.out, tx, ty, sm);
+  }
+}
+
+template <int MH, int THREADS>
 hipError_t launch_variant(const Geometry& g, const MergeConsts& mc, const uint16_t* frames,
                           const float* motion, const float* rmin, float* out, hipStream_t stream) {
   const dim3 grid((g.OW + MW - 1) / MW, (g.OH + MH - 1) / MH);
   hipLaunchKernelGGL((k_merge<MH, THREADS>), grid, dim3(THREADS), 0, stream, frames, motion, rmin, g,
                      mc, out);
+  return hipGetLastError();
+}
+
+template <int MH, int THREADS>
+hipError_t launch_batch_variant(const BurstArgs* bursts, const WorkItem* items, int n_items,
+                                int* counter, int n_groups, hipStream_t stream) {
+  hipLaunchKernelGGL((k_merge_batch<MH, THREADS>), dim3(n_groups), dim3(THREADS), 0, stream, bursts,
+                     items, n_items, counter);
   return hipGetLastError();
 }
 
@@ -454,6 +516,37 @@ hipError_t launch_merge(int variant, const Geometry& g, const MergeConsts& mc, c
     case 2: return launch_variant<16, 256>(g, mc, frames, motion, rmin, out, stream);
     case 3: return launch_variant<16, 128>(g, mc, frames, motion, rmin, out, stream);
     default: return launch_variant<32, 256>(g, mc, frames, motion, rmin, out, stream);
+  }
+}
+
+hipError_t launch_merge_batch(int variant, const BurstArgs* bursts, const WorkItem* items, int n_items,
+                              int* counter, int n_groups, hipStream_t stream) {
+  switch (variant) {
+    case 1: return launch_batch_variant<32, 512>(bursts, items, n_items, counter, n_groups, stream);
+    case 2: return launch_batch_variant<16, 256>(bursts, items, n_items, counter, n_groups, stream);
+    case 3: return launch_batch_variant<16, 128>(bursts, items, n_items, counter, n_groups, stream);
+    default: return launch_batch_variant<32, 256>(bursts, items, n_items, counter, n_groups, stream);
+  }
+}
+
+int merge_tile_rows(int variant) { return kMergeVariants[variant].rows; }
+
+namespace {
+template <int MH, int THREADS>
+int blocks_per_cu() {
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_merge_batch<MH, THREADS>, THREADS, 0) != hipSuccess)
+    return 1;
+  return b > 0 ? b : 1;
+}
+}  // namespace
+
+int merge_batch_blocks_per_cu(int variant) {
+  switch (variant) {
+    case 1: return blocks_per_cu<32, 512>();
+    case 2: return blocks_per_cu<16, 256>();
+    case 3: return blocks_per_cu<16, 128>();
+    default: return blocks_per_cu<32, 256>();
   }
 }
 

@@ -41,26 +41,48 @@ struct Bounds4 {
   int x0, x1, y0, y1;  // range of the bilinear base corner floor(u + v/2)
 };
 
-__global__ __launch_bounds__(THREADS) void k_robust(const uint16_t* __restrict__ frames,
-                                                    const float* __restrict__ motion,
-                                                    const float* __restrict__ s_tile, Geometry g,
-                                                    RobustConsts rc, float* __restrict__ rmin,
-                                                    float* __restrict__ robust) {
-  __shared__ float sMuRef[3][RR_N];
-  __shared__ float sInvDen[RR_N];
-  __shared__ float sGuide[3][GU_CAP];  // guide, then the box means
-  __shared__ float sHs[3][GU_CAP];     // horizontal 3-sums
-  __shared__ float sR[RR_N];
-  __shared__ float sTmp[RR_H * RB_W];
-  __shared__ int sTyR[RR_H], sTxR[RR_W];        // alignment tile of each region row / column
-  __shared__ int sRlo[TT_Y], sRhi[TT_Y], sClo[TT_X], sChi[TT_X];
-  __shared__ float2 sV[TT_X * TT_Y];
-  __shared__ float sS[TT_X * TT_Y];
-  __shared__ Bounds4 sTB[TT_X * TT_Y];
-  __shared__ int sRed[4];
+struct RobustSmem {
+  float sMuRef[3][RR_N];
+  float sInvDen[RR_N];
+  float sGuide[3][GU_CAP];  // guide, then the box means
+  float sHs[3][GU_CAP];     // horizontal 3-sums
+  float sR[RR_N];
+  float sTmp[RR_H * RB_W];
+  int sTyR[RR_H], sTxR[RR_W];  // alignment tile of each region row / column
+  int sRlo[TT_Y], sRhi[TT_Y], sClo[TT_X], sChi[TT_X];
+  float2 sV[TT_X * TT_Y];
+  float sS[TT_X * TT_Y];
+  Bounds4 sTB[TT_X * TT_Y];
+  int sRed[4];
+  int sItem;
+};
+
+// R_hat of one 32x16 half-res tile (tile_x, tile_y) of one burst, every aligned frame.
+__device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
+                                            const float* __restrict__ motion,
+                                            const float* __restrict__ s_tile, const Geometry& g,
+                                            const RobustConsts& rc, float* __restrict__ rmin,
+                                            float* __restrict__ robust, int tile_x, int tile_y,
+                                            RobustSmem& sm) {
+  float(*sMuRef)[RR_N] = sm.sMuRef;
+  float* sInvDen = sm.sInvDen;
+  float(*sGuide)[GU_CAP] = sm.sGuide;
+  float(*sHs)[GU_CAP] = sm.sHs;
+  float* sR = sm.sR;
+  float* sTmp = sm.sTmp;
+  int* sTyR = sm.sTyR;
+  int* sTxR = sm.sTxR;
+  int* sRlo = sm.sRlo;
+  int* sRhi = sm.sRhi;
+  int* sClo = sm.sClo;
+  int* sChi = sm.sChi;
+  float2* sV = sm.sV;
+  float* sS = sm.sS;
+  Bounds4* sTB = sm.sTB;
+  int* sRed = sm.sRed;
 
   const int tid = threadIdx.x;
-  const int I0 = blockIdx.y * RB_H, J0 = blockIdx.x * RB_W;
+  const int I0 = tile_y * RB_H, J0 = tile_x * RB_W;
   const int ra0 = I0 - 2, ca0 = J0 - 2;  // region origin (may be outside the grid)
   const size_t plane = (size_t)g.h * g.w;
 
@@ -275,15 +297,59 @@ __global__ __launch_bounds__(THREADS) void k_robust(const uint16_t* __restrict__
   }
 }
 
+__global__ __launch_bounds__(THREADS) void k_robust(const uint16_t* __restrict__ frames,
+                                                    const float* __restrict__ motion,
+                                                    const float* __restrict__ s_tile, Geometry g,
+                                                    RobustConsts rc, float* __restrict__ rmin,
+                                                    float* __restrict__ robust) {
+  __shared__ RobustSmem sm;
+  robust_tile(frames, motion, s_tile, g, rc, rmin, robust, blockIdx.x, blockIdx.y, sm);
+}
+
+// Persistent form over (burst, tile) items of a batch.
+__global__ __launch_bounds__(THREADS) void k_robust_batch(const BurstArgs* __restrict__ bursts,
+                                                          const WorkItem* __restrict__ items,
+                                                          int n_items, int* __restrict__ counter) {
+  __shared__ RobustSmem sm;
+  while (true) {
+    __syncthreads();
+    if (threadIdx.x == 0) sm.sItem = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = sm.sItem;
+    if (it >= n_items) break;
+    const WorkItem w = items[it];
+    const BurstArgs& b = bursts[w.burst];
+    robust_tile(b.frames, b.motion, b.s_tile, b.g, b.rc, b.rmin, nullptr,
+                w.tile % b.robust_tiles_x, w.tile / b.robust_tiles_x, sm);
+  }
+}
+
 }  // namespace
+
+int robust_tiles_x(const Geometry& g) { return (g.w + RB_W - 1) / RB_W; }
+int robust_tiles_y(const Geometry& g) { return (g.h + RB_H - 1) / RB_H; }
 
 hipError_t launch_robust(const Geometry& g, const RobustConsts& rc, const uint16_t* frames,
                          const float* motion, const float* s_tile, float* rmin, float* robust,
                          hipStream_t stream) {
   if (g.n < 2) return hipSuccess;
-  const dim3 grid((g.w + RB_W - 1) / RB_W, (g.h + RB_H - 1) / RB_H);
+  const dim3 grid(robust_tiles_x(g), robust_tiles_y(g));
   hipLaunchKernelGGL(k_robust, grid, dim3(THREADS), 0, stream, frames, motion, s_tile, g, rc, rmin,
                      robust);
+  return hipGetLastError();
+}
+
+int robust_batch_blocks_per_cu() {
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_robust_batch, THREADS, 0) != hipSuccess) return 1;
+  return b > 0 ? b : 1;
+}
+
+hipError_t launch_robust_batch(const BurstArgs* bursts, const WorkItem* items, int n_items,
+                               int* counter, int n_groups, hipStream_t stream) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_robust_batch, dim3(n_groups), dim3(THREADS), 0, stream, bursts, items, n_items,
+                     counter);
   return hipGetLastError();
 }
 

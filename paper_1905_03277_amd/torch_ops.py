@@ -67,3 +67,38 @@ def merge_maps(frames: torch.Tensor, motion: torch.Tensor, desc, tuning) -> dict
                                  res["robust"].data_ptr(), res["robust_min"].data_ptr(),
                                  res["s_tile"].data_ptr(), _stream(dev))
     return res
+
+
+def merge_batch(bursts, outs=None) -> list:
+    """Merge a list of (frames, motion, desc, tuning) tuples in one graph launch.
+    Returns the output tensors (allocated unless given)."""
+    if outs is None:
+        outs = [torch.empty((3, d.out_height, d.out_width), dtype=torch.float32, device=f.device)
+                for f, m, d, t in bursts]
+    dev = bursts[0][0].device
+    for (f, m, d, t), o in zip(bursts, outs):
+        _check_inputs(f, m, d)
+        if f.device != dev or o.device != dev or tuple(o.shape) != (3, d.out_height, d.out_width) \
+                or o.dtype != torch.float32 or not o.is_contiguous():
+            raise ValueError("every burst and output must be on one device, outputs [3][OH][OW] float32")
+    with torch.cuda.device(dev):
+        binding.hmfsr_merge_batch([binding.make_desc(d) for f, m, d, t in bursts],
+                                  [binding.make_tuning(t) for f, m, d, t in bursts],
+                                  [f.data_ptr() for f, m, d, t in bursts],
+                                  [m.data_ptr() for f, m, d, t in bursts],
+                                  [o.data_ptr() for o in outs], _stream(dev))
+    return outs
+
+
+def autotune(frames: torch.Tensor, motion: torch.Tensor, desc, tuning,
+             out: torch.Tensor | None = None):
+    """Run the tile-shape autotuner on one burst; returns (chosen index, output)."""
+    _check_inputs(frames, motion, desc)
+    if out is None:
+        out = torch.empty((3, desc.out_height, desc.out_width), dtype=torch.float32,
+                          device=frames.device)
+    with torch.cuda.device(frames.device):
+        v = binding.hmfsr_autotune(binding.make_desc(desc), binding.make_tuning(tuning),
+                                   frames.data_ptr(), motion.data_ptr(), out.data_ptr(),
+                                   _stream(frames.device))
+    return v, out

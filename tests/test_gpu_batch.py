@@ -1,0 +1,94 @@
+"""Batched persistent merge (one captured graph) and the tile-shape autotuner."""
+import numpy as np
+import pytest
+import torch
+
+import oracle.merge as om
+from paper_1905_03277_amd import synth, torch_ops
+from parity_util import assert_parity
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+# (frames, H, W, scale, tile, cfa): uneven like the batched workload, small enough for tests
+SHAPES = [(8, 96, 128, 1.0, 16, 0), (2, 64, 64, 2.0, 16, 1), (15, 48, 96, 1.5, 8, 0),
+          (1, 64, 96, 1.5, 16, 2), (5, 160, 200, 1.0, 32, 3), (3, 70, 102, 2.0, 16, 0),
+          (12, 64, 80, 1.0, 16, 0), (4, 128, 96, 1.5, 16, 1)]
+
+
+def make_bursts():
+    out = []
+    for i, (n, h, w, s, t, cfa) in enumerate(SHAPES):
+        b = synth.make_burst(n, h, w, seed=5000 + i, scale=s, tile_size=t, cfa=cfa)
+        out.append(b)
+    return out
+
+
+def as_args(bursts, tunings=None):
+    return [(b.frames.to(DEV), b.motion.to(DEV), b.desc, (tunings or {}).get(i, b.tuning))
+            for i, b in enumerate(bursts)]
+
+
+def per_burst(args):
+    outs = [torch_ops.merge(f, m, d, t) for f, m, d, t in args]
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in outs]
+
+
+def test_batch_equals_per_burst_bitwise_and_replays():
+    bursts = make_bursts()
+    args = as_args(bursts)
+    print("[case] batch of", len(args), flush=True)
+    want = per_burst(args)
+    outs = torch_ops.merge_batch(args)
+    torch.cuda.synchronize()
+    for i, (o, w) in enumerate(zip(outs, want)):
+        np.testing.assert_array_equal(o.cpu().numpy(), w, err_msg=f"burst {i}")
+    # second call replays the captured graph into the same buffers
+    for o in outs:
+        o.fill_(-1.0)
+    torch_ops.merge_batch(args, outs)
+    torch.cuda.synchronize()
+    for i, (o, w) in enumerate(zip(outs, want)):
+        np.testing.assert_array_equal(o.cpu().numpy(), w, err_msg=f"replay burst {i}")
+    # new tuning values are uploaded before the replay
+    tun = {2: bursts[2].tuning.replace(t=0.5, k_detail=0.4), 4: bursts[4].tuning.replace(s=1.0)}
+    args2 = as_args(bursts, tun)
+    args2 = [(a[0], a[1], a[2], a2[3]) for a, a2 in zip(args, args2)]   # same buffers
+    torch_ops.merge_batch(args2, outs)
+    torch.cuda.synchronize()
+    want2 = per_burst(args2)
+    for i, (o, w) in enumerate(zip(outs, want2)):
+        np.testing.assert_array_equal(o.cpu().numpy(), w, err_msg=f"retuned burst {i}")
+    assert not np.array_equal(want2[2], want[2])
+
+
+def test_batch_matches_oracle():
+    bursts = make_bursts()
+    args = as_args(bursts)
+    outs = torch_ops.merge_batch(args)
+    torch.cuda.synchronize()
+    for i in (1, 2, 5):
+        b = bursts[i]
+        f, m = b.numpy()
+        print("[case] batch member", i, flush=True)
+        assert_parity(outs[i].cpu().numpy(), om.merge(f, m, b.desc, b.tuning), f"batch burst {i}")
+
+
+def test_autotune_picks_a_shape_and_is_used(monkeypatch, tmp_path):
+    monkeypatch.setenv("HMFSR_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    b = synth.make_burst(6, 192, 256, seed=77, scale=1.5, tile_size=16)
+    f, m = b.frames.to(DEV), b.motion.to(DEV)
+    v, out = torch_ops.autotune(f, m, b.desc, b.tuning)
+    torch.cuda.synchronize()
+    assert 0 <= v < 4
+    monkeypatch.setenv("HMFSR_MERGE_VARIANT", str(v))
+    ref = torch_ops.merge(f, m, b.desc, b.tuning)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), ref.cpu().numpy())
+    monkeypatch.delenv("HMFSR_MERGE_VARIANT")
+    again = torch_ops.merge(f, m, b.desc, b.tuning)   # the tuned table now picks v
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(again.cpu().numpy(), ref.cpu().numpy())
+    lines = (tmp_path / "tune.txt").read_text().split()
+    assert lines[-1] == str(v)
