@@ -85,12 +85,71 @@ def cpu_baseline(burst, budget_s: float = 12.0):
                       f"{dt:.1f} s, single thread"}
 
 
+def bench_batch(dev, reps: int = 3) -> dict:
+    """The uneven batched workload (64 bursts, 2-15 frames, 0.2-12 MP, scale
+    1/1.5/2): one replay of the captured persistent-kernel graph versus one
+    hmfsr_merge launch sequence per burst, after autotuning one burst of every
+    (scale, frame-count) class present."""
+    import torch
+    from paper_1905_03277_amd import synth, torch_ops
+
+    print("[bench] generating the 64-burst batch", file=sys.stderr, flush=True)
+    bursts = synth.make_batch(64, device=dev)
+    args = [(b.frames, b.motion, b.desc, b.tuning) for b in bursts]
+    outs = [torch.empty((3, b.desc.out_height, b.desc.out_width), dtype=torch.float32, device=dev)
+            for b in bursts]
+    tuned = {}
+    for (f, m, d, t), o in zip(args, outs):
+        key = (0 if d.scale <= 1 else 1 if d.scale <= 1.5 else 2,
+               0 if d.n_frames <= 4 else 1 if d.n_frames <= 8 else 2)
+        if key not in tuned:
+            tuned[key] = torch_ops.autotune(f, m, d, t, out=o)[0]
+    torch.cuda.synchronize()
+    in_mp = sum(d.n_frames * d.height * d.width for f, m, d, t in args) / 1e6
+    stream = torch.cuda.current_stream()
+
+    def timeit(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    print("[bench] batch: graph replay vs per-burst launches", file=sys.stderr, flush=True)
+    ms_graph = timeit(lambda: torch_ops.merge_batch(args, outs))
+    ms_loop = timeit(lambda: [torch_ops.merge(f, m, d, t, out=o) for (f, m, d, t), o in zip(args, outs)])
+    # per-burst rates of the launch loop
+    rates = []
+    for f, m, d, t in args:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        torch_ops.merge(f, m, d, t)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rates.append(d.n_frames * d.height * d.width / 1e6 / (e0.elapsed_time(e1) / 1e3))
+    rates.sort()
+    return {"workload": "64 bursts, frames U{2..15}, sizes {512x384, 1024x768, 2016x1512, "
+                        "4032x3024}, scale {1, 1.5, 2}",
+            "input_MP": round(in_mp, 1), "ms_graph": round(ms_graph, 3), "ms_per_burst_loop": round(ms_loop, 3),
+            "MPs_graph": round(in_mp / (ms_graph / 1e3), 1),
+            "MPs_per_burst_loop": round(in_mp / (ms_loop / 1e3), 1),
+            "speedup": round(ms_loop / ms_graph, 3),
+            "per_burst_MPs_loop": {"min": round(rates[0], 1), "median": round(rates[len(rates) // 2], 1),
+                                   "max": round(rates[-1], 1)},
+            "tuned_shapes": {f"{k[0]}/{k[1]}": v for k, v in tuned.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-burst batched leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus 1); the merge shards by "
@@ -167,6 +226,9 @@ def main():
                 "frac": round(byts["total"] / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "wall_s_timed": round(wall, 3),
     }
+    if not args.no_batch:
+        del out
+        line["batched"] = bench_batch(dev)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(burst.to("cpu"))

@@ -306,10 +306,17 @@ def make_burst(n_frames: int, height: int, width: int, *, seed: int, sigma_t: fl
             sx0, sy0 = _warp(px, py, thetas[0], trans[0, 0], trans[0, 1], cx, cy)
             gt[:, r0:r1] = eval_scene(sp, sx0, sy0).to(torch.float32)
 
-    frames_u16 = frames.cpu().numpy().astype(np.uint16)
-    frames_t = torch.from_numpy(frames_u16)
+    frames_t = None
     if str(device) != "cpu":
-        frames_t = frames_t.to(device)
+        try:  # convert on the device when torch supports it
+            frames_t = frames.to(torch.uint16)
+        except (RuntimeError, TypeError):
+            frames_t = None
+    if frames_t is None:
+        frames_t = torch.from_numpy(frames.cpu().numpy().astype(np.uint16))
+        if str(device) != "cpu":
+            frames_t = frames_t.to(device)
+    del frames
     meta = {"seed": seed, "thetas": thetas, "trans": trans, "occluder": occ}
     return Burst(desc, tuning, frames_t, torch.from_numpy(motion).to(device), gt, meta)
 
