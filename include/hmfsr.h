@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define HMFSR_VERSION 100 /* 1.0.0 */
+#define HMFSR_VERSION 110 /* 1.1.0 */
 
 /* Colour filter array layout: colours of the 2x2 Bayer cell read row by row. */
 typedef enum {
@@ -117,11 +117,42 @@ typedef struct {
  *          and taken as 0.
  *  out     DEVICE float32 [3][out_height][out_width], planes R, G, B of the
  *          normalised linear result (eq. 1).
+ *  saved   NULL, or DEVICE float32 [3][3][out_height][out_width]: per channel
+ *          the numerator, denominator (raw units, both scaled by 2^-m) and
+ *          reference exponent m (log2 units) of eq. (1) at every output
+ *          pixel. hmfsr_merge_backward can reuse it instead of rerunning the
+ *          forward.
  * Returns HMFSR_OK, or an error code with nothing enqueued.
  */
 hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
                          const uint16_t* frames, const float* motion, float* out,
-                         void* stream);
+                         float* saved, void* stream);
+
+/*
+ * hmfsr_merge_backward -- adjoint of hmfsr_merge. Given dL/dC for the output C
+ * of hmfsr_merge on the same inputs, the gradient of L with respect to the
+ * tuning scalars and to the displacements. The paper defines no gradient:
+ * this is the derivative of the merge as defined by eq. (1)-(9) and S.1,
+ * with every piecewise-constant decision (nine-sample window centres,
+ * bilinear cells, the motion-prior choice of eq. 8, the clamps of D and of
+ * R in eq. 5, the 5x5 argmin of eq. 9, first minimum in scan order) held fixed.
+ *  frames, motion  as for hmfsr_merge.
+ *  saved     NULL (the forward normaliser is recomputed internally) or the
+ *            buffer a hmfsr_merge call on the same inputs filled.
+ *  grad_out  DEVICE float32 [3][out_height][out_width]: dL/dC.
+ *  grad_tuning  DEVICE float32 [9]: dL/d(k_detail, k_denoise, d_th, d_tr,
+ *            k_stretch, k_shrink, s, t, s_motion). m_th is a threshold with
+ *            zero derivative almost everywhere and gets none.
+ *  grad_motion  DEVICE float32 [n_frames][TY][TX][2]: dL/d(vx, vy); the
+ *            base frame's vectors are ignored by the merge and get 0.
+ * Kernel weights are recomputed, not stored. Sums are taken in a fixed order:
+ * repeated calls give identical bits. The internal workspace grows to about
+ * 40 bytes per output pixel plus 9 * 4 more when saved is NULL.
+ */
+hmfsr_status hmfsr_merge_backward(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
+                                  const uint16_t* frames, const float* motion,
+                                  const float* saved, const float* grad_out,
+                                  float* grad_tuning, float* grad_motion, void* stream);
 
 /*
  * hmfsr_merge_maps -- the per-frame intermediate maps of the merge, for
@@ -187,6 +218,9 @@ enum {
   HMFSR_STAGE_ROBUST = 1, /* robustness and its 5x5 minimum (eq. 5-9)  */
   HMFSR_STAGE_MERGE = 2,  /* kernel-regression accumulation (eq. 1-4)  */
   HMFSR_STAGE_BATCH = 3,  /* one replay of a batched-merge graph       */
+  HMFSR_STAGE_MERGE_BWD = 4,   /* adjoint of the accumulation              */
+  HMFSR_STAGE_ROBUST_BWD = 5,  /* adjoint of the robustness                */
+  HMFSR_STAGE_GRAD_REDUCE = 6, /* fixed-order sums of the gradient partials */
   HMFSR_NUM_STAGES = 8
 };
 typedef struct {

@@ -17,14 +17,19 @@ LIB_PATH = os.path.join(_HERE, "libhmfsr.so")
 HMFSR_OK, HMFSR_E_INVALID, HMFSR_E_UNSUPPORTED, HMFSR_E_HIP, HMFSR_E_NOMEM = 0, -1, -2, -3, -4
 
 # Every symbol include/hmfsr.h declares.
-EXPORTED = ("hmfsr_merge", "hmfsr_merge_maps", "hmfsr_merge_batch", "hmfsr_autotune",
-            "hmfsr_profile_begin", "hmfsr_profile_end", "hmfsr_strerror", "hmfsr_version",
-            "hmfsr_release")
+EXPORTED = ("hmfsr_merge", "hmfsr_merge_backward", "hmfsr_merge_maps", "hmfsr_merge_batch",
+            "hmfsr_autotune", "hmfsr_profile_begin", "hmfsr_profile_end", "hmfsr_strerror",
+            "hmfsr_version", "hmfsr_release")
 
 STAGE_PRIOR, STAGE_ROBUST, STAGE_MERGE, STAGE_BATCH = 0, 1, 2, 3
+STAGE_MERGE_BWD, STAGE_ROBUST_BWD, STAGE_GRAD_REDUCE = 4, 5, 6
 NUM_STAGES = 8
 STAGE_NAMES = {STAGE_PRIOR: "k_prior", STAGE_ROBUST: "k_robust", STAGE_MERGE: "k_merge",
-               STAGE_BATCH: "batch_graph"}
+               STAGE_BATCH: "batch_graph", STAGE_MERGE_BWD: "k_merge_bwd",
+               STAGE_ROBUST_BWD: "k_robust_bwd", STAGE_GRAD_REDUCE: "k_grad_reduce"}
+
+# Order of hmfsr_merge_backward's grad_tuning.
+GRAD_NAMES = ("k_detail", "k_denoise", "d_th", "d_tr", "k_stretch", "k_shrink", "s", "t", "s_motion")
 
 
 class hmfsr_desc(ctypes.Structure):
@@ -66,8 +71,10 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(LIB_PATH)
         vp, i32 = ctypes.c_void_p, ctypes.c_int32
         pd, pt = ctypes.POINTER(hmfsr_desc), ctypes.POINTER(hmfsr_tuning)
-        L.hmfsr_merge.argtypes = [pd, pt, vp, vp, vp, vp]
+        L.hmfsr_merge.argtypes = [pd, pt, vp, vp, vp, vp, vp]
         L.hmfsr_merge.restype = i32
+        L.hmfsr_merge_backward.argtypes = [pd, pt, vp, vp, vp, vp, vp, vp, vp]
+        L.hmfsr_merge_backward.restype = i32
         L.hmfsr_merge_maps.argtypes = [pd, pt, vp, vp, vp, vp, vp, vp, vp]
         L.hmfsr_merge_maps.restype = i32
         L.hmfsr_merge_batch.argtypes = [i32, pd, pt, ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -108,9 +115,17 @@ def make_tuning(t) -> hmfsr_tuning:
 
 
 def hmfsr_merge(desc: hmfsr_desc, tuning: hmfsr_tuning, frames: int, motion: int, out: int,
-                stream: int = 0) -> None:
+                saved: int = 0, stream: int = 0) -> None:
     _check(lib().hmfsr_merge(ctypes.byref(desc), ctypes.byref(tuning), frames, motion, out,
-                             stream or None), "hmfsr_merge")
+                             saved or None, stream or None), "hmfsr_merge")
+
+
+def hmfsr_merge_backward(desc: hmfsr_desc, tuning: hmfsr_tuning, frames: int, motion: int,
+                         saved: int, grad_out: int, grad_tuning: int, grad_motion: int,
+                         stream: int = 0) -> None:
+    _check(lib().hmfsr_merge_backward(ctypes.byref(desc), ctypes.byref(tuning), frames, motion,
+                                      saved or None, grad_out, grad_tuning, grad_motion,
+                                      stream or None), "hmfsr_merge_backward")
 
 
 def hmfsr_merge_maps(desc, tuning, frames: int, motion: int, omega: int, robust: int,

@@ -147,31 +147,40 @@ hmfsr_status current_device(int* dev_out) {
   return HMFSR_OK;
 }
 
+namespace {
 // Growing a workspace frees the old one only after the stream that may still
 // use it has drained.
-hmfsr_status workspace(int dev, size_t bytes, hipStream_t stream, void** out) {
-  DeviceState& st = g_dev[dev];
-  if (st.workspace_bytes < bytes) {
-    if (st.workspace) {
+hmfsr_status grow(void*& buf, size_t& have, size_t bytes, hipStream_t stream, void** out) {
+  if (have < bytes) {
+    if (buf) {
       if (hipStreamSynchronize(stream) != hipSuccess) return HMFSR_E_HIP;
-      hipFree(st.workspace);
-      st.workspace = nullptr;
-      st.workspace_bytes = 0;
+      hipFree(buf);
+      buf = nullptr;
+      have = 0;
     }
-    if (hipMalloc(&st.workspace, bytes) != hipSuccess) {
+    if (hipMalloc(&buf, bytes) != hipSuccess) {
       (void)hipGetLastError();
-      st.workspace = nullptr;
+      buf = nullptr;
       return HMFSR_E_NOMEM;
     }
-    st.workspace_bytes = bytes;
+    have = bytes;
   }
-  *out = st.workspace;
+  *out = buf;
   return HMFSR_OK;
+}
+}  // namespace
+
+hmfsr_status workspace(int dev, size_t bytes, hipStream_t stream, void** out) {
+  return grow(g_dev[dev].workspace, g_dev[dev].workspace_bytes, bytes, stream, out);
+}
+
+hmfsr_status bwd_workspace(int dev, size_t bytes, hipStream_t stream, void** out) {
+  return grow(g_dev[dev].bwd_ws, g_dev[dev].bwd_ws_bytes, bytes, stream, out);
 }
 
 hmfsr_status run_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, const Geometry& g,
-                       const uint16_t* frames, const float* motion, float* out, const Work& w,
-                       int variant, hipStream_t s) {
+                       const uint16_t* frames, const float* motion, float* out, float* saved,
+                       const Work& w, int variant, hipStream_t s) {
   const PriorConsts pc = make_prior(tuning);
   const RobustConsts rc = make_robust(desc, tuning);
   const MergeConsts mc = make_merge(desc, tuning, g);
@@ -182,7 +191,7 @@ hmfsr_status run_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, const
       }) != hipSuccess)
     return HMFSR_E_HIP;
   if (timed(HMFSR_STAGE_MERGE, s, [&] {
-        return launch_merge(variant, g, mc, frames, motion, w.rmin, out, s);
+        return launch_merge(variant, g, mc, frames, motion, w.rmin, out, saved, s);
       }) != hipSuccess)
     return HMFSR_E_HIP;
   return HMFSR_OK;
@@ -195,11 +204,12 @@ using namespace hmfsr;
 extern "C" {
 
 hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, const uint16_t* frames,
-                         const float* motion, float* out, void* stream) {
+                         const float* motion, float* out, float* saved, void* stream) {
   hmfsr_status st = validate(desc, tuning);
   if (st != HMFSR_OK) return st;
   if (!frames || !motion || !out) return HMFSR_E_INVALID;
-  if (((uintptr_t)frames & 3) || ((uintptr_t)motion & 3) || ((uintptr_t)out & 3)) return HMFSR_E_INVALID;
+  if (((uintptr_t)frames & 3) || ((uintptr_t)motion & 3) || ((uintptr_t)out & 3) || ((uintptr_t)saved & 3))
+    return HMFSR_E_INVALID;
   std::lock_guard<std::mutex> lock(g_mutex);
   int dev = 0;
   if ((st = current_device(&dev)) != HMFSR_OK) return st;
@@ -207,7 +217,66 @@ hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, con
   void* ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
   if ((st = workspace(dev, work_bytes(g), s, &ws)) != HMFSR_OK) return st;
-  return run_merge(desc, tuning, g, frames, motion, out, work_carve(ws, g), merge_variant(g), s);
+  return run_merge(desc, tuning, g, frames, motion, out, saved, work_carve(ws, g), merge_variant(g), s);
+}
+
+hmfsr_status hmfsr_merge_backward(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
+                                  const uint16_t* frames, const float* motion, const float* saved,
+                                  const float* grad_out, float* grad_tuning, float* grad_motion,
+                                  void* stream) {
+  hmfsr_status st = validate(desc, tuning);
+  if (st != HMFSR_OK) return st;
+  if (!frames || !motion || !grad_out || !grad_tuning || !grad_motion) return HMFSR_E_INVALID;
+  for (const void* p : {(const void*)frames, (const void*)motion, (const void*)saved, (const void*)grad_out,
+                        (const void*)grad_tuning, (const void*)grad_motion})
+    if ((uintptr_t)p & 3) return HMFSR_E_INVALID;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  int dev = 0;
+  if ((st = current_device(&dev)) != HMFSR_OK) return st;
+  const Geometry g = make_geometry(desc);
+  hipStream_t s = (hipStream_t)stream;
+  void* ws = nullptr;
+  const bool need_saved = saved == nullptr;
+  if ((st = bwd_workspace(dev, bwd_bytes(g, need_saved), s, &ws)) != HMFSR_OK) return st;
+  const BwdWork w = bwd_carve(ws, g, need_saved);
+  const PriorConsts pc = make_prior(tuning);
+  const RobustConsts rc = make_robust(desc, tuning);
+  const MergeConsts mc = make_merge(desc, tuning, g);
+  BwdConsts bc;
+  bc.kd = tuning->k_detail;
+  bc.kn = tuning->k_denoise;
+  bc.kst = tuning->k_stretch;
+  bc.ksh = tuning->k_shrink;
+  bc.sl = mc.om.inv_16_range_dtr / (double)tuning->d_tr;
+  bc.tiles_x = (g.OW + 63) / 64;
+  bc.tiles_y = (g.OH + kBwdRows - 1) / kBwdRows;
+  bc.n_tiles = bc.tiles_x * bc.tiles_y;
+  if (timed(HMFSR_STAGE_PRIOR, s, [&] { return launch_prior(g, pc, motion, w.fwd.s_tile, s); }) != hipSuccess)
+    return HMFSR_E_HIP;
+  if (timed(HMFSR_STAGE_ROBUST, s, [&] {
+        return launch_robust(g, rc, frames, motion, w.fwd.s_tile, w.fwd.rmin, w.rmap, s);
+      }) != hipSuccess)
+    return HMFSR_E_HIP;
+  if (need_saved) {
+    if (timed(HMFSR_STAGE_MERGE, s, [&] {
+          return launch_merge(merge_variant(g), g, mc, frames, motion, w.fwd.rmin, nullptr, w.saved, s);
+        }) != hipSuccess)
+      return HMFSR_E_HIP;
+    saved = w.saved;
+  }
+  if (timed(HMFSR_STAGE_MERGE_BWD, s, [&] {
+        return launch_merge_bwd(g, mc, bc, frames, motion, w.fwd.rmin, saved, grad_out, w, s);
+      }) != hipSuccess)
+    return HMFSR_E_HIP;
+  if (timed(HMFSR_STAGE_ROBUST_BWD, s, [&] {
+        return launch_robust_bwd(g, rc, pc, bc, frames, motion, w, s);
+      }) != hipSuccess)
+    return HMFSR_E_HIP;
+  if (timed(HMFSR_STAGE_GRAD_REDUCE, s, [&] {
+        return launch_grad_reduce(g, bc, w, grad_tuning, grad_motion, s);
+      }) != hipSuccess)
+    return HMFSR_E_HIP;
+  return HMFSR_OK;
 }
 
 hmfsr_status hmfsr_merge_maps(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
@@ -295,16 +364,17 @@ void hmfsr_release(void) {
   const bool have_cur = hipGetDevice(&cur) == hipSuccess;
   for (int d = 0; d < kMaxDevices; ++d) {
     DeviceState& st = g_dev[d];
-    if (!st.workspace && !st.batch_ws && !st.plan.exec && !st.capture_stream) continue;
+    if (!st.workspace && !st.batch_ws && !st.bwd_ws && !st.plan.exec && !st.capture_stream) continue;
     if (hipSetDevice(d) != hipSuccess) continue;
     if (st.plan.exec) hipGraphExecDestroy(st.plan.exec);
     if (st.plan.graph) hipGraphDestroy(st.plan.graph);
     st.plan = BatchPlan();
     if (st.workspace) hipFree(st.workspace);
     if (st.batch_ws) hipFree(st.batch_ws);
+    if (st.bwd_ws) hipFree(st.bwd_ws);
     if (st.capture_stream) hipStreamDestroy(st.capture_stream);
-    st.workspace = st.batch_ws = nullptr;
-    st.workspace_bytes = st.batch_ws_bytes = 0;
+    st.workspace = st.batch_ws = st.bwd_ws = nullptr;
+    st.workspace_bytes = st.batch_ws_bytes = st.bwd_ws_bytes = 0;
     st.capture_stream = nullptr;
   }
   if (have_cur) hipSetDevice(cur);

@@ -110,17 +110,17 @@ hmfsr_status hmfsr_autotune(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
   if ((st = workspace(dev, work_bytes(g), s, &ws)) != HMFSR_OK) return st;
   const Work w = work_carve(ws, g);
   // robustness once, then every tile shape: one warm-up and three timed launches
-  if ((st = run_merge(desc, tuning, g, frames, motion, out, w, kDefaultVariant, s)) != HMFSR_OK) return st;
+  if ((st = run_merge(desc, tuning, g, frames, motion, out, nullptr, w, kDefaultVariant, s)) != HMFSR_OK) return st;
   const MergeConsts mc = make_merge(desc, tuning, g);
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return HMFSR_E_HIP;
   int best = kDefaultVariant;
   float best_ms = 1e30f;
   for (int v = 0; v < kNumMergeVariants && st == HMFSR_OK; ++v) {
-    if (launch_merge(v, g, mc, frames, motion, w.rmin, out, s) != hipSuccess) st = HMFSR_E_HIP;
+    if (launch_merge(v, g, mc, frames, motion, w.rmin, out, nullptr, s) != hipSuccess) st = HMFSR_E_HIP;
     if (hipEventRecord(a, s) != hipSuccess) st = HMFSR_E_HIP;
     for (int r = 0; r < 3 && st == HMFSR_OK; ++r)
-      if (launch_merge(v, g, mc, frames, motion, w.rmin, out, s) != hipSuccess) st = HMFSR_E_HIP;
+      if (launch_merge(v, g, mc, frames, motion, w.rmin, out, nullptr, s) != hipSuccess) st = HMFSR_E_HIP;
     float ms = 0.f;
     if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
         hipEventElapsedTime(&ms, a, b) != hipSuccess)
@@ -134,7 +134,7 @@ hmfsr_status hmfsr_autotune(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
   hipEventDestroy(b);
   if (st != HMFSR_OK) return st;
   // leave `out` holding the merge of the chosen shape
-  if (launch_merge(best, g, mc, frames, motion, w.rmin, out, s) != hipSuccess) return HMFSR_E_HIP;
+  if (launch_merge(best, g, mc, frames, motion, w.rmin, out, nullptr, s) != hipSuccess) return HMFSR_E_HIP;
   tune_load();
   g_tune.v[scale_class(g.scale)][frame_bucket(g.n)] = best;
   g_tune.tuned[scale_class(g.scale)][frame_bucket(g.n)] = true;

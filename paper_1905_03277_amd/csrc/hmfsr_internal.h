@@ -84,8 +84,11 @@ struct MergeVariant {
 };
 extern const MergeVariant kMergeVariants[];
 extern const int kNumMergeVariants;
+// out and saved are each nullable; saved receives the normaliser of eq. (1):
+// [3][3][OH][OW] numerator, denominator and reference exponent per channel.
 hipError_t launch_merge(int variant, const Geometry& g, const MergeConsts& mc, const uint16_t* frames,
-                        const float* motion, const float* rmin, float* out, hipStream_t stream);
+                        const float* motion, const float* rmin, float* out, float* saved,
+                        hipStream_t stream);
 hipError_t launch_merge_batch(int variant, const BurstArgs* bursts, const WorkItem* items, int n_items,
                               int* counter, int n_groups, hipStream_t stream);
 hipError_t launch_robust_batch(const BurstArgs* bursts, const WorkItem* items, int n_items,
@@ -101,5 +104,41 @@ hipError_t launch_fill_i32(int* p, int v, size_t n, hipStream_t stream);
 hipError_t launch_fill(float* p, float v, size_t n, hipStream_t stream);
 hipError_t launch_omega_map(const Geometry& g, const OmegaConsts& oc, const uint16_t* frames,
                             double* omega, hipStream_t stream);
+
+// ---- adjoint ---------------------------------------------------------------
+
+// Output tile of the adjoint kernel: 64 x kBwdRows pixels.
+constexpr int kBwdRows = 16;
+constexpr int kBwdVT = (64 / 8 + 2) * (kBwdRows / 8 + 2);   // alignment tiles per output tile, max
+constexpr int kBwdRH = (64 / 2 + 2) * (kBwdRows / 2 + 2);   // R_hat window cells per output tile, max
+
+struct BwdConsts {
+  double kd, kn, kst, ksh;  // k_detail, k_denoise, k_stretch, k_shrink
+  double sl;                // dD/dD_tr per unit of sqrt(lambda1) of the integer tensor
+  int tiles_x, tiles_y, n_tiles;  // output tiles of the adjoint's tile shape
+};
+
+// Workspace of the adjoint (on top of the forward's s_tile and R_hat maps).
+struct BwdWork {
+  Work fwd;
+  float* rmap;        // [n][h][w] R of eq. (5)
+  float* saved;       // [9][OH][OW] normaliser of eq. (1) when the caller keeps none
+  float* part_rh;     // [n][tiles][kBwdRH] dL/dR_hat over each tile's R_hat window
+  double* part_mo;    // [tiles][n][kBwdVT][2] dL/dv of the alignment tiles each tile touches
+  double* part_theta; // [tiles][6] dL/d(k_detail, k_denoise, d_th, d_tr, k_stretch, k_shrink), unscaled
+  double* part_rob;   // [n][TY][TX][5] robustness part: dL/dvx, dL/dvy, dL/dt, dL/ds, dL/ds_motion
+};
+size_t bwd_bytes(const Geometry& g, bool need_saved);
+BwdWork bwd_carve(void* base, const Geometry& g, bool need_saved);
+
+hipError_t launch_merge_bwd(const Geometry& g, const MergeConsts& mc, const BwdConsts& bc,
+                            const uint16_t* frames, const float* motion, const float* rmin,
+                            const float* saved, const float* grad_out, const BwdWork& w,
+                            hipStream_t stream);
+hipError_t launch_robust_bwd(const Geometry& g, const RobustConsts& rc, const PriorConsts& pc,
+                             const BwdConsts& bc, const uint16_t* frames, const float* motion,
+                             const BwdWork& w, hipStream_t stream);
+hipError_t launch_grad_reduce(const Geometry& g, const BwdConsts& bc, const BwdWork& w,
+                              float* grad_tuning, float* grad_motion, hipStream_t stream);
 
 }  // namespace hmfsr

@@ -28,6 +28,8 @@ struct DeviceState {
   size_t workspace_bytes = 0;
   void* batch_ws = nullptr;   // batch workspace
   size_t batch_ws_bytes = 0;
+  void* bwd_ws = nullptr;     // adjoint workspace
+  size_t bwd_ws_bytes = 0;
   hipStream_t capture_stream = nullptr;
   BatchPlan plan;
 };
@@ -68,13 +70,14 @@ MergeConsts make_merge(const hmfsr_desc* d, const hmfsr_tuning* t, const Geometr
 OmegaConsts make_omega(const hmfsr_desc* d, const hmfsr_tuning* t);
 hmfsr_status current_device(int* dev_out);  // caller holds g_mutex
 hmfsr_status workspace(int dev, size_t bytes, hipStream_t stream, void** out);  // caller holds g_mutex
+hmfsr_status bwd_workspace(int dev, size_t bytes, hipStream_t stream, void** out);  // caller holds g_mutex
 
 // Merge tile shape for a burst: HMFSR_MERGE_VARIANT, else the autotuned
 // choice for the burst's (scale, frame count) class, else the default.
 int merge_variant(const Geometry& g);
 // The three kernels of one merge on `s` (workspace from `workspace`).
 hmfsr_status run_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, const Geometry& g,
-                       const uint16_t* frames, const float* motion, float* out, const Work& w,
-                       int variant, hipStream_t s);
+                       const uint16_t* frames, const float* motion, float* out, float* saved,
+                       const Work& w, int variant, hipStream_t s);
 
 }  // namespace hmfsr

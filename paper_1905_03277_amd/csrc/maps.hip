@@ -2,14 +2,14 @@
 #include <math.h>
 
 #include "hmfsr_internal.h"
+#include "prior.h"
 
 namespace hmfsr {
 namespace {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// eq. (7)-(8): spread of the displacements over the 3x3 tile neighbourhood
-// (tiles outside the grid skipped) -> rejection strength s1 or s2.
+// eq. (7)-(8): rejection strength s1 or s2 per tile.
 __device__ __forceinline__ void prior_one(const float* __restrict__ motion, const Geometry& g,
                                           const PriorConsts& pc, float* __restrict__ s_tile, int n,
                                           int ty, int tx) {
@@ -18,23 +18,7 @@ __device__ __forceinline__ void prior_one(const float* __restrict__ motion, cons
     s_tile[idx] = 0.0f;
     return;
   }
-  double xmax = -INFINITY, xmin = INFINITY, ymax = -INFINITY, ymin = INFINITY;
-  for (int a = -1; a <= 1; ++a) {
-    for (int b = -1; b <= 1; ++b) {
-      const int y = ty + a, x = tx + b;
-      if (y < 0 || y >= g.TY || x < 0 || x >= g.TX) continue;
-      const float* v = motion + (((size_t)n * g.TY + y) * g.TX + x) * 2;
-      const double vx = v[0], vy = v[1];
-      xmax = fmax(xmax, vx);
-      xmin = fmin(xmin, vx);
-      ymax = fmax(ymax, vy);
-      ymin = fmin(ymin, vy);
-    }
-  }
-  const double mx = xmax - xmin, my = ymax - ymin;
-  // M > M_th evaluated as M^2 > M_th^2, rounded operation by operation.
-  const double m2 = __dadd_rn(__dmul_rn(mx, mx), __dmul_rn(my, my));
-  s_tile[idx] = m2 > __dmul_rn(pc.m_th, pc.m_th) ? pc.s1 : pc.s2;
+  s_tile[idx] = prior_moving(motion, g, pc.m_th, n, ty, tx) ? pc.s1 : pc.s2;
 }
 
 __global__ void k_prior(const float* __restrict__ motion, Geometry g, PriorConsts pc,

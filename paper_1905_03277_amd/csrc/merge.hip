@@ -21,42 +21,13 @@
 
 #include "device_util.h"
 #include "hmfsr_internal.h"
+#include "merge_common.h"
 #include "omega.h"
 
 namespace hmfsr {
 namespace {
 
-constexpr int MW = 64;          // output columns per tile = lanes per wave
 constexpr float SLACK = 64.f;   // log2 headroom above the reference exponent
-// -log2(e) / 2: exponent of eq. (2) in base 2.
-constexpr double NEG_HALF_LOG2E = -0.72134752044448170368;
-// Distances given to out-of-frame sample columns / rows: their quadratic
-// form is then ~1e200 or more (Omega^-1 is bounded below), i.e. weight 0.
-constexpr double FAR_X = 1e100, FAR_Y = 1e120;
-
-template <int MH>
-struct Caps {
-  // sized for scale 1 with up to ~8 px of displacement spread inside the tile
-  static constexpr int RAW = (MW + 16) * (MH + 16);
-  static constexpr int LUMA = (MW / 2 + 8) * (MH / 2 + 8);
-  static constexpr int OM = (MW / 2 + 6) * (MH / 2 + 6);
-  static constexpr int RH = (MW / 2 + 2) * (MH / 2 + 2);
-  static constexpr int TX = MW / 8 + 2, TY = MH / 8 + 2;  // alignment tiles (T >= 8)
-  static constexpr int VT = TX * TY;
-};
-
-__device__ __forceinline__ int colour_of(int col4, int parity) { return (col4 >> (2 * parity)) & 3; }
-
-struct RowInfo {
-  int ya, yb;  // R_hat window row offsets (already multiplied by the window width)
-  float fy;
-};
-
-// Footprint of a set of output pixels in one frame: ranges of the
-// nine-sample window centres (jc, ic) and of the Omega bilinear corners (hj, hi).
-struct Bounds {
-  int jc0, jc1, ic0, ic1, hj0, hj1, hi0, hi1;
-};
 
 template <int MH>
 struct MergeSmem {
@@ -81,8 +52,9 @@ template <int MH, int THREADS>
 __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
                                            const float* __restrict__ motion,
                                            const float* __restrict__ rmin, const Geometry& g,
-                                           const MergeConsts& mc, float* __restrict__ out, int tile_x,
-                                           int tile_y, MergeSmem<MH>& sm) {
+                                           const MergeConsts& mc, float* __restrict__ out,
+                                           float* __restrict__ saved, int tile_x, int tile_y,
+                                           MergeSmem<MH>& sm) {
   constexpr int WAVES = THREADS / 64;
   constexpr int PX = MH / WAVES;
   static_assert(PX * WAVES == MH, "tile rows must split evenly over the waves");
@@ -112,13 +84,13 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
   // ---- per-tile geometry ------------------------------------------------
   const int C = C0 + lane;
   const bool col_ok = lane < ncol;
-  const double X = ((double)C + 0.5) / g.scale;  // base-frame position of the column
+  const double X = out_pos(C, g.scale);  // base-frame position of the column
   if (tid < MW) {
     sX[tid] = X;
     sTxCol[tid] = col_ok ? min((int)floor(X) / g.T, g.TX - 1) : 0;
   }
   for (int r = tid; r < MH; r += THREADS) {
-    const double Y = ((double)(R0 + r) + 0.5) / g.scale;
+    const double Y = out_pos(R0 + r, g.scale);
     sY[r] = Y;
     sTyRow[r] = r < nrow ? min((int)floor(Y) / g.T, g.TY - 1) : 0;
   }
@@ -139,10 +111,8 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
   }
   // R_hat window on the base half-res grid: bilinear corners of X/2 - 1/2.
   if (tid == 0) {
-    sRh0[0] = clampi((int)floor(sX[0] * 0.5 - 0.5), 0, g.w - 1);
-    sRh0[1] = clampi((int)floor(sX[ncol - 1] * 0.5 - 0.5) + 1, 0, g.w - 1);
-    sRh0[2] = clampi((int)floor(sY[0] * 0.5 - 0.5), 0, g.h - 1);
-    sRh0[3] = clampi((int)floor(sY[nrow - 1] * 0.5 - 0.5) + 1, 0, g.h - 1);
+    rh_range(C0, C0 + ncol - 1, g.scale, g.w, sRh0[0], sRh0[1]);
+    rh_range(R0, R0 + nrow - 1, g.scale, g.h, sRh0[2], sRh0[3]);
   }
   __syncthreads();
   const int rhc0 = sRh0[0], rhw = sRh0[1] - sRh0[0] + 1;
@@ -450,8 +420,18 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
       const int r = wave * PX + p;
       if (r >= nrow) continue;
       const size_t o = (size_t)(R0 + r) * g.OW + C;
+      if (out) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) out[o + c * plane] = (num[p][c] / den[p][c] - mc.black) * mc.inv_range;
+        for (int c = 0; c < 3; ++c) out[o + c * plane] = (num[p][c] / den[p][c] - mc.black) * mc.inv_range;
+      }
+      if (saved) {  // the normaliser of eq. (1), for the adjoint
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          saved[o + c * plane] = num[p][c];
+          saved[o + (3 + c) * plane] = den[p][c];
+          saved[o + (6 + c) * plane] = M[p][c];
+        }
+      }
     }
   }
 }
@@ -459,9 +439,10 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
 template <int MH, int THREADS>
 __global__ __launch_bounds__(THREADS, (MH / (THREADS / 64) <= 4) ? 4 : 2) void k_merge(
     const uint16_t* __restrict__ frames, const float* __restrict__ motion,
-    const float* __restrict__ rmin, Geometry g, MergeConsts mc, float* __restrict__ out) {
+    const float* __restrict__ rmin, Geometry g, MergeConsts mc, float* __restrict__ out,
+    float* __restrict__ saved) {
   __shared__ MergeSmem<MH> sm;
-  merge_tile<MH, THREADS>(frames, motion, rmin, g, mc, out, blockIdx.x, blockIdx.y, sm);
+  merge_tile<MH, THREADS>(frames, motion, rmin, g, mc, out, saved, blockIdx.x, blockIdx.y, sm);
 }
 
 // Persistent form: workgroups pull (burst, tile) items from a global counter
@@ -481,16 +462,17 @@ __global__ __launch_bounds__(THREADS, (MH / (THREADS / 64) <= 4) ? 4 : 2) void k
     const WorkItem w = items[it];
     const BurstArgs& b = bursts[w.burst];
     const int tx = w.tile % b.merge_tiles_x, ty = w.tile / b.merge_tiles_x;
-    merge_tile<MH, THREADS>(b.frames, b.motion, b.rmin, b.g, b.mc, b.out, tx, ty, sm);
+    merge_tile<MH, THREADS>(b.frames, b.motion, b.rmin, b.g, b.mc, b.out, nullptr, tx, ty, sm);
   }
 }
 
 template <int MH, int THREADS>
 hipError_t launch_variant(const Geometry& g, const MergeConsts& mc, const uint16_t* frames,
-                          const float* motion, const float* rmin, float* out, hipStream_t stream) {
+                          const float* motion, const float* rmin, float* out, float* saved,
+                          hipStream_t stream) {
   const dim3 grid((g.OW + MW - 1) / MW, (g.OH + MH - 1) / MH);
   hipLaunchKernelGGL((k_merge<MH, THREADS>), grid, dim3(THREADS), 0, stream, frames, motion, rmin, g,
-                     mc, out);
+                     mc, out, saved);
   return hipGetLastError();
 }
 
@@ -510,12 +492,13 @@ const MergeVariant kMergeVariants[] = {
 const int kNumMergeVariants = sizeof(kMergeVariants) / sizeof(kMergeVariants[0]);
 
 hipError_t launch_merge(int variant, const Geometry& g, const MergeConsts& mc, const uint16_t* frames,
-                        const float* motion, const float* rmin, float* out, hipStream_t stream) {
+                        const float* motion, const float* rmin, float* out, float* saved,
+                        hipStream_t stream) {
   switch (variant) {
-    case 1: return launch_variant<32, 512>(g, mc, frames, motion, rmin, out, stream);
-    case 2: return launch_variant<16, 256>(g, mc, frames, motion, rmin, out, stream);
-    case 3: return launch_variant<16, 128>(g, mc, frames, motion, rmin, out, stream);
-    default: return launch_variant<32, 256>(g, mc, frames, motion, rmin, out, stream);
+    case 1: return launch_variant<32, 512>(g, mc, frames, motion, rmin, out, saved, stream);
+    case 2: return launch_variant<16, 256>(g, mc, frames, motion, rmin, out, saved, stream);
+    case 3: return launch_variant<16, 128>(g, mc, frames, motion, rmin, out, saved, stream);
+    default: return launch_variant<32, 256>(g, mc, frames, motion, rmin, out, saved, stream);
   }
 }
 

@@ -1,0 +1,919 @@
+// Adjoint of the merge: given dL/dC for the output C, the gradient of L with
+// respect to the tuning scalars of the kernel covariance (Sec. 5.1.2, eq. 4,
+// supplement S.1: k_detail, k_denoise, D_th, D_tr, k_stretch, k_shrink) and of
+// the robustness (eq. 5 and 8: s, t, s_motion), and to the per-tile
+// displacement of every aligned frame.
+//
+// Kernel weights are recomputed, never stored: the forward keeps only the
+// normaliser of eq. (1) per output pixel and channel (numerator, denominator,
+// reference exponent). With w_i = exp(e_i - m) and den = sum rho_i w_i,
+//   dC/drho_i = w_i (c_i - C) / den,   dC/de_i = rho_i w_i (c_i - C) / den,
+// and e = -1/2 d^T Omega^-1 d with d = q + 1/2 - p gives
+//   de/dp = Omega^-1 d,   de/dOmega = 1/2 Omega^-1 d d^T Omega^-1.
+//
+// k_merge_bwd   one workgroup per 64 x 16 output tile, staging each frame as
+//               the forward does. Per pixel and frame it forms dL/de for the
+//               nine samples and dL/drho, then
+//               - dL/dp (offsets and the Omega sampling position), summed per
+//                 alignment tile into per-workgroup partials;
+//               - dL/dOmega_bar, contracted at the four bilinear corners with
+//                 dOmega/dtheta, which the Omega staging keeps per half-res
+//                 pixel in LDS, into six per-thread sums;
+//               - dL/drho, transposed through the fixed R_hat bilinear weights
+//                 onto the tile's R_hat window (per-workgroup partials).
+// k_robust_bwd  one workgroup per (aligned frame, alignment tile): gathers
+//               dL/dR_hat, hands it to the 5x5 argmin of eq. (9), then
+//               through the clamp and exponential of eq. (5) and the
+//               noise-corrected distance of eq. (6) to s or s_motion, t and
+//               the tile's displacement (through the sampled colour mean).
+// k_grad_*      add the partials up.
+// Every sum runs in a fixed order, so two runs give identical bits.
+#include <math.h>
+
+#include "device_util.h"
+#include "hmfsr_internal.h"
+#include "merge_common.h"
+#include "omega.h"
+#include "prior.h"
+
+namespace hmfsr {
+namespace {
+
+constexpr int BMH = kBwdRows;
+constexpr int BTHREADS = 256;
+constexpr int BWAVES = BTHREADS / 64;
+constexpr int BPX = BMH / BWAVES;  // pixel rows per thread
+using BCP = Caps<BMH>;
+static_assert(BCP::VT == kBwdVT && BCP::RH == kBwdRH, "partial layouts follow the tile caps");
+
+struct BwdSmem {
+  double sX[MW], sY[BMH];
+  int sTyRow[BMH], sTxCol[MW];
+  int sRlo[BCP::TY], sRhi[BCP::TY], sClo[BCP::TX], sChi[BCP::TX];
+  RowInfo sRow[BMH];
+  int sRya[BMH], sRyb[BMH];           // R_hat window rows of each pixel row
+  int sRxa[MW], sRxb[MW];             // R_hat window columns of each pixel column
+  float sRfx[MW];
+  int sJlo[BCP::RH_W], sJhi[BCP::RH_W];  // pixel columns touching each window column
+  int sIlo[BCP::RH_H], sIhi[BCP::RH_H];  // pixel rows touching each window row
+  float2 sV[BCP::VT];
+  Bounds sTB[BCP::VT];
+  float sRaw[BCP::RAW];
+  float sLum[BCP::LUMA];
+  double sOm[3][BCP::OM];
+  // dOmega/dtheta per half-res pixel: (cos 2phi, sin 2phi, p0, p1), (p2..p5), (p6..p9)
+  float4 sP[3][BCP::OM];
+  float sRh[BCP::RH];
+  float sGr[BMH][MW];    // dL/drho per pixel, this frame
+  float2 sGp[BMH][MW];   // dL/dp per pixel, this frame
+  double2 sHm[BMH][BCP::TX];
+  float sHr[BMH][BCP::RH_W];
+  double sAcc[BWAVES][6];
+  int sRed[8];
+  int sRh0[4];
+};
+
+__device__ __forceinline__ float pick3(const float (&a)[3], int c) { return c == 0 ? a[0] : (c == 1 ? a[1] : a[2]); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;  // lane 0 holds the sum, always added in the same order
+}
+
+__global__ __launch_bounds__(BTHREADS, 2) void k_merge_bwd(
+    const uint16_t* __restrict__ frames, const float* __restrict__ motion,
+    const float* __restrict__ rmin, const float* __restrict__ saved,
+    const float* __restrict__ grad_out, Geometry g, MergeConsts mc, BwdConsts bc,
+    double* __restrict__ part_theta, double* __restrict__ part_mo, float* __restrict__ part_rh) {
+  __shared__ BwdSmem sm;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tile_x = blockIdx.x, tile_y = blockIdx.y;
+  const int tile = tile_y * bc.tiles_x + tile_x;
+  const int C0 = tile_x * MW, R0 = tile_y * BMH;
+  const int ncol = min(MW, g.OW - C0), nrow = min(BMH, g.OH - R0);
+
+  // ---- per-tile geometry (as the forward) -------------------------------
+  const int C = C0 + lane;
+  const bool col_ok = lane < ncol;
+  const double X = out_pos(C, g.scale);
+  if (tid < MW) {
+    sm.sX[tid] = X;
+    sm.sTxCol[tid] = col_ok ? tile_of(X, g.T, g.TX) : 0;
+  }
+  for (int r = tid; r < BMH; r += BTHREADS) {
+    const double Y = out_pos(R0 + r, g.scale);
+    sm.sY[r] = Y;
+    sm.sTyRow[r] = r < nrow ? tile_of(Y, g.T, g.TY) : 0;
+  }
+  __syncthreads();
+  const int txA = sm.sTxCol[0], txB = sm.sTxCol[ncol - 1];
+  const int tyA = sm.sTyRow[0], tyB = sm.sTyRow[nrow - 1];
+  const int ntx = txB - txA + 1, nty = tyB - tyA + 1, ntiles = ntx * nty;
+  if (tid < ncol) {
+    const int t = sm.sTxCol[tid] - txA;
+    if (tid == 0 || sm.sTxCol[tid - 1] != sm.sTxCol[tid]) sm.sClo[t] = tid;
+    if (tid == ncol - 1 || sm.sTxCol[tid + 1] != sm.sTxCol[tid]) sm.sChi[t] = tid;
+  }
+  for (int r = tid; r < nrow; r += BTHREADS) {
+    const int t = sm.sTyRow[r] - tyA;
+    if (r == 0 || sm.sTyRow[r - 1] != sm.sTyRow[r]) sm.sRlo[t] = r;
+    if (r == nrow - 1 || sm.sTyRow[r + 1] != sm.sTyRow[r]) sm.sRhi[t] = r;
+  }
+  if (tid == 0) {
+    rh_range(C0, C0 + ncol - 1, g.scale, g.w, sm.sRh0[0], sm.sRh0[1]);
+    rh_range(R0, R0 + nrow - 1, g.scale, g.h, sm.sRh0[2], sm.sRh0[3]);
+  }
+  __syncthreads();
+  const int rhc0 = sm.sRh0[0], rhw = sm.sRh0[1] - sm.sRh0[0] + 1;
+  const int rhr0 = sm.sRh0[2], rhh = sm.sRh0[3] - sm.sRh0[2] + 1;
+  for (int r = tid; r < BMH; r += BTHREADS) {
+    const double hy = sm.sY[r] * 0.5 - 0.5;
+    const double fhy = floor(hy);
+    const int y0 = (int)fhy;
+    const int ya = clampi(y0, 0, g.h - 1) - rhr0, yb = clampi(y0 + 1, 0, g.h - 1) - rhr0;
+    RowInfo ri;
+    ri.ya = ya * rhw;
+    ri.yb = yb * rhw;
+    ri.fy = (float)(hy - fhy);
+    sm.sRow[r] = ri;
+    sm.sRya[r] = ya;
+    sm.sRyb[r] = yb;
+  }
+  int rxa, rxb;
+  float rfx;
+  {
+    const double hx = X * 0.5 - 0.5;
+    const double fhx = floor(hx);
+    rxa = clampi((int)fhx, 0, g.w - 1) - rhc0;
+    rxb = clampi((int)fhx + 1, 0, g.w - 1) - rhc0;
+    rfx = (float)(hx - fhx);
+  }
+  if (tid < MW) {
+    sm.sRxa[tid] = rxa;
+    sm.sRxb[tid] = rxb;
+    sm.sRfx[tid] = rfx;
+  }
+  __syncthreads();
+  // pixel columns (rows) whose R_hat corners include window column J (row I):
+  // the corners are monotonic in the pixel position.
+  if (tid < rhw) {
+    int lo = ncol, hi = -1;
+    for (int c = 0; c < ncol; ++c) {
+      if (sm.sRxa[c] <= tid && tid <= sm.sRxb[c]) {
+        lo = min(lo, c);
+        hi = c;
+      }
+    }
+    sm.sJlo[tid] = lo;
+    sm.sJhi[tid] = hi;
+  } else if (tid >= 64 && tid < 64 + rhh) {
+    const int I = tid - 64;
+    int lo = nrow, hi = -1;
+    for (int r = 0; r < nrow; ++r) {
+      if (sm.sRya[r] <= I && I <= sm.sRyb[r]) {
+        lo = min(lo, r);
+        hi = r;
+      }
+    }
+    sm.sIlo[I] = lo;
+    sm.sIhi[I] = hi;
+  }
+  const int txl = sm.sTxCol[lane] - txA;
+  const float vlim = (float)(max(g.W, g.H) + 16);
+
+  // ---- the forward's normaliser and dL/dC per pixel ----------------------
+  float gam[BPX][3], cval[BPX][3], mref[BPX][3];
+  {
+    const size_t plane = (size_t)g.OH * g.OW;
+#pragma unroll
+    for (int p = 0; p < BPX; ++p) {
+      const int r = wave * BPX + p;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        gam[p][c] = 0.f;
+        cval[p][c] = 0.f;
+        mref[p][c] = 0.f;
+      }
+      if (!col_ok || r >= nrow) continue;
+      const size_t o = (size_t)(R0 + r) * g.OW + C;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float num = saved[o + c * plane], den = saved[o + (3 + c) * plane];
+        cval[p][c] = num / den;  // raw units, as the forward divides
+        mref[p][c] = saved[o + (6 + c) * plane];
+        // dL/dC_raw = dL/dC * inv_range, over the denominator of eq. (1)
+        gam[p][c] = grad_out[o + c * plane] * mc.inv_range / den;
+      }
+    }
+  }
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+
+  for (int fi = 0; fi < g.n; ++fi) {
+    const int n = fi == 0 ? g.ref : (fi <= g.ref ? fi - 1 : fi);
+    const bool is_ref = n == g.ref;
+    const uint16_t* f = frames + (size_t)n * g.H * g.W;
+    __syncthreads();
+    for (int k = tid; k < ntiles; k += BTHREADS) {
+      float2 v = make_float2(0.f, 0.f);
+      if (!is_ref) {
+        const int ky = k / ntx;
+        const float* p = motion + (((size_t)n * g.TY + tyA + ky) * g.TX + txA + (k - ky * ntx)) * 2;
+        v = make_float2(fminf(fmaxf(p[0], -vlim), vlim), fminf(fmaxf(p[1], -vlim), vlim));
+      }
+      sm.sV[k] = v;
+    }
+    if (tid < 8) sm.sRed[tid] = 0x7fffffff;
+    if (!is_ref) {
+      const float* rm = rmin + (size_t)n * g.h * g.w;
+      const float inv = 1.f / (float)rhw;
+      for (int k = tid; k < rhw * rhh; k += BTHREADS) {
+        const int r = split_row(k, inv);
+        sm.sRh[k] = rm[(size_t)(rhr0 + r) * g.w + rhc0 + k - r * rhw];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < BPX; ++p) {
+      sm.sGr[wave * BPX + p][lane] = 0.f;
+      sm.sGp[wave * BPX + p][lane] = make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    for (int k = tid; k < ntiles; k += BTHREADS) {
+      const int ky = k / ntx, kx = k - ky * ntx;
+      const float2 v = sm.sV[k];
+      const double pxa = sm.sX[sm.sClo[kx]] + (double)v.x, pxb = sm.sX[sm.sChi[kx]] + (double)v.x;
+      const double pya = sm.sY[sm.sRlo[ky]] + (double)v.y, pyb = sm.sY[sm.sRhi[ky]] + (double)v.y;
+      Bounds b;
+      b.jc0 = (int)floor(pxa);
+      b.jc1 = (int)floor(pxb);
+      b.ic0 = (int)floor(pya);
+      b.ic1 = (int)floor(pyb);
+      b.hj0 = (int)floor(pxa * 0.5 - 0.5);
+      b.hj1 = (int)floor(pxb * 0.5 - 0.5);
+      b.hi0 = (int)floor(pya * 0.5 - 0.5);
+      b.hi1 = (int)floor(pyb * 0.5 - 0.5);
+      sm.sTB[k] = b;
+      atomicMin(&sm.sRed[0], b.jc0); atomicMin(&sm.sRed[1], -b.jc1);
+      atomicMin(&sm.sRed[2], b.ic0); atomicMin(&sm.sRed[3], -b.ic1);
+      atomicMin(&sm.sRed[4], b.hj0); atomicMin(&sm.sRed[5], -b.hj1);
+      atomicMin(&sm.sRed[6], b.hi0); atomicMin(&sm.sRed[7], -b.hi1);
+    }
+    __syncthreads();
+
+    bool whole = true;
+    int seg = 0;
+    while (true) {
+      Bounds bd;
+      if (whole) {
+        bd.jc0 = sm.sRed[0]; bd.jc1 = -sm.sRed[1]; bd.ic0 = sm.sRed[2]; bd.ic1 = -sm.sRed[3];
+        bd.hj0 = sm.sRed[4]; bd.hj1 = -sm.sRed[5]; bd.hi0 = sm.sRed[6]; bd.hi1 = -sm.sRed[7];
+      } else {
+        bd = sm.sTB[seg];
+      }
+      const int sty = whole ? -1 : seg / ntx, stx = whole ? -1 : seg % ntx;
+      const int oc0 = bd.hj0, ow = bd.hj1 - bd.hj0 + 2;
+      const int or0 = bd.hi0, oh = bd.hi1 - bd.hi0 + 2;
+      const int lc0 = max(clampi(bd.hj0, 0, g.w - 1) - 1, 0);
+      const int lc1 = min(clampi(bd.hj1 + 1, 0, g.w - 1) + 1, g.w - 1);
+      const int lr0 = max(clampi(bd.hi0, 0, g.h - 1) - 1, 0);
+      const int lr1 = min(clampi(bd.hi1 + 1, 0, g.h - 1) + 1, g.h - 1);
+      const int rc0 = min(2 * lc0, bd.jc0 - 1), rc1 = max(2 * lc1 + 1, bd.jc1 + 1);
+      const int rr0 = min(2 * lr0, bd.ic0 - 1), rr1 = max(2 * lr1 + 1, bd.ic1 + 1);
+      const int lw = lc1 - lc0 + 1, lh = lr1 - lr0 + 1;
+      const int rw = rc1 - rc0 + 1, rh = rr1 - rr0 + 1;
+      if (whole && (ow * oh > BCP::OM || lw * lh > BCP::LUMA || rw * rh > BCP::RAW)) {
+        whole = false;
+        seg = 0;
+        continue;
+      }
+      {
+        const float inv = 1.f / (float)rw;
+        for (int k = tid; k < rw * rh; k += BTHREADS) {
+          const int r = split_row(k, inv), c = k - r * rw;
+          const int gr = rr0 + r, gc = rc0 + c;
+          sm.sRaw[k] = (gr >= 0 && gr < g.H && gc >= 0 && gc < g.W) ? (float)f[(size_t)gr * g.W + gc] : 0.f;
+        }
+      }
+      __syncthreads();
+      {
+        const float inv = 1.f / (float)lw;
+        for (int k = tid; k < lw * lh; k += BTHREADS) {
+          const int r = split_row(k, inv), c = k - r * lw;
+          const int o = (2 * (lr0 + r) - rr0) * rw + 2 * (lc0 + c) - rc0;
+          sm.sLum[k] = (sm.sRaw[o] + sm.sRaw[o + 1]) + (sm.sRaw[o + rw] + sm.sRaw[o + rw + 1]);
+        }
+      }
+      __syncthreads();
+      {
+        const float inv = 1.f / (float)ow;
+        for (int k = tid; k < ow * oh; k += BTHREADS) {
+          const int r = split_row(k, inv), c = k - r * ow;
+          const int I = clampi(or0 + r, 0, g.h - 1), J = clampi(oc0 + c, 0, g.w - 1);
+          float l[3][3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const int row = (clampi(I + a - 1, 0, g.h - 1) - lr0) * lw;
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb) l[a][bb] = sm.sLum[row + clampi(J + bb - 1, 0, g.w - 1) - lc0];
+          }
+          double oxx, oxy, oyy;
+          OmegaParts pt;
+          omega_parts_from_quads(l, mc.om, oxx, oxy, oyy, pt);
+          sm.sOm[0][k] = oxx;
+          sm.sOm[1][k] = oxy;
+          sm.sOm[2][k] = oyy;
+          // sigma_1,2 = k1s, k2s (k1 = sigma_1^2): per unit dL/dk1, dL/dk2 the
+          // derivatives of sigma_1,2 in every scalar, each times 2 sigma.
+          const double D = pt.D, A = pt.A, invA = recip64(A);
+          const double s1 = 2.0 * pt.k1s, s2 = 2.0 * pt.k2s;
+          const double f1 = pt.d_free ? s1 * (bc.kn - bc.kst * A) : 0.0;
+          const double f2 = pt.d_free ? s2 * (bc.kn - invA / bc.ksh) : 0.0;
+          const double sl = pt.sqrt_l1 * bc.sl;
+          sm.sP[0][k] = make_float4((float)(pt.gx2 - pt.gy2), (float)(2.0 * pt.gxy), (float)(s1 * pt.k1s),
+                                    (float)(s2 * pt.k2s));
+          sm.sP[1][k] = make_float4((float)(s1 * D), (float)(s2 * D), (float)(s1 * (1.0 - D) * A),
+                                    (float)(s2 * (1.0 - D) * invA));
+          sm.sP[2][k] = make_float4((float)f1, (float)f2, (float)(f1 * sl), (float)(f2 * sl));
+        }
+      }
+      __syncthreads();
+
+      if (col_ok) {
+#pragma unroll
+        for (int p = 0; p < BPX; ++p) {
+          const int r = wave * BPX + p;
+          if (r >= nrow) continue;
+          const int tyl = sm.sTyRow[r] - tyA;
+          if (!whole && (tyl != sty || txl != stx)) continue;
+          float rho = 1.f;
+          if (!is_ref) {
+            const RowInfo ri = sm.sRow[r];
+            const float top = sm.sRh[ri.ya + rxa] + rfx * (sm.sRh[ri.ya + rxb] - sm.sRh[ri.ya + rxa]);
+            const float bot = sm.sRh[ri.yb + rxa] + rfx * (sm.sRh[ri.yb + rxb] - sm.sRh[ri.yb + rxa]);
+            rho = top + ri.fy * (bot - top);
+            if (!(rho > 0.f)) continue;
+          }
+          const float2 v = sm.sV[tyl * ntx + txl];
+          const double px = X + (double)v.x, py = sm.sY[r] + (double)v.y;
+          const double fjc = floor(px), fic = floor(py);
+          const double frx = px - fjc, fry = py - fic;
+          const int jc = (int)fjc, ic = (int)fic;
+          const double hx = px * 0.5 - 0.5, hy = py * 0.5 - 0.5;
+          const double fhj = floor(hx), fhi = floor(hy);
+          const double fx = hx - fhj, fy = hy - fhi;
+          const int ob = ((int)fhi - or0) * ow + ((int)fhj - oc0);
+          double O[3];
+          float dOx[3], dOy[3];  // dOmega_bar / d(hx, hy)
+#pragma unroll
+          for (int e = 0; e < 3; ++e) {
+            const double o00 = sm.sOm[e][ob], o01 = sm.sOm[e][ob + 1];
+            const double o10 = sm.sOm[e][ob + ow], o11 = sm.sOm[e][ob + ow + 1];
+            const double top = fma(fx, o01 - o00, o00);
+            const double bot = fma(fx, o11 - o10, o10);
+            O[e] = fma(fy, bot - top, top);
+            dOx[e] = (float)fma(fy, (o11 - o10) - (o01 - o00), o01 - o00);
+            dOy[e] = (float)(bot - top);
+          }
+          const double idet = recip64(O[0] * O[2] - O[1] * O[1]);
+          const double sc = NEG_HALF_LOG2E * idet;
+          const double qa = O[2] * sc, qb2 = -2.0 * O[1] * sc, qc = O[0] * sc;
+          double dx[3], dy[3];
+          float dxf[3], dyf[3];  // offsets of in-frame samples, 0 elsewhere
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            dx[j] = ((double)j - 0.5) - frx;
+            dy[j] = ((double)j - 0.5) - fry;
+            const int qj = jc + j - 1, qi = ic + j - 1;
+            const bool okx = qj >= 0 && qj < g.W, oky = qi >= 0 && qi < g.H;
+            dxf[j] = okx ? (float)dx[j] : 0.f;
+            dyf[j] = oky ? (float)dy[j] : 0.f;
+            if (!okx) dx[j] = FAR_X;
+            if (!oky) dy[j] = FAR_Y;
+          }
+          double E[3][3];
+          {
+            double ax[3], cy[3], by[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              ax[j] = qa * (dx[j] * dx[j]);
+              cy[j] = qc * (dy[j] * dy[j]);
+              by[j] = qb2 * dy[j];
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int j = 0; j < 3; ++j) E[i][j] = fma(by[i], dx[j], ax[j] + cy[i]);
+          }
+          // channel of each colour group: centre (0), left/right (1), up/down (2), corners (3)
+          const int pr = ic & 1, pc = jc & 1;
+          const int c0 = colour_of(mc.col4, pr * 2 + pc);
+          const int c1 = colour_of(mc.col4, pr * 2 + (pc ^ 1));
+          const bool isG = c0 == 1;
+          const int chX = ((isG ? c1 : c0) == 0) ? 0 : 2, chY = 2 - chX;
+          const int chg[4] = {isG ? 1 : chX, isG ? chX : 1, isG ? chY : 1, isG ? 1 : chY};
+          float Mg[4], Gg[4], Cg[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            Mg[q] = pick3(mref[p], chg[q]);
+            Gg[q] = pick3(gam[p], chg[q]);
+            Cg[q] = pick3(cval[p], chg[q]);
+          }
+          const int vb = (ic - 1 - rr0) * rw + (jc - 1 - rc0);
+          float a[3][3];
+          float grho = 0.f;
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              const int q = (i == 1 && j == 1) ? 0 : (i == 1 ? 1 : (j == 1 ? 2 : 3));
+              const float w = __builtin_amdgcn_exp2f((float)(E[i][j] - (double)Mg[q]));
+              const float bq = Gg[q] * w * (sm.sRaw[vb + i * rw + j] - Cg[q]);  // dL/drho part
+              grho += bq;
+              a[i][j] = rho * bq;  // dL/de
+            }
+          // S = sum a d d^T, t = sum a d (offsets separate into columns and rows)
+          float Acol[3], Arow[3], Sxy = 0.f;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) Acol[j] = a[0][j] + a[1][j] + a[2][j];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            Arow[i] = a[i][0] + a[i][1] + a[i][2];
+            Sxy = fmaf(dyf[i], fmaf(a[i][0], dxf[0], fmaf(a[i][1], dxf[1], a[i][2] * dxf[2])), Sxy);
+          }
+          float Sxx = 0.f, Syy = 0.f, tx = 0.f, ty = 0.f;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            tx = fmaf(Acol[j], dxf[j], tx);
+            Sxx = fmaf(Acol[j] * dxf[j], dxf[j], Sxx);
+            ty = fmaf(Arow[j], dyf[j], ty);
+            Syy = fmaf(Arow[j] * dyf[j], dyf[j], Syy);
+          }
+          const float ia = (float)(O[2] * idet), ib = (float)(-O[1] * idet), ic_ = (float)(O[0] * idet);
+          // dL/dOmega_bar = 1/2 Omega^-1 S Omega^-1 (Oxy on both off-diagonal entries)
+          const float K11 = fmaf(ia, Sxx, ib * Sxy), K12 = fmaf(ia, Sxy, ib * Syy);
+          const float K21 = fmaf(ib, Sxx, ic_ * Sxy), K22 = fmaf(ib, Sxy, ic_ * Syy);
+          const float Gxx = 0.5f * fmaf(K11, ia, K12 * ib);
+          const float Gxy = fmaf(K11, ib, K12 * ic_);
+          const float Gyy = 0.5f * fmaf(K21, ib, K22 * ic_);
+          // dL/dp: the offsets, and Omega sampled at p / 2 - 1/2
+          const float gpx = fmaf(ia, tx, ib * ty) + 0.5f * fmaf(Gxx, dOx[0], fmaf(Gxy, dOx[1], Gyy * dOx[2]));
+          const float gpy = fmaf(ib, tx, ic_ * ty) + 0.5f * fmaf(Gxx, dOy[0], fmaf(Gxy, dOy[1], Gyy * dOy[2]));
+          // contract with dOmega/dtheta at the four corners
+          const float T = 0.5f * (Gxx + Gyy), U = 0.5f * (Gyy - Gxx), V = -0.5f * Gxy;
+          const float ffx = (float)fx, ffy = (float)fy;
+          const float wq[4] = {(1.f - ffx) * (1.f - ffy), ffx * (1.f - ffy), (1.f - ffx) * ffy, ffx * ffy};
+          const int cq[4] = {ob, ob + 1, ob + ow, ob + ow + 1};
+          float s6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float4 P0 = sm.sP[0][cq[q]], P1 = sm.sP[1][cq[q]], P2 = sm.sP[2][cq[q]];
+            const float qq = fmaf(P0.x, U, P0.y * V);
+            const float k1 = wq[q] * (T + qq), k2 = wq[q] * (T - qq);  // dL/dk1, dL/dk2 at the corner
+            s6[0] = fmaf(k1, P0.z, fmaf(k2, P0.w, s6[0]));
+            s6[1] = fmaf(k1, P1.x, fmaf(k2, P1.y, s6[1]));
+            s6[2] = fmaf(k1, P2.x, fmaf(k2, P2.y, s6[2]));
+            s6[3] = fmaf(k1, P2.z, fmaf(k2, P2.w, s6[3]));
+            s6[4] = fmaf(k1, P1.z, s6[4]);
+            s6[5] = fmaf(k2, P1.w, s6[5]);
+          }
+#pragma unroll
+          for (int e = 0; e < 6; ++e) acc[e] += (double)s6[e];
+          if (!is_ref) {
+            sm.sGr[r][lane] = grho;
+            sm.sGp[r][lane] = make_float2(gpx, gpy);
+          }
+        }
+      }
+      if (whole || ++seg >= ntiles) break;
+      __syncthreads();
+    }
+
+    if (!is_ref) {
+      __syncthreads();
+      // rows x (alignment tile columns, R_hat window columns)
+      const int per_row = ntx + rhw;
+      for (int k = tid; k < nrow * per_row; k += BTHREADS) {
+        const int r = k / per_row, q = k - r * per_row;
+        if (q < ntx) {
+          double sx = 0.0, sy = 0.0;
+          for (int c = sm.sClo[q]; c <= sm.sChi[q]; ++c) {
+            const float2 gp = sm.sGp[r][c];
+            sx += (double)gp.x;
+            sy += (double)gp.y;
+          }
+          sm.sHm[r][q] = make_double2(sx, sy);
+        } else {
+          const int J = q - ntx;
+          float s = 0.f;
+          for (int c = sm.sJlo[J]; c <= sm.sJhi[J]; ++c) {
+            const float wgt = (sm.sRxa[c] == J ? 1.f - sm.sRfx[c] : 0.f) + (sm.sRxb[c] == J ? sm.sRfx[c] : 0.f);
+            s = fmaf(wgt, sm.sGr[r][c], s);
+          }
+          sm.sHr[r][J] = s;
+        }
+      }
+      __syncthreads();
+      const int nwin = rhh * rhw;
+      for (int k = tid; k < ntiles + nwin; k += BTHREADS) {
+        if (k < ntiles) {
+          const int ky = k / ntx, kx = k - ky * ntx;
+          double sx = 0.0, sy = 0.0;
+          for (int r = sm.sRlo[ky]; r <= sm.sRhi[ky]; ++r) {
+            sx += sm.sHm[r][kx].x;
+            sy += sm.sHm[r][kx].y;
+          }
+          double* dst = part_mo + (((size_t)tile * g.n + n) * kBwdVT + k) * 2;
+          dst[0] = sx;
+          dst[1] = sy;
+        } else {
+          const int q = k - ntiles;
+          const int I = q / rhw, J = q - I * rhw;
+          float s = 0.f;
+          for (int r = sm.sIlo[I]; r <= sm.sIhi[I]; ++r) {
+            const float fyr = sm.sRow[r].fy;
+            const float wgt = (sm.sRya[r] == I ? 1.f - fyr : 0.f) + (sm.sRyb[r] == I ? fyr : 0.f);
+            s = fmaf(wgt, sm.sHr[r][J], s);
+          }
+          part_rh[((size_t)n * bc.n_tiles + tile) * kBwdRH + q] = s;
+        }
+      }
+    }
+  }
+
+  // ---- the six covariance-scalar sums of the workgroup ------------------
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const double v = wave_sum(acc[e]);
+    if (lane == 0) sm.sAcc[wave][e] = v;
+  }
+  __syncthreads();
+  if (tid < 6) {
+    double s = 0.0;
+    for (int w = 0; w < BWAVES; ++w) s += sm.sAcc[w][tid];
+    part_theta[(size_t)tile * 6 + tid] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// robustness adjoint
+// ---------------------------------------------------------------------------
+constexpr int RB = 8;  // half-res pixels per block edge
+
+// dL/dR_hat at base half-res pixel (I, J) of frame n: the sum of the window
+// partials of every output tile whose R_hat window holds it, in tile order.
+__device__ float gather_rh(const float* __restrict__ part_rh, const Geometry& g, const BwdConsts& bc,
+                           int n, int I, int J) {
+  float s = 0.f;
+  const int ty0 = (int)((2.0 * I + 1.0) * g.scale / BMH), tx0 = (int)((2.0 * J + 1.0) * g.scale / MW);
+  for (int oty = max(ty0 - 2, 0); oty <= min(ty0 + 2, bc.tiles_y - 1); ++oty) {
+    const int R0 = oty * BMH, nrow = min(BMH, g.OH - R0);
+    int r0, r1;
+    rh_range(R0, R0 + nrow - 1, g.scale, g.h, r0, r1);
+    if (I < r0 || I > r1) continue;
+    for (int otx = max(tx0 - 2, 0); otx <= min(tx0 + 2, bc.tiles_x - 1); ++otx) {
+      const int C0 = otx * MW, ncol = min(MW, g.OW - C0);
+      int c0, c1;
+      rh_range(C0, C0 + ncol - 1, g.scale, g.w, c0, c1);
+      if (J < c0 || J > c1) continue;
+      s += part_rh[((size_t)n * bc.n_tiles + oty * bc.tiles_x + otx) * kBwdRH + (I - r0) * (c1 - c0 + 1) +
+                   (J - c0)];
+    }
+  }
+  return s;
+}
+
+// Guide colour (R, mean of the greens, B) of half-res pixel (I, J), raw units.
+__device__ __forceinline__ void guide_px(const uint16_t* f, const Geometry& g, int I, int J, float (&c)[3]) {
+  const uint32_t top = *(const uint32_t*)(f + (size_t)(2 * I) * g.W + 2 * J);
+  const uint32_t bot = *(const uint32_t*)(f + (size_t)(2 * I + 1) * g.W + 2 * J);
+  const int q[4] = {(int)(top & 0xffff), (int)(top >> 16), (int)(bot & 0xffff), (int)(bot >> 16)};
+  c[0] = (float)q[g.red_pos];
+  c[1] = (float)(q[g.green_pos[0]] + q[g.green_pos[1]]) * 0.5f;
+  c[2] = (float)q[g.blue_pos];
+}
+
+// 3x3 box mean of the guide around (I, J), edge-clamped; optionally the
+// population variance too.
+__device__ __forceinline__ void box3(const uint16_t* f, const Geometry& g, int I, int J, float (&mu)[3],
+                                     float (*var)[3]) {
+  float v[9][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) guide_px(f, g, clampi(I + a - 1, 0, g.h - 1), clampi(J + b - 1, 0, g.w - 1), v[a * 3 + b]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s += v[q][c];
+    mu[c] = s * (1.f / 9.f);
+    if (var) {
+      float sv = 0.f;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) sv = fmaf(v[q][c] - mu[c], v[q][c] - mu[c], sv);
+      (*var)[c] = sv * (1.f / 9.f);
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_robust_bwd(const uint16_t* __restrict__ frames,
+                                                   const float* __restrict__ motion,
+                                                   const float* __restrict__ rmap,
+                                                   const float* __restrict__ part_rh, Geometry g,
+                                                   RobustConsts rc, PriorConsts pc, BwdConsts bc,
+                                                   double* __restrict__ part_rob) {
+  const int tx = blockIdx.x, ty = blockIdx.y, n = blockIdx.z;
+  const int tid = threadIdx.x;
+  double* dst = part_rob + (((size_t)n * g.TY + ty) * g.TX + tx) * 5;
+  if (n == g.ref) {
+    if (tid < 5) dst[tid] = 0.0;
+    return;
+  }
+  __shared__ float sR[RB + 8][RB + 8];
+  __shared__ float sG[RB + 4][RB + 4];
+  __shared__ int sA[RB + 4][RB + 4];
+  const size_t plane = (size_t)g.h * g.w;
+  const float* R = rmap + (size_t)n * plane;
+  const uint16_t* fref = frames + (size_t)g.ref * g.H * g.W;
+  const uint16_t* fn = frames + (size_t)n * g.H * g.W;
+  const bool moving = prior_moving(motion, g, pc.m_th, n, ty, tx);
+  const float s_used = moving ? pc.s1 : pc.s2;
+  const float vlim = (float)(max(g.W, g.H) + 16);
+  const float* pv = motion + (((size_t)n * g.TY + ty) * g.TX + tx) * 2;
+  const float vx = fminf(fmaxf(pv[0], -vlim), vlim), vy = fminf(fmaxf(pv[1], -vlim), vlim);
+  const int half = g.T / 2;
+  const int i0 = ty * half, i1 = min(i0 + half, g.h), j0 = tx * half, j1 = min(j0 + half, g.w);
+  double gvx = 0.0, gvy = 0.0, gt = 0.0, gs = 0.0;
+  for (int bi0 = i0; bi0 < i1; bi0 += RB) {
+    for (int bj0 = j0; bj0 < j1; bj0 += RB) {
+      __syncthreads();
+      for (int k = tid; k < (RB + 8) * (RB + 8); k += 64) {
+        const int rr = k / (RB + 8), cc = k - rr * (RB + 8);
+        sR[rr][cc] = R[(size_t)clampi(bi0 - 4 + rr, 0, g.h - 1) * g.w + clampi(bj0 - 4 + cc, 0, g.w - 1)];
+      }
+      __syncthreads();
+      // dL/dR_hat of the cells whose 5x5 window can reach the block, and
+      // where it goes: the first minimum of the window in scan order.
+      for (int k = tid; k < (RB + 4) * (RB + 4); k += 64) {
+        const int r2 = k / (RB + 4), c2 = k - r2 * (RB + 4);
+        const int I = bi0 - 2 + r2, J = bj0 - 2 + c2;
+        float gr = 0.f;
+        int arg = -1;
+        if (I >= 0 && I < g.h && J >= 0 && J < g.w) gr = gather_rh(part_rh, g, bc, n, I, J);
+        if (gr != 0.f) {
+          float best = INFINITY;
+          for (int di = -2; di <= 2; ++di) {
+            const int ci = clampi(I + di, 0, g.h - 1);
+            for (int dj = -2; dj <= 2; ++dj) {
+              const int cj = clampi(J + dj, 0, g.w - 1);
+              const float v = sR[ci - (bi0 - 4)][cj - (bj0 - 4)];
+              if (v < best) {
+                best = v;
+                arg = ci * g.w + cj;
+              }
+            }
+          }
+        }
+        sG[r2][c2] = gr;
+        sA[r2][c2] = arg;
+      }
+      __syncthreads();
+      const int i = bi0 + tid / RB, j = bj0 + tid % RB;
+      if (i < i1 && j < j1) {
+        float gR = 0.f;
+        const int me = i * g.w + j;
+        for (int di = -2; di <= 2; ++di)
+          for (int dj = -2; dj <= 2; ++dj) {
+            const int r2 = i + di - (bi0 - 2), c2 = j + dj - (bj0 - 2);
+            if (sA[r2][c2] == me) gR += sG[r2][c2];
+          }
+        const float Rv = sR[i - bi0 + 4][j - bj0 + 4];
+        if (gR != 0.f && Rv > 0.f && Rv < 1.f) {  // unclamped R of eq. (5)
+          float mu_ref[3], var_ref[3];
+          box3(fref, g, i, j, mu_ref, &var_ref);
+          float den = 0.f;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            float var = fmaf(rc.a_r, fmaxf(mu_ref[c] - rc.black, 0.f), rc.b_r);
+            if (c == 1) var *= 0.5f;
+            den += fmaxf(var_ref[c], var);
+          }
+          // mu_w: frame n's box mean sampled bilinearly at (j, i) + v / 2
+          const double hx = (double)j + (double)vx * 0.5, hy = (double)i + (double)vy * 0.5;
+          const double fhx = floor(hx), fhy = floor(hy);
+          const float fx = (float)(hx - fhx), fy = (float)(hy - fhy);
+          const int xa = clampi((int)fhx, 0, g.w - 1), xb = clampi((int)fhx + 1, 0, g.w - 1);
+          const int ya = clampi((int)fhy, 0, g.h - 1), yb = clampi((int)fhy + 1, 0, g.h - 1);
+          float m00[3], m01[3], m10[3], m11[3];
+          box3(fn, g, ya, xa, m00, nullptr);
+          box3(fn, g, ya, xb, m01, nullptr);
+          box3(fn, g, yb, xa, m10, nullptr);
+          box3(fn, g, yb, xb, m11, nullptr);
+          float num = 0.f, dd[3], ddp[3], dmx[3], dmy[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const float top = fmaf(fx, m01[c] - m00[c], m00[c]), bot = fmaf(fx, m11[c] - m10[c], m10[c]);
+            const float mu_w = fmaf(fy, bot - top, top);
+            dmx[c] = fmaf(fy, (m11[c] - m10[c]) - (m01[c] - m00[c]), m01[c] - m00[c]);
+            dmy[c] = bot - top;
+            float var = fmaf(rc.a_r, fmaxf(mu_ref[c] - rc.black, 0.f), rc.b_r);
+            if (c == 1) var *= 0.5f;
+            const float dmd2 = var * (2.f / 9.f);
+            const float dms = mu_ref[c] - mu_w, dms2 = dms * dms;
+            const float q = 1.f / (dms2 + dmd2);
+            dd[c] = dms * dms2 * q;  // eq. (6) shrinkage
+            ddp[c] = dms2 * (dms2 + 3.f * dmd2) * q * q;
+            num = fmaf(dd[c], dd[c], num);
+          }
+          const float ex = __expf(-num / den);
+          gt -= (double)gR;
+          gs += (double)(gR * ex);
+          const float g_r = -gR * s_used * ex;
+          float gx = 0.f, gy = 0.f;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            // r = sum d^2 / den; d_ms = mu_ref - mu_w; mu_w sampled at u + v / 2
+            const float g_mu = -g_r * (2.f * dd[c] / den) * ddp[c];
+            gx = fmaf(g_mu, dmx[c], gx);
+            gy = fmaf(g_mu, dmy[c], gy);
+          }
+          gvx += 0.5 * (double)gx;
+          gvy += 0.5 * (double)gy;
+        }
+      }
+    }
+  }
+  gvx = wave_sum(gvx);
+  gvy = wave_sum(gvy);
+  gt = wave_sum(gt);
+  gs = wave_sum(gs);
+  if (tid == 0) {
+    dst[0] = gvx;
+    dst[1] = gvy;
+    dst[2] = gt;
+    dst[3] = moving ? 0.0 : gs;
+    dst[4] = moving ? gs : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fixed-order reductions
+// ---------------------------------------------------------------------------
+// First output row (column) whose alignment tile index is >= t.
+__device__ int first_out_with_tile(int t, int n_out, double scale, int T, int nt) {
+  int lo = 0, hi = n_out;  // answer in [lo, hi]
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (tile_of(out_pos(mid, scale), T, nt) >= t) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+__global__ void k_grad_motion(const double* __restrict__ part_mo, const double* __restrict__ part_rob,
+                              Geometry g, BwdConsts bc, float* __restrict__ grad_motion) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = g.TY * g.TX;
+  if (idx >= g.n * per) return;
+  const int n = idx / per, t = idx - n * per, ty = t / g.TX, tx = t - ty * g.TX;
+  float* out = grad_motion + (size_t)idx * 2;
+  if (n == g.ref) {
+    out[0] = 0.f;
+    out[1] = 0.f;
+    return;
+  }
+  const int rlo = first_out_with_tile(ty, g.OH, g.scale, g.T, g.TY);
+  const int rhi = first_out_with_tile(ty + 1, g.OH, g.scale, g.T, g.TY) - 1;
+  const int clo = first_out_with_tile(tx, g.OW, g.scale, g.T, g.TX);
+  const int chi = first_out_with_tile(tx + 1, g.OW, g.scale, g.T, g.TX) - 1;
+  double sx = 0.0, sy = 0.0;
+  if (rlo <= rhi && clo <= chi) {
+    for (int oty = rlo / BMH; oty <= rhi / BMH; ++oty) {
+      const int tyA = tile_of(out_pos(oty * BMH, g.scale), g.T, g.TY);
+      for (int otx = clo / MW; otx <= chi / MW; ++otx) {
+        const int C0 = otx * MW;
+        const int txA = tile_of(out_pos(C0, g.scale), g.T, g.TX);
+        const int txB = tile_of(out_pos(min(C0 + MW - 1, g.OW - 1), g.scale), g.T, g.TX);
+        const int k = (ty - tyA) * (txB - txA + 1) + (tx - txA);
+        const double* p = part_mo + (((size_t)(oty * bc.tiles_x + otx) * g.n + n) * kBwdVT + k) * 2;
+        sx += p[0];
+        sy += p[1];
+      }
+    }
+  }
+  const double* rob = part_rob + (size_t)idx * 5;
+  out[0] = (float)(sx + rob[0]);
+  out[1] = (float)(sy + rob[1]);
+}
+
+__global__ __launch_bounds__(256) void k_grad_tuning(const double* __restrict__ part_theta, int n_tiles,
+                                                     const double* __restrict__ part_rob, int n_rob,
+                                                     BwdConsts bc, float* __restrict__ grad_tuning) {
+  __shared__ double sS[4][9];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double a[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) a[e] = 0.0;
+  for (int t = tid; t < n_tiles; t += 256)
+#pragma unroll
+    for (int e = 0; e < 6; ++e) a[e] += part_theta[(size_t)t * 6 + e];
+  for (int t = tid; t < n_rob; t += 256) {
+    const double* r = part_rob + (size_t)t * 5;
+    a[6] += r[3];
+    a[7] += r[2];
+    a[8] += r[4];
+  }
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    const double v = wave_sum(a[e]);
+    if (lane == 0) sS[wave][e] = v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s[9];
+    for (int e = 0; e < 9; ++e) s[e] = ((sS[0][e] + sS[1][e]) + sS[2][e]) + sS[3][e];
+    // sigma_1,2 are proportional to k_detail; the other factors were left out of the sums
+    grad_tuning[0] = (float)(s[0] / bc.kd);
+    grad_tuning[1] = (float)(s[1] * bc.kd);
+    grad_tuning[2] = (float)(s[2] * bc.kd);
+    grad_tuning[3] = (float)(s[3] * bc.kd);
+    grad_tuning[4] = (float)(s[4] * bc.kd);
+    grad_tuning[5] = (float)(-s[5] * bc.kd / (bc.ksh * bc.ksh));
+    grad_tuning[6] = (float)s[6];
+    grad_tuning[7] = (float)s[7];
+    grad_tuning[8] = (float)s[8];
+  }
+}
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+size_t bwd_bytes(const Geometry& g, bool need_saved) {
+  const size_t tiles = (size_t)((g.OW + MW - 1) / MW) * ((g.OH + BMH - 1) / BMH);
+  const size_t plane = (size_t)g.h * g.w;
+  size_t b = align256(work_bytes(g));
+  b += align256(plane * g.n * sizeof(float));
+  if (need_saved) b += align256((size_t)9 * g.OH * g.OW * sizeof(float));
+  b += align256((size_t)g.n * tiles * kBwdRH * sizeof(float));
+  b += align256(tiles * g.n * kBwdVT * 2 * sizeof(double));
+  b += align256(tiles * 6 * sizeof(double));
+  b += align256((size_t)g.n * g.TY * g.TX * 5 * sizeof(double));
+  return b;
+}
+
+BwdWork bwd_carve(void* base, const Geometry& g, bool need_saved) {
+  const size_t tiles = (size_t)((g.OW + MW - 1) / MW) * ((g.OH + BMH - 1) / BMH);
+  const size_t plane = (size_t)g.h * g.w;
+  char* p = (char*)base;
+  BwdWork w;
+  w.fwd = work_carve(p, g);
+  p += align256(work_bytes(g));
+  w.rmap = (float*)p;
+  p += align256(plane * g.n * sizeof(float));
+  w.saved = nullptr;
+  if (need_saved) {
+    w.saved = (float*)p;
+    p += align256((size_t)9 * g.OH * g.OW * sizeof(float));
+  }
+  w.part_rh = (float*)p;
+  p += align256((size_t)g.n * tiles * kBwdRH * sizeof(float));
+  w.part_mo = (double*)p;
+  p += align256(tiles * g.n * kBwdVT * 2 * sizeof(double));
+  w.part_theta = (double*)p;
+  p += align256(tiles * 6 * sizeof(double));
+  w.part_rob = (double*)p;
+  return w;
+}
+
+hipError_t launch_merge_bwd(const Geometry& g, const MergeConsts& mc, const BwdConsts& bc,
+                            const uint16_t* frames, const float* motion, const float* rmin,
+                            const float* saved, const float* grad_out, const BwdWork& w,
+                            hipStream_t stream) {
+  const dim3 grid(bc.tiles_x, bc.tiles_y);
+  hipLaunchKernelGGL(k_merge_bwd, grid, dim3(BTHREADS), 0, stream, frames, motion, rmin, saved, grad_out,
+                     g, mc, bc, w.part_theta, w.part_mo, w.part_rh);
+  return hipGetLastError();
+}
+
+hipError_t launch_robust_bwd(const Geometry& g, const RobustConsts& rc, const PriorConsts& pc,
+                             const BwdConsts& bc, const uint16_t* frames, const float* motion,
+                             const BwdWork& w, hipStream_t stream) {
+  const dim3 grid(g.TX, g.TY, g.n);
+  hipLaunchKernelGGL(k_robust_bwd, grid, dim3(64), 0, stream, frames, motion, w.rmap, w.part_rh, g, rc, pc,
+                     bc, w.part_rob);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const Geometry& g, const BwdConsts& bc, const BwdWork& w,
+                              float* grad_tuning, float* grad_motion, hipStream_t stream) {
+  const int total = g.n * g.TY * g.TX;
+  hipLaunchKernelGGL(k_grad_motion, dim3((total + 255) / 256), dim3(256), 0, stream, w.part_mo, w.part_rob,
+                     g, bc, grad_motion);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grad_tuning, dim3(1), dim3(256), 0, stream, w.part_theta, bc.n_tiles, w.part_rob,
+                     total, bc, grad_tuning);
+  return hipGetLastError();
+}
+
+}  // namespace hmfsr

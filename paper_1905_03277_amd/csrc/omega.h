@@ -43,11 +43,20 @@ __device__ __forceinline__ double sqrt64(double x) {
   return x > 0.0 ? x * y : 0.0;
 }
 
+// What the adjoint needs of one pixel's kernel covariance besides Omega.
+struct OmegaParts {
+  double gx2, gy2, gxy;  // products of the unit gradient direction
+  double A, D;           // anisotropy and denoising weight (S.1), D clamped
+  double k1s, k2s;       // square roots of the edge / gradient variances
+  double sqrt_l1;        // sqrt(lambda1) of the integer tensor
+  bool d_free;           // D strictly inside (0, 1), i.e. not clamped
+};
+
 // l[a][b]: quad sums of the 3x3 half-res window around the pixel (edge-clamped),
 // as int or as float holding integers (differences stay exact below 2^24).
-template <typename Q>
-__device__ __forceinline__ void omega_from_quads(const Q (&l)[3][3], const OmegaConsts& c,
-                                                 double& oxx, double& oxy, double& oyy) {
+template <bool PARTS, typename Q>
+__device__ __forceinline__ void omega_core(const Q (&l)[3][3], const OmegaConsts& c, double& oxx,
+                                           double& oxy, double& oyy, OmegaParts* parts) {
   double txx = 0.0, txy = 0.0, tyy = 0.0;
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
@@ -80,8 +89,9 @@ __device__ __forceinline__ void omega_from_quads(const Q (&l)[3][3], const Omega
   const double gx2 = ex * ex * inv_n2, gy2 = ey * ey * inv_n2, gxy = ex * ey * inv_n2;
 
   const double A = tr > 0.0 ? 1.0 + sqrt64(2.0 * rad * recip64(tr)) : 1.0;
-  double D = 1.0 - sqrt64(0.5 * tr + rad) * c.inv_16_range_dtr + c.d_th;
-  D = D < 0.0 ? 0.0 : (D > 1.0 ? 1.0 : D);
+  const double sqrt_l1 = sqrt64(0.5 * tr + rad);
+  const double D_raw = 1.0 - sqrt_l1 * c.inv_16_range_dtr + c.d_th;
+  const double D = D_raw < 0.0 ? 0.0 : (D_raw > 1.0 ? 1.0 : D_raw);
   const double k1s = (1.0 - D) * (c.kd_st * A) + D * c.kd_dn;
   const double k2s = (1.0 - D) * (c.kd_sh * recip64(A)) + D * c.kd_dn;
   const double k1 = k1s * k1s, k2 = k2s * k2s;
@@ -89,6 +99,30 @@ __device__ __forceinline__ void omega_from_quads(const Q (&l)[3][3], const Omega
   oxx = k1 * gy2 + k2 * gx2;
   oxy = (k2 - k1) * gxy;
   oyy = k1 * gx2 + k2 * gy2;
+  if (PARTS) {
+    parts->gx2 = gx2;
+    parts->gy2 = gy2;
+    parts->gxy = gxy;
+    parts->A = A;
+    parts->D = D;
+    parts->k1s = k1s;
+    parts->k2s = k2s;
+    parts->sqrt_l1 = sqrt_l1;
+    parts->d_free = D_raw > 0.0 && D_raw < 1.0;
+  }
+}
+
+template <typename Q>
+__device__ __forceinline__ void omega_from_quads(const Q (&l)[3][3], const OmegaConsts& c,
+                                                 double& oxx, double& oxy, double& oyy) {
+  omega_core<false>(l, c, oxx, oxy, oyy, nullptr);
+}
+
+template <typename Q>
+__device__ __forceinline__ void omega_parts_from_quads(const Q (&l)[3][3], const OmegaConsts& c,
+                                                       double& oxx, double& oxy, double& oyy,
+                                                       OmegaParts& parts) {
+  omega_core<true>(l, c, oxx, oxy, oyy, &parts);
 }
 
 }  // namespace hmfsr

@@ -33,21 +33,95 @@ def _check_inputs(frames: torch.Tensor, motion: torch.Tensor, desc):
         raise ValueError("frames and motion must be on one device")
 
 
+def _check_out(t: torch.Tensor | None, shape, device, what):
+    if t is None:
+        return torch.empty(shape, dtype=torch.float32, device=device)
+    if tuple(t.shape) != tuple(shape) or t.dtype != torch.float32 or not t.is_contiguous() \
+            or t.device != device:
+        raise ValueError(f"{what} must be a contiguous float32 tensor of shape {tuple(shape)} on {device}")
+    return t
+
+
 def merge(frames: torch.Tensor, motion: torch.Tensor, desc, tuning,
-          out: torch.Tensor | None = None) -> torch.Tensor:
-    """Merge one burst; returns float32 [3][OH][OW] on the frames' device."""
+          out: torch.Tensor | None = None, saved: torch.Tensor | None = None) -> torch.Tensor:
+    """Merge one burst; returns float32 [3][OH][OW] on the frames' device.
+    ``saved`` (float32 [3][3][OH][OW]), if given, receives the normaliser the
+    adjoint can reuse."""
     _check_inputs(frames, motion, desc)
-    shape = (3, desc.out_height, desc.out_width)
-    if out is None:
-        out = torch.empty(shape, dtype=torch.float32, device=frames.device)
-    elif tuple(out.shape) != shape or out.dtype != torch.float32 or not out.is_contiguous() \
-            or out.device != frames.device:
-        raise ValueError("out must be a contiguous float32 tensor of shape [3][OH][OW]")
+    out = _check_out(out, (3, desc.out_height, desc.out_width), frames.device, "out")
+    if saved is not None:
+        _check_out(saved, (3, 3, desc.out_height, desc.out_width), frames.device, "saved")
     with torch.cuda.device(frames.device):
         binding.hmfsr_merge(binding.make_desc(desc), binding.make_tuning(tuning),
                             frames.data_ptr(), motion.data_ptr(), out.data_ptr(),
-                            _stream(frames.device))
+                            0 if saved is None else saved.data_ptr(), _stream(frames.device))
     return out
+
+
+def merge_backward(frames: torch.Tensor, motion: torch.Tensor, desc, tuning,
+                   grad_out: torch.Tensor, saved: torch.Tensor | None = None):
+    """Adjoint of ``merge`` for dL/dC = grad_out: returns (grad_tuning float32
+    [9] in ``binding.GRAD_NAMES`` order, grad_motion float32 [N][TY][TX][2]),
+    both on the frames' device."""
+    _check_inputs(frames, motion, desc)
+    dev = frames.device
+    shape = (3, desc.out_height, desc.out_width)
+    grad_out = grad_out.to(device=dev, dtype=torch.float32).contiguous()
+    if tuple(grad_out.shape) != shape:
+        raise ValueError(f"grad_out shape {tuple(grad_out.shape)} != {shape}")
+    if saved is not None:
+        _check_out(saved, (3,) + shape, dev, "saved")
+    g_tun = torch.empty(9, dtype=torch.float32, device=dev)
+    g_mot = torch.empty_like(motion)
+    with torch.cuda.device(dev):
+        binding.hmfsr_merge_backward(binding.make_desc(desc), binding.make_tuning(tuning),
+                                     frames.data_ptr(), motion.data_ptr(),
+                                     0 if saved is None else saved.data_ptr(), grad_out.data_ptr(),
+                                     g_tun.data_ptr(), g_mot.data_ptr(), _stream(dev))
+    return g_tun, g_mot
+
+
+TUNING_FIELDS = binding.GRAD_NAMES + ("m_th",)
+
+
+class _TuningView:
+    """Attribute view of a 10-vector of tuning values (hmfsr_tuning order)."""
+
+    def __init__(self, values):
+        for name, v in zip(TUNING_FIELDS, values):
+            setattr(self, name, float(v))
+
+
+class HmfsrMerge(torch.autograd.Function):
+    """C = merge(frames, motion, tuning) with gradients for motion and the
+    tuning vector [k_detail, k_denoise, d_th, d_tr, k_stretch, k_shrink, s, t,
+    s_motion, m_th] (m_th gets zero). The forward keeps the normaliser of
+    eq. (1) so that the backward needs no second forward."""
+
+    @staticmethod
+    def forward(ctx, frames, motion, tuning_vec, desc):
+        tun = _TuningView(tuning_vec.detach().to("cpu", torch.float32).tolist())
+        motion_c = motion.detach().contiguous()
+        saved = torch.empty((3, 3, desc.out_height, desc.out_width), dtype=torch.float32,
+                            device=frames.device)
+        out = merge(frames, motion_c, desc, tun, saved=saved)
+        ctx.save_for_backward(frames, motion_c, saved)
+        ctx.desc, ctx.tun = desc, tun
+        ctx.tuning_meta = (tuning_vec.device, tuning_vec.dtype)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        frames, motion, saved = ctx.saved_tensors
+        g_tun, g_mot = merge_backward(frames, motion, ctx.desc, ctx.tun, grad_out, saved=saved)
+        dev, dt = ctx.tuning_meta
+        g_vec = torch.cat([g_tun, g_tun.new_zeros(1)]).to(device=dev, dtype=dt)
+        return None, g_mot, g_vec, None
+
+
+def merge_autograd(frames, motion, tuning_vec, desc):
+    """Differentiable merge (see ``HmfsrMerge``)."""
+    return HmfsrMerge.apply(frames, motion, tuning_vec, desc)
 
 
 def merge_maps(frames: torch.Tensor, motion: torch.Tensor, desc, tuning) -> dict:

@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version_and_strerror():
-    assert binding.hmfsr_version() == 100
+    assert binding.hmfsr_version() == 110
     assert "INVALID" in binding.strerror(binding.HMFSR_E_INVALID)
     assert "unknown" in binding.strerror(-99)
 
@@ -39,7 +39,7 @@ def _good():
 def _call(desc, tun, ptr=1):
     # Invalid descriptors are rejected on the host, before any HIP call; the
     # dummy pointers are never dereferenced.
-    return binding.lib().hmfsr_merge(ctypes.byref(desc), ctypes.byref(tun), ptr, ptr, ptr, None)
+    return binding.lib().hmfsr_merge(ctypes.byref(desc), ctypes.byref(tun), ptr, ptr, ptr, None, None)
 
 
 @pytest.mark.parametrize("field,value", [
@@ -73,11 +73,35 @@ def test_unknown_cfa_unsupported():
 def test_null_pointers_rejected():
     desc, tun = _good()
     assert _call(desc, tun, ptr=None) == binding.HMFSR_E_INVALID
-    assert binding.lib().hmfsr_merge(None, ctypes.byref(tun), 1, 1, 1, None) == binding.HMFSR_E_INVALID
+    assert binding.lib().hmfsr_merge(None, ctypes.byref(tun), 1, 1, 1, None, None) == binding.HMFSR_E_INVALID
 
 
 def test_binding_raises():
     desc, tun = _good()
     desc.n_frames = 0
     with pytest.raises(binding.HmfsrError):
-        binding.hmfsr_merge(desc, tun, 1, 1, 1, 0)
+        binding.hmfsr_merge(desc, tun, 1, 1, 1)
+
+
+def _call_bwd(desc, tun, ptr=4, grad=4):
+    return binding.lib().hmfsr_merge_backward(ctypes.byref(desc), ctypes.byref(tun), ptr, ptr, None,
+                                              ptr, grad, grad, None)
+
+
+@pytest.mark.parametrize("field,value", [("n_frames", 0), ("scale", 0.9), ("tile_size", 6)])
+def test_backward_rejects_invalid_descriptor(field, value):
+    desc, tun = _good()
+    setattr(desc, field, value)
+    assert _call_bwd(desc, tun) == binding.HMFSR_E_INVALID
+
+
+def test_backward_rejects_invalid_tuning_and_pointers():
+    desc, tun = _good()
+    tun.k_shrink = 0.0
+    assert _call_bwd(desc, tun) == binding.HMFSR_E_INVALID
+    desc, tun = _good()
+    assert _call_bwd(desc, tun, grad=None) == binding.HMFSR_E_INVALID
+    assert _call_bwd(desc, tun, ptr=None) == binding.HMFSR_E_INVALID
+    assert _call_bwd(desc, tun, grad=6) == binding.HMFSR_E_INVALID   # misaligned
+    with pytest.raises(binding.HmfsrError):
+        binding.hmfsr_merge_backward(desc, tun, 4, 4, 0, 4, 0, 4)
