@@ -6,6 +6,12 @@ resident in HBM. Prints one JSON line with input-Bayer MP/s, the dominant
 kernel's roofline position and the FP64 oracle's CPU rate on a bounded sample.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+                    [--no-batch] [--no-grad]
+
+Two more legs follow the headline line's measurement and are reported inside
+it: the 64-burst batched workload (one graph replay vs per-burst launches) and
+the differentiation workload (16 bursts of 8 x 768 x 1024 at scale 2, forward
+plus adjoint).
 """
 import argparse
 import json
@@ -143,6 +149,65 @@ def bench_batch(dev, reps: int = 3) -> dict:
             "tuned_shapes": {f"{k[0]}/{k[1]}": v for k, v in tuned.items()}}
 
 
+def bench_grad(dev, reps: int = 3) -> dict:
+    """The differentiation workload: 16 bursts of 8 x 768 x 1024 RGGB at scale 2.
+    One pass = for every burst, the forward merge (keeping the normaliser of
+    eq. 1), the L2 loss gradient against the synthetic ground-truth scene and
+    the adjoint (tuning and motion gradients)."""
+    import torch
+    from paper_1905_03277_amd import binding, synth, torch_ops
+
+    print("[bench] generating the 16-burst differentiation workload", file=sys.stderr, flush=True)
+    bursts = [synth.make_config(5, burst=i, device=dev) for i in range(16)]
+    d0 = bursts[0].desc
+    outs = [torch.empty((3, b.desc.out_height, b.desc.out_width), dtype=torch.float32, device=dev)
+            for b in bursts]
+    saveds = [torch_ops.saved_buffer(b.desc, dev)
+              for b in bursts]
+    grads = []
+
+    def fwd():
+        for b, o, sv in zip(bursts, outs, saveds):
+            torch_ops.merge(b.frames, b.motion, b.desc, b.tuning, out=o, saved=sv)
+
+    def fwd_bwd():
+        grads.clear()
+        for b, o, sv in zip(bursts, outs, saveds):
+            torch_ops.merge(b.frames, b.motion, b.desc, b.tuning, out=o, saved=sv)
+            g = (o - b.gt).mul_(2.0 / o.numel())          # d/dC of mean((C - GT)^2)
+            grads.append(torch_ops.merge_backward(b.frames, b.motion, b.desc, b.tuning, g, saved=sv))
+
+    stream = torch.cuda.current_stream()
+
+    def timeit(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    print("[bench] differentiation: forward, forward + adjoint", file=sys.stderr, flush=True)
+    ms_f = timeit(fwd)
+    ms_fb = timeit(fwd_bwd)
+    binding.hmfsr_profile_begin()
+    fwd_bwd()
+    stages = binding.hmfsr_profile_end()
+    loss = float(sum(torch.mean((o - b.gt) ** 2).item() for o, b in zip(outs, bursts)) / len(bursts))
+    g_t = torch.stack([g[0] for g in grads]).sum(0).cpu().tolist()
+    in_mp = sum(b.desc.n_frames * b.desc.height * b.desc.width for b in bursts) / 1e6
+    return {"workload": f"16 bursts, {d0.n_frames} frames {d0.width}x{d0.height} RGGB, scale {d0.scale}, "
+                        "L2 loss against the synthetic scene",
+            "input_MP": round(in_mp, 1), "ms_fwd": round(ms_f, 3), "ms_fwd_bwd": round(ms_fb, 3),
+            "MPs_fwd": round(in_mp / (ms_f / 1e3), 1), "MPs_fwd_bwd": round(in_mp / (ms_fb / 1e3), 1),
+            "kernels_ms_per_burst": {k: round(tot / max(cnt, 1), 4) for k, (tot, cnt) in stages.items()},
+            "mean_loss": loss,
+            "grad_tuning_sum": dict(zip(binding.GRAD_NAMES, [float(f"{v:.6g}") for v in g_t]))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +215,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-burst batched leg")
+    ap.add_argument("--no-grad", action="store_true", help="skip the forward + adjoint leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus 1); the merge shards by "
@@ -227,8 +293,9 @@ def main():
         "wall_s_timed": round(wall, 3),
     }
     if not args.no_batch:
-        del out
         line["batched"] = bench_batch(dev)
+    if not args.no_grad:
+        line["fwd_bwd"] = bench_grad(dev)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(burst.to("cpu"))

@@ -117,11 +117,15 @@ typedef struct {
  *          and taken as 0.
  *  out     DEVICE float32 [3][out_height][out_width], planes R, G, B of the
  *          normalised linear result (eq. 1).
- *  saved   NULL, or DEVICE float32 [3][3][out_height][out_width]: per channel
- *          the numerator, denominator (raw units, both scaled by 2^-m) and
- *          reference exponent m (log2 units) of eq. (1) at every output
- *          pixel. hmfsr_merge_backward can reuse it instead of rerunning the
- *          forward.
+ *  saved   NULL, or a DEVICE buffer of 12 * out_height * out_width 4-byte
+ *          words, 8-byte aligned, that receives the normaliser of eq. (1) for
+ *          hmfsr_merge_backward (which then needs no second forward): three
+ *          float64 planes [3][out_height][out_width] with C per channel in raw
+ *          units, then three float32 planes with the denominator (scaled by
+ *          2^-m) and three with the reference exponent m (log2 units). With
+ *          saved the normaliser is accumulated in float64 and the 64 x 16
+ *          tile shape is used, so `out` can differ from a call without it in
+ *          the last bits.
  * Returns HMFSR_OK, or an error code with nothing enqueued.
  */
 hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
@@ -147,7 +151,7 @@ hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
  *            base frame's vectors are ignored by the merge and get 0.
  * Kernel weights are recomputed, not stored. Sums are taken in a fixed order:
  * repeated calls give identical bits. The internal workspace grows to about
- * 40 bytes per output pixel plus 9 * 4 more when saved is NULL.
+ * 40 bytes per output pixel plus 48 more when saved is NULL.
  */
 hmfsr_status hmfsr_merge_backward(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
                                   const uint16_t* frames, const float* motion,

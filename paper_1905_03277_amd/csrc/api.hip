@@ -208,7 +208,7 @@ hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, con
   hmfsr_status st = validate(desc, tuning);
   if (st != HMFSR_OK) return st;
   if (!frames || !motion || !out) return HMFSR_E_INVALID;
-  if (((uintptr_t)frames & 3) || ((uintptr_t)motion & 3) || ((uintptr_t)out & 3) || ((uintptr_t)saved & 3))
+  if (((uintptr_t)frames & 3) || ((uintptr_t)motion & 3) || ((uintptr_t)out & 3) || ((uintptr_t)saved & 7))
     return HMFSR_E_INVALID;
   std::lock_guard<std::mutex> lock(g_mutex);
   int dev = 0;
@@ -227,9 +227,10 @@ hmfsr_status hmfsr_merge_backward(const hmfsr_desc* desc, const hmfsr_tuning* tu
   hmfsr_status st = validate(desc, tuning);
   if (st != HMFSR_OK) return st;
   if (!frames || !motion || !grad_out || !grad_tuning || !grad_motion) return HMFSR_E_INVALID;
-  for (const void* p : {(const void*)frames, (const void*)motion, (const void*)saved, (const void*)grad_out,
+  for (const void* p : {(const void*)frames, (const void*)motion, (const void*)grad_out,
                         (const void*)grad_tuning, (const void*)grad_motion})
     if ((uintptr_t)p & 3) return HMFSR_E_INVALID;
+  if ((uintptr_t)saved & 7) return HMFSR_E_INVALID;
   std::lock_guard<std::mutex> lock(g_mutex);
   int dev = 0;
   if ((st = current_device(&dev)) != HMFSR_OK) return st;

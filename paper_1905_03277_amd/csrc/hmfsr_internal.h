@@ -84,8 +84,10 @@ struct MergeVariant {
 };
 extern const MergeVariant kMergeVariants[];
 extern const int kNumMergeVariants;
-// out and saved are each nullable; saved receives the normaliser of eq. (1):
-// [3][3][OH][OW] numerator, denominator and reference exponent per channel.
+// out and saved are each nullable. saved receives the normaliser of eq. (1),
+// accumulated in float64 (the 64 x 16 tile shape is then used): three float64
+// planes C per channel (raw units), then three float32 planes of the
+// denominator and three of the reference exponent (12 4-byte words per pixel).
 hipError_t launch_merge(int variant, const Geometry& g, const MergeConsts& mc, const uint16_t* frames,
                         const float* motion, const float* rmin, float* out, float* saved,
                         hipStream_t stream);
@@ -122,7 +124,7 @@ struct BwdConsts {
 struct BwdWork {
   Work fwd;
   float* rmap;        // [n][h][w] R of eq. (5)
-  float* saved;       // [9][OH][OW] normaliser of eq. (1) when the caller keeps none
+  float* saved;       // [12][OH][OW] words: normaliser of eq. (1) when the caller keeps none
   float* part_rh;     // [n][tiles][kBwdRH] dL/dR_hat over each tile's R_hat window
   double* part_mo;    // [tiles][n][kBwdVT][2] dL/dv of the alignment tiles each tile touches
   double* part_theta; // [tiles][6] dL/d(k_detail, k_denoise, d_th, d_tr, k_stretch, k_shrink), unscaled

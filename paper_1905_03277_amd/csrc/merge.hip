@@ -19,6 +19,8 @@
 // motion field), the tile is processed one alignment tile at a time.
 #include <math.h>
 
+#include <type_traits>
+
 #include "device_util.h"
 #include "hmfsr_internal.h"
 #include "merge_common.h"
@@ -48,7 +50,8 @@ struct MergeSmem {
 };
 
 // One 64 x MH output tile (tile_x, tile_y) of one burst.
-template <int MH, int THREADS>
+// SAVE: accumulate the normaliser in float64 and store it for the adjoint.
+template <int MH, int THREADS, bool SAVE>
 __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
                                            const float* __restrict__ motion,
                                            const float* __restrict__ rmin, const Geometry& g,
@@ -141,13 +144,15 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
   const float vlim = (float)(max(g.W, g.H) + 16);
 
   // ---- accumulators -----------------------------------------------------
-  float num[PX][3], den[PX][3], M[PX][3];
+  using Acc = typename std::conditional<SAVE, double, float>::type;
+  Acc num[PX][3], den[PX][3];
+  float M[PX][3];
 #pragma unroll
   for (int p = 0; p < PX; ++p)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      num[p][c] = 0.f;
-      den[p][c] = 0.f;
+      num[p][c] = 0;
+      den[p][c] = 0;
       M[p][c] = -INFINITY;
     }
 
@@ -399,12 +404,13 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
           const float Gn = isG ? S0n + S3n : S1n + S2n, Gd = isG ? S0d + S3d : S1d + S2d;
           const float Xn = isG ? S1n : S0n, Xd = isG ? S1d : S0d;
           const float Yn = isG ? S2n : S3n, Yd = isG ? S2d : S3d;
-          num[p][0] = fmaf(rho, xIsR ? Xn : Yn, num[p][0]);
-          den[p][0] = fmaf(rho, xIsR ? Xd : Yd, den[p][0]);
-          num[p][1] = fmaf(rho, Gn, num[p][1]);
-          den[p][1] = fmaf(rho, Gd, den[p][1]);
-          num[p][2] = fmaf(rho, xIsR ? Yn : Xn, num[p][2]);
-          den[p][2] = fmaf(rho, xIsR ? Yd : Xd, den[p][2]);
+          const Acc ra = rho;
+          num[p][0] = fma(ra, (Acc)(xIsR ? Xn : Yn), num[p][0]);
+          den[p][0] = fma(ra, (Acc)(xIsR ? Xd : Yd), den[p][0]);
+          num[p][1] = fma(ra, (Acc)Gn, num[p][1]);
+          den[p][1] = fma(ra, (Acc)Gd, den[p][1]);
+          num[p][2] = fma(ra, (Acc)(xIsR ? Yn : Xn), num[p][2]);
+          den[p][2] = fma(ra, (Acc)(xIsR ? Yd : Xd), den[p][2]);
         }
       }
       if (whole || ++seg >= ntiles) break;
@@ -422,14 +428,15 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
       const size_t o = (size_t)(R0 + r) * g.OW + C;
       if (out) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) out[o + c * plane] = (num[p][c] / den[p][c] - mc.black) * mc.inv_range;
+        for (int c = 0; c < 3; ++c)
+          out[o + c * plane] = (float)((num[p][c] / den[p][c] - (Acc)mc.black) * (Acc)mc.inv_range);
       }
-      if (saved) {  // the normaliser of eq. (1), for the adjoint
+      if (SAVE) {  // the normaliser of eq. (1), for the adjoint
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          saved[o + c * plane] = num[p][c];
-          saved[o + (3 + c) * plane] = den[p][c];
-          saved[o + (6 + c) * plane] = M[p][c];
+          ((double*)saved)[o + c * plane] = (double)(num[p][c] / den[p][c]);
+          saved[o + (6 + c) * plane] = (float)den[p][c];
+          saved[o + (9 + c) * plane] = M[p][c];
         }
       }
     }
@@ -439,10 +446,18 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
 template <int MH, int THREADS>
 __global__ __launch_bounds__(THREADS, (MH / (THREADS / 64) <= 4) ? 4 : 2) void k_merge(
     const uint16_t* __restrict__ frames, const float* __restrict__ motion,
+    const float* __restrict__ rmin, Geometry g, MergeConsts mc, float* __restrict__ out) {
+  __shared__ MergeSmem<MH> sm;
+  merge_tile<MH, THREADS, false>(frames, motion, rmin, g, mc, out, nullptr, blockIdx.x, blockIdx.y, sm);
+}
+
+// Forward that also keeps the normaliser for the adjoint (float64 accumulation).
+__global__ __launch_bounds__(256, 2) void k_merge_save(
+    const uint16_t* __restrict__ frames, const float* __restrict__ motion,
     const float* __restrict__ rmin, Geometry g, MergeConsts mc, float* __restrict__ out,
     float* __restrict__ saved) {
-  __shared__ MergeSmem<MH> sm;
-  merge_tile<MH, THREADS>(frames, motion, rmin, g, mc, out, saved, blockIdx.x, blockIdx.y, sm);
+  __shared__ MergeSmem<16> sm;
+  merge_tile<16, 256, true>(frames, motion, rmin, g, mc, out, saved, blockIdx.x, blockIdx.y, sm);
 }
 
 // Persistent form: workgroups pull (burst, tile) items from a global counter
@@ -462,17 +477,16 @@ __global__ __launch_bounds__(THREADS, (MH / (THREADS / 64) <= 4) ? 4 : 2) void k
     const WorkItem w = items[it];
     const BurstArgs& b = bursts[w.burst];
     const int tx = w.tile % b.merge_tiles_x, ty = w.tile / b.merge_tiles_x;
-    merge_tile<MH, THREADS>(b.frames, b.motion, b.rmin, b.g, b.mc, b.out, nullptr, tx, ty, sm);
+    merge_tile<MH, THREADS, false>(b.frames, b.motion, b.rmin, b.g, b.mc, b.out, nullptr, tx, ty, sm);
   }
 }
 
 template <int MH, int THREADS>
 hipError_t launch_variant(const Geometry& g, const MergeConsts& mc, const uint16_t* frames,
-                          const float* motion, const float* rmin, float* out, float* saved,
-                          hipStream_t stream) {
+                          const float* motion, const float* rmin, float* out, hipStream_t stream) {
   const dim3 grid((g.OW + MW - 1) / MW, (g.OH + MH - 1) / MH);
   hipLaunchKernelGGL((k_merge<MH, THREADS>), grid, dim3(THREADS), 0, stream, frames, motion, rmin, g,
-                     mc, out, saved);
+                     mc, out);
   return hipGetLastError();
 }
 
@@ -494,11 +508,16 @@ const int kNumMergeVariants = sizeof(kMergeVariants) / sizeof(kMergeVariants[0])
 hipError_t launch_merge(int variant, const Geometry& g, const MergeConsts& mc, const uint16_t* frames,
                         const float* motion, const float* rmin, float* out, float* saved,
                         hipStream_t stream) {
+  if (saved) {  // one tile shape keeps the normaliser
+    const dim3 grid((g.OW + MW - 1) / MW, (g.OH + 15) / 16);
+    hipLaunchKernelGGL(k_merge_save, grid, dim3(256), 0, stream, frames, motion, rmin, g, mc, out, saved);
+    return hipGetLastError();
+  }
   switch (variant) {
-    case 1: return launch_variant<32, 512>(g, mc, frames, motion, rmin, out, saved, stream);
-    case 2: return launch_variant<16, 256>(g, mc, frames, motion, rmin, out, saved, stream);
-    case 3: return launch_variant<16, 128>(g, mc, frames, motion, rmin, out, saved, stream);
-    default: return launch_variant<32, 256>(g, mc, frames, motion, rmin, out, saved, stream);
+    case 1: return launch_variant<32, 512>(g, mc, frames, motion, rmin, out, stream);
+    case 2: return launch_variant<16, 256>(g, mc, frames, motion, rmin, out, stream);
+    case 3: return launch_variant<16, 128>(g, mc, frames, motion, rmin, out, stream);
+    default: return launch_variant<32, 256>(g, mc, frames, motion, rmin, out, stream);
   }
 }
 

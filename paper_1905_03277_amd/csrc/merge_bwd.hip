@@ -5,8 +5,9 @@
 // displacement of every aligned frame.
 //
 // Kernel weights are recomputed, never stored: the forward keeps only the
-// normaliser of eq. (1) per output pixel and channel (numerator, denominator,
-// reference exponent). With w_i = exp(e_i - m) and den = sum rho_i w_i,
+// normaliser of eq. (1) per output pixel and channel (the value C in float64,
+// the denominator, the reference exponent). With w_i = exp(e_i - m) and
+// den = sum rho_i w_i,
 //   dC/drho_i = w_i (c_i - C) / den,   dC/de_i = rho_i w_i (c_i - C) / den,
 // and e = -1/2 d^T Omega^-1 d with d = q + 1/2 - p gives
 //   de/dp = Omega^-1 d,   de/dOmega = 1/2 Omega^-1 d d^T Omega^-1.
@@ -61,8 +62,12 @@ struct BwdSmem {
   float sRaw[BCP::RAW];
   float sLum[BCP::LUMA];
   double sOm[3][BCP::OM];
-  // dOmega/dtheta per half-res pixel: (cos 2phi, sin 2phi, p0, p1), (p2..p5), (p6..p9)
-  float4 sP[3][BCP::OM];
+  // dOmega/dtheta per half-res pixel: the gradient direction as (cos 2phi,
+  // sin 2phi) in float64 (the edge projection of dL/dOmega cancels up to
+  // (k1/k2)^2), and the per-scalar factors p0..p9.
+  double2 sDir[BCP::OM];
+  float4 sP[2][BCP::OM];
+  float2 sP2[BCP::OM];
   float sRh[BCP::RH];
   float sGr[BMH][MW];    // dL/drho per pixel, this frame
   float2 sGp[BMH][MW];   // dL/dp per pixel, this frame
@@ -183,27 +188,33 @@ __global__ __launch_bounds__(BTHREADS, 2) void k_merge_bwd(
   const float vlim = (float)(max(g.W, g.H) + 16);
 
   // ---- the forward's normaliser and dL/dC per pixel ----------------------
-  float gam[BPX][3], cval[BPX][3], mref[BPX][3];
+  // C is kept as a float pair (hi + lo): x - C is then accurate to a float
+  // rounding even where x and C nearly cancel, which the tuning gradients need
+  // (the weights of one channel sum their (x - C) terms to zero).
+  float gam[BPX][3], chi[BPX][3], clo[BPX][3], mref[BPX][3];
   {
     const size_t plane = (size_t)g.OH * g.OW;
+    const double* Cs = (const double*)saved;
 #pragma unroll
     for (int p = 0; p < BPX; ++p) {
       const int r = wave * BPX + p;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         gam[p][c] = 0.f;
-        cval[p][c] = 0.f;
+        chi[p][c] = 0.f;
+        clo[p][c] = 0.f;
         mref[p][c] = 0.f;
       }
       if (!col_ok || r >= nrow) continue;
       const size_t o = (size_t)(R0 + r) * g.OW + C;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float num = saved[o + c * plane], den = saved[o + (3 + c) * plane];
-        cval[p][c] = num / den;  // raw units, as the forward divides
-        mref[p][c] = saved[o + (6 + c) * plane];
+        const double cv = Cs[o + c * plane];  // raw units
+        chi[p][c] = (float)cv;
+        clo[p][c] = (float)(cv - (double)chi[p][c]);
+        mref[p][c] = saved[o + (9 + c) * plane];
         // dL/dC_raw = dL/dC * inv_range, over the denominator of eq. (1)
-        gam[p][c] = grad_out[o + c * plane] * mc.inv_range / den;
+        gam[p][c] = grad_out[o + c * plane] * mc.inv_range / saved[o + (6 + c) * plane];
       }
     }
   }
@@ -329,11 +340,11 @@ __global__ __launch_bounds__(BTHREADS, 2) void k_merge_bwd(
           const double f1 = pt.d_free ? s1 * (bc.kn - bc.kst * A) : 0.0;
           const double f2 = pt.d_free ? s2 * (bc.kn - invA / bc.ksh) : 0.0;
           const double sl = pt.sqrt_l1 * bc.sl;
-          sm.sP[0][k] = make_float4((float)(pt.gx2 - pt.gy2), (float)(2.0 * pt.gxy), (float)(s1 * pt.k1s),
-                                    (float)(s2 * pt.k2s));
-          sm.sP[1][k] = make_float4((float)(s1 * D), (float)(s2 * D), (float)(s1 * (1.0 - D) * A),
-                                    (float)(s2 * (1.0 - D) * invA));
-          sm.sP[2][k] = make_float4((float)f1, (float)f2, (float)(f1 * sl), (float)(f2 * sl));
+          sm.sDir[k] = make_double2(pt.gx2 - pt.gy2, 2.0 * pt.gxy);
+          sm.sP[0][k] = make_float4((float)(s1 * pt.k1s), (float)(s2 * pt.k2s), (float)(s1 * D), (float)(s2 * D));
+          sm.sP[1][k] = make_float4((float)(s1 * (1.0 - D) * A), (float)(s2 * (1.0 - D) * invA), (float)f1,
+                                    (float)f2);
+          sm.sP2[k] = make_float2((float)(f1 * sl), (float)(f2 * sl));
         }
       }
       __syncthreads();
@@ -362,8 +373,7 @@ __global__ __launch_bounds__(BTHREADS, 2) void k_merge_bwd(
           const double fhj = floor(hx), fhi = floor(hy);
           const double fx = hx - fhj, fy = hy - fhi;
           const int ob = ((int)fhi - or0) * ow + ((int)fhj - oc0);
-          double O[3];
-          float dOx[3], dOy[3];  // dOmega_bar / d(hx, hy)
+          double O[3], dOx[3], dOy[3];  // Omega_bar and its derivatives along hx, hy
 #pragma unroll
           for (int e = 0; e < 3; ++e) {
             const double o00 = sm.sOm[e][ob], o01 = sm.sOm[e][ob + 1];
@@ -371,8 +381,8 @@ __global__ __launch_bounds__(BTHREADS, 2) void k_merge_bwd(
             const double top = fma(fx, o01 - o00, o00);
             const double bot = fma(fx, o11 - o10, o10);
             O[e] = fma(fy, bot - top, top);
-            dOx[e] = (float)fma(fy, (o11 - o10) - (o01 - o00), o01 - o00);
-            dOy[e] = (float)(bot - top);
+            dOx[e] = fma(fy, (o11 - o10) - (o01 - o00), o01 - o00);
+            dOy[e] = bot - top;
           }
           const double idet = recip64(O[0] * O[2] - O[1] * O[1]);
           const double sc = NEG_HALF_LOG2E * idet;
@@ -411,12 +421,13 @@ __global__ __launch_bounds__(BTHREADS, 2) void k_merge_bwd(
           const bool isG = c0 == 1;
           const int chX = ((isG ? c1 : c0) == 0) ? 0 : 2, chY = 2 - chX;
           const int chg[4] = {isG ? 1 : chX, isG ? chX : 1, isG ? chY : 1, isG ? 1 : chY};
-          float Mg[4], Gg[4], Cg[4];
+          float Mg[4], Gg[4], Ch[4], Cl[4];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             Mg[q] = pick3(mref[p], chg[q]);
             Gg[q] = pick3(gam[p], chg[q]);
-            Cg[q] = pick3(cval[p], chg[q]);
+            Ch[q] = pick3(chi[p], chg[q]);
+            Cl[q] = pick3(clo[p], chg[q]);
           }
           const int vb = (ic - 1 - rr0) * rw + (jc - 1 - rc0);
           float a[3][3];
@@ -427,7 +438,7 @@ __global__ __launch_bounds__(BTHREADS, 2) void k_merge_bwd(
             for (int j = 0; j < 3; ++j) {
               const int q = (i == 1 && j == 1) ? 0 : (i == 1 ? 1 : (j == 1 ? 2 : 3));
               const float w = __builtin_amdgcn_exp2f((float)(E[i][j] - (double)Mg[q]));
-              const float bq = Gg[q] * w * (sm.sRaw[vb + i * rw + j] - Cg[q]);  // dL/drho part
+              const float bq = Gg[q] * w * ((sm.sRaw[vb + i * rw + j] - Ch[q]) - Cl[q]);  // dL/drho part
               grho += bq;
               a[i][j] = rho * bq;  // dL/de
             }
@@ -448,33 +459,40 @@ __global__ __launch_bounds__(BTHREADS, 2) void k_merge_bwd(
             ty = fmaf(Arow[j], dyf[j], ty);
             Syy = fmaf(Arow[j] * dyf[j], dyf[j], Syy);
           }
-          const float ia = (float)(O[2] * idet), ib = (float)(-O[1] * idet), ic_ = (float)(O[0] * idet);
-          // dL/dOmega_bar = 1/2 Omega^-1 S Omega^-1 (Oxy on both off-diagonal entries)
-          const float K11 = fmaf(ia, Sxx, ib * Sxy), K12 = fmaf(ia, Sxy, ib * Syy);
-          const float K21 = fmaf(ib, Sxx, ic_ * Sxy), K22 = fmaf(ib, Sxy, ic_ * Syy);
-          const float Gxx = 0.5f * fmaf(K11, ia, K12 * ib);
-          const float Gxy = fmaf(K11, ib, K12 * ic_);
-          const float Gyy = 0.5f * fmaf(K21, ib, K22 * ic_);
+          // dL/dOmega_bar = 1/2 Omega^-1 S Omega^-1 (Oxy on both off-diagonal
+          // entries), in float64: its edge component is ~(k2/k1)^2 of its size.
+          const double ia = O[2] * idet, ib = -O[1] * idet, ic_ = O[0] * idet;
+          const double Sxx_d = Sxx, Sxy_d = Sxy, Syy_d = Syy;
+          const double K11 = fma(ia, Sxx_d, ib * Sxy_d), K12 = fma(ia, Sxy_d, ib * Syy_d);
+          const double K21 = fma(ib, Sxx_d, ic_ * Sxy_d), K22 = fma(ib, Sxy_d, ic_ * Syy_d);
+          const double Gxx = 0.5 * fma(K11, ia, K12 * ib);
+          const double Gxy = fma(K11, ib, K12 * ic_);
+          const double Gyy = 0.5 * fma(K21, ib, K22 * ic_);
           // dL/dp: the offsets, and Omega sampled at p / 2 - 1/2
-          const float gpx = fmaf(ia, tx, ib * ty) + 0.5f * fmaf(Gxx, dOx[0], fmaf(Gxy, dOx[1], Gyy * dOx[2]));
-          const float gpy = fmaf(ib, tx, ic_ * ty) + 0.5f * fmaf(Gxx, dOy[0], fmaf(Gxy, dOy[1], Gyy * dOy[2]));
-          // contract with dOmega/dtheta at the four corners
-          const float T = 0.5f * (Gxx + Gyy), U = 0.5f * (Gyy - Gxx), V = -0.5f * Gxy;
+          const float gpx = (float)(fma(ia, (double)tx, ib * (double)ty) +
+                                    0.5 * fma(Gxx, dOx[0], fma(Gxy, dOx[1], Gyy * dOx[2])));
+          const float gpy = (float)(fma(ib, (double)tx, ic_ * (double)ty) +
+                                    0.5 * fma(Gxx, dOy[0], fma(Gxy, dOy[1], Gyy * dOy[2])));
+          // dL/dk1, dL/dk2 at each corner: projections of dL/dOmega on its edge and
+          // gradient directions, 1/2 tr +- (cos 2phi U + sin 2phi V); then times dk/dtheta
+          const double T = 0.5 * (Gxx + Gyy), U = 0.5 * (Gyy - Gxx), V = -0.5 * Gxy;
           const float ffx = (float)fx, ffy = (float)fy;
           const float wq[4] = {(1.f - ffx) * (1.f - ffy), ffx * (1.f - ffy), (1.f - ffx) * ffy, ffx * ffy};
           const int cq[4] = {ob, ob + 1, ob + ow, ob + ow + 1};
           float s6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const float4 P0 = sm.sP[0][cq[q]], P1 = sm.sP[1][cq[q]], P2 = sm.sP[2][cq[q]];
-            const float qq = fmaf(P0.x, U, P0.y * V);
-            const float k1 = wq[q] * (T + qq), k2 = wq[q] * (T - qq);  // dL/dk1, dL/dk2 at the corner
-            s6[0] = fmaf(k1, P0.z, fmaf(k2, P0.w, s6[0]));
-            s6[1] = fmaf(k1, P1.x, fmaf(k2, P1.y, s6[1]));
-            s6[2] = fmaf(k1, P2.x, fmaf(k2, P2.y, s6[2]));
-            s6[3] = fmaf(k1, P2.z, fmaf(k2, P2.w, s6[3]));
-            s6[4] = fmaf(k1, P1.z, s6[4]);
-            s6[5] = fmaf(k2, P1.w, s6[5]);
+            const double2 dir = sm.sDir[cq[q]];
+            const float4 P0 = sm.sP[0][cq[q]], P1 = sm.sP[1][cq[q]];
+            const float2 P2 = sm.sP2[cq[q]];
+            const double qq = fma(dir.x, U, dir.y * V);
+            const float k1 = wq[q] * (float)(T + qq), k2 = wq[q] * (float)(T - qq);
+            s6[0] = fmaf(k1, P0.x, fmaf(k2, P0.y, s6[0]));
+            s6[1] = fmaf(k1, P0.z, fmaf(k2, P0.w, s6[1]));
+            s6[2] = fmaf(k1, P1.z, fmaf(k2, P1.w, s6[2]));
+            s6[3] = fmaf(k1, P2.x, fmaf(k2, P2.y, s6[3]));
+            s6[4] = fmaf(k1, P1.x, s6[4]);
+            s6[5] = fmaf(k2, P1.y, s6[5]);
           }
 #pragma unroll
           for (int e = 0; e < 6; ++e) acc[e] += (double)s6[e];
@@ -853,7 +871,7 @@ size_t bwd_bytes(const Geometry& g, bool need_saved) {
   const size_t plane = (size_t)g.h * g.w;
   size_t b = align256(work_bytes(g));
   b += align256(plane * g.n * sizeof(float));
-  if (need_saved) b += align256((size_t)9 * g.OH * g.OW * sizeof(float));
+  if (need_saved) b += align256((size_t)12 * g.OH * g.OW * sizeof(float));
   b += align256((size_t)g.n * tiles * kBwdRH * sizeof(float));
   b += align256(tiles * g.n * kBwdVT * 2 * sizeof(double));
   b += align256(tiles * 6 * sizeof(double));
@@ -873,7 +891,7 @@ BwdWork bwd_carve(void* base, const Geometry& g, bool need_saved) {
   w.saved = nullptr;
   if (need_saved) {
     w.saved = (float*)p;
-    p += align256((size_t)9 * g.OH * g.OW * sizeof(float));
+    p += align256((size_t)12 * g.OH * g.OW * sizeof(float));
   }
   w.part_rh = (float*)p;
   p += align256((size_t)g.n * tiles * kBwdRH * sizeof(float));

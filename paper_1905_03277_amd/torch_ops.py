@@ -45,17 +45,24 @@ def _check_out(t: torch.Tensor | None, shape, device, what):
 def merge(frames: torch.Tensor, motion: torch.Tensor, desc, tuning,
           out: torch.Tensor | None = None, saved: torch.Tensor | None = None) -> torch.Tensor:
     """Merge one burst; returns float32 [3][OH][OW] on the frames' device.
-    ``saved`` (float32 [3][3][OH][OW]), if given, receives the normaliser the
-    adjoint can reuse."""
+    ``saved`` (float32 [12][OH][OW], see ``saved_buffer``), if given, receives
+    the normaliser the adjoint can reuse."""
     _check_inputs(frames, motion, desc)
     out = _check_out(out, (3, desc.out_height, desc.out_width), frames.device, "out")
     if saved is not None:
-        _check_out(saved, (3, 3, desc.out_height, desc.out_width), frames.device, "saved")
+        _check_out(saved, (12, desc.out_height, desc.out_width), frames.device, "saved")
     with torch.cuda.device(frames.device):
         binding.hmfsr_merge(binding.make_desc(desc), binding.make_tuning(tuning),
                             frames.data_ptr(), motion.data_ptr(), out.data_ptr(),
                             0 if saved is None else saved.data_ptr(), _stream(frames.device))
     return out
+
+
+def saved_buffer(desc, device) -> torch.Tensor:
+    """A buffer for the forward's normaliser: 12 words per output pixel (three
+    float64 planes of C, three float32 planes each of the denominator and the
+    reference exponent)."""
+    return torch.empty((12, desc.out_height, desc.out_width), dtype=torch.float32, device=device)
 
 
 def merge_backward(frames: torch.Tensor, motion: torch.Tensor, desc, tuning,
@@ -70,7 +77,7 @@ def merge_backward(frames: torch.Tensor, motion: torch.Tensor, desc, tuning,
     if tuple(grad_out.shape) != shape:
         raise ValueError(f"grad_out shape {tuple(grad_out.shape)} != {shape}")
     if saved is not None:
-        _check_out(saved, (3,) + shape, dev, "saved")
+        _check_out(saved, (12,) + shape[1:], dev, "saved")
     g_tun = torch.empty(9, dtype=torch.float32, device=dev)
     g_mot = torch.empty_like(motion)
     with torch.cuda.device(dev):
@@ -102,8 +109,7 @@ class HmfsrMerge(torch.autograd.Function):
     def forward(ctx, frames, motion, tuning_vec, desc):
         tun = _TuningView(tuning_vec.detach().to("cpu", torch.float32).tolist())
         motion_c = motion.detach().contiguous()
-        saved = torch.empty((3, 3, desc.out_height, desc.out_width), dtype=torch.float32,
-                            device=frames.device)
+        saved = saved_buffer(desc, frames.device)
         out = merge(frames, motion_c, desc, tun, saved=saved)
         ctx.save_for_backward(frames, motion_c, saved)
         ctx.desc, ctx.tun = desc, tun

@@ -40,7 +40,7 @@ def gpu_backward(f, m, desc, tuning, g_out, use_saved=True):
     mt = torch.from_numpy(m).to(DEV)
     saved = None
     if use_saved:
-        saved = torch.empty((3, 3, desc.out_height, desc.out_width), dtype=torch.float32, device=DEV)
+        saved = torch_ops.saved_buffer(desc, DEV)
         torch_ops.merge(ft, mt, desc, tuning, saved=saved)
     gt, gm = torch_ops.merge_backward(ft, mt, desc, tuning, torch.from_numpy(g_out).to(DEV), saved=saved)
     torch.cuda.synchronize()
