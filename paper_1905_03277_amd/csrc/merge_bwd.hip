@@ -577,29 +577,25 @@ __global__ __launch_bounds__(BTHREADS, 2) void k_merge_bwd(
 // ---------------------------------------------------------------------------
 constexpr int RB = 8;  // half-res pixels per block edge
 
-// dL/dR_hat at base half-res pixel (I, J) of frame n: the sum of the window
-// partials of every output tile whose R_hat window holds it, in tile order.
-__device__ float gather_rh(const float* __restrict__ part_rh, const Geometry& g, const BwdConsts& bc,
-                           int n, int I, int J) {
-  float s = 0.f;
-  const int ty0 = (int)((2.0 * I + 1.0) * g.scale / BMH), tx0 = (int)((2.0 * J + 1.0) * g.scale / MW);
-  for (int oty = max(ty0 - 2, 0); oty <= min(ty0 + 2, bc.tiles_y - 1); ++oty) {
-    const int R0 = oty * BMH, nrow = min(BMH, g.OH - R0);
-    int r0, r1;
-    rh_range(R0, R0 + nrow - 1, g.scale, g.h, r0, r1);
-    if (I < r0 || I > r1) continue;
-    for (int otx = max(tx0 - 2, 0); otx <= min(tx0 + 2, bc.tiles_x - 1); ++otx) {
-      const int C0 = otx * MW, ncol = min(MW, g.OW - C0);
-      int c0, c1;
-      rh_range(C0, C0 + ncol - 1, g.scale, g.w, c0, c1);
-      if (J < c0 || J > c1) continue;
-      s += part_rh[((size_t)n * bc.n_tiles + oty * bc.tiles_x + otx) * kBwdRH + (I - r0) * (c1 - c0 + 1) +
-                   (J - c0)];
-    }
+// Output tiles whose R_hat window holds base half-res row I (column J with
+// the column geometry): at most three, ascending. Returns how many; lo[k] is
+// the first window row (column) of tile t[k] and wd[k] its width.
+__device__ int rh_tiles(int I, int n_out, int edge, int n_tiles_axis, int n_half, double scale, int (&t)[3],
+                        int (&lo)[3], int (&wd)[3]) {
+  int cnt = 0;
+  const int t0 = (int)((2.0 * I + 1.0) * scale / edge);
+  for (int ot = max(t0 - 2, 0); ot <= min(t0 + 2, n_tiles_axis - 1) && cnt < 3; ++ot) {
+    const int o0 = ot * edge, no = min(edge, n_out - o0);
+    int a, b;
+    rh_range(o0, o0 + no - 1, scale, n_half, a, b);
+    if (I < a || I > b) continue;
+    t[cnt] = ot;
+    lo[cnt] = a;
+    wd[cnt] = b - a + 1;
+    ++cnt;
   }
-  return s;
+  return cnt;
 }
-
 // Guide colour (R, mean of the greens, B) of half-res pixel (I, J), raw units.
 __device__ __forceinline__ void guide_px(const uint16_t* f, const Geometry& g, int I, int J, float (&c)[3]) {
   const uint32_t top = *(const uint32_t*)(f + (size_t)(2 * I) * g.W + 2 * J);
@@ -650,6 +646,9 @@ __global__ __launch_bounds__(64) void k_robust_bwd(const uint16_t* __restrict__ 
   __shared__ float sR[RB + 8][RB + 8];
   __shared__ float sG[RB + 4][RB + 4];
   __shared__ int sA[RB + 4][RB + 4];
+  // output tiles whose R_hat windows cover each cell row / column of the block
+  __shared__ int sNr[RB + 4], sTr[RB + 4][3], sLr[RB + 4][3];
+  __shared__ int sNc[RB + 4], sTc[RB + 4][3], sLc[RB + 4][3], sWc[RB + 4][3];
   const size_t plane = (size_t)g.h * g.w;
   const float* R = rmap + (size_t)n * plane;
   const uint16_t* fref = frames + (size_t)g.ref * g.H * g.W;
@@ -669,6 +668,26 @@ __global__ __launch_bounds__(64) void k_robust_bwd(const uint16_t* __restrict__ 
         const int rr = k / (RB + 8), cc = k - rr * (RB + 8);
         sR[rr][cc] = R[(size_t)clampi(bi0 - 4 + rr, 0, g.h - 1) * g.w + clampi(bj0 - 4 + cc, 0, g.w - 1)];
       }
+      if (tid < RB + 4) {
+        int t[3], lo[3], wd[3];
+        const int I = bi0 - 2 + tid;
+        const int cnt = (I >= 0 && I < g.h) ? rh_tiles(I, g.OH, BMH, bc.tiles_y, g.h, g.scale, t, lo, wd) : 0;
+        sNr[tid] = cnt;
+        for (int k = 0; k < cnt; ++k) {
+          sTr[tid][k] = t[k];
+          sLr[tid][k] = lo[k];
+        }
+      } else if (tid >= 32 && tid < 32 + RB + 4) {
+        int t[3], lo[3], wd[3];
+        const int c = tid - 32, J = bj0 - 2 + c;
+        const int cnt = (J >= 0 && J < g.w) ? rh_tiles(J, g.OW, MW, bc.tiles_x, g.w, g.scale, t, lo, wd) : 0;
+        sNc[c] = cnt;
+        for (int k = 0; k < cnt; ++k) {
+          sTc[c][k] = t[k];
+          sLc[c][k] = lo[k];
+          sWc[c][k] = wd[k];
+        }
+      }
       __syncthreads();
       // dL/dR_hat of the cells whose 5x5 window can reach the block, and
       // where it goes: the first minimum of the window in scan order.
@@ -677,7 +696,12 @@ __global__ __launch_bounds__(64) void k_robust_bwd(const uint16_t* __restrict__ 
         const int I = bi0 - 2 + r2, J = bj0 - 2 + c2;
         float gr = 0.f;
         int arg = -1;
-        if (I >= 0 && I < g.h && J >= 0 && J < g.w) gr = gather_rh(part_rh, g, bc, n, I, J);
+        // dL/dR_hat: the window partials of every output tile holding the cell, in tile order
+        for (int a = 0; a < sNr[r2]; ++a) {
+          const float* row = part_rh + ((size_t)n * bc.n_tiles + sTr[r2][a] * bc.tiles_x) * kBwdRH;
+          for (int b2 = 0; b2 < sNc[c2]; ++b2)
+            gr += row[(size_t)sTc[c2][b2] * kBwdRH + (I - sLr[r2][a]) * sWc[c2][b2] + (J - sLc[c2][b2])];
+        }
         if (gr != 0.f) {
           float best = INFINITY;
           for (int di = -2; di <= 2; ++di) {
