@@ -34,6 +34,11 @@ ALU_PEAK_TOPS = CUS * LANES * CLOCK_GHZ / 1000.0   # vector lane-operations: 39.
 OPS_SAMPLE = 161.0      # per output pixel and frame: nine-sample weights and accumulation
 OPS_OMEGA = 79.0        # per half-res pixel and frame: luma, structure tensor, eigen, S.1, Omega
 OPS_ROBUST = 98.0       # per half-res pixel and aligned frame: guide means, eq. 5-6, 5x5 min
+# Adjoint of the accumulation: the recomputed weights (the forward count less its
+# accumulation) plus dL/de, dL/drho, the offset moments, dL/dOmega_bar, dL/dp and
+# the four corner projections onto the six covariance scalars.
+OPS_ADJ_SAMPLE = 337.0  # per output pixel and frame
+OPS_ADJ_OMEGA = 99.0    # per half-res pixel and frame: Omega and its ten per-scalar factors
 
 
 def algorithmic_ops(desc) -> dict:
@@ -197,13 +202,20 @@ def bench_grad(dev, reps: int = 3) -> dict:
     fwd_bwd()
     stages = binding.hmfsr_profile_end()
     loss = float(sum(torch.mean((o - b.gt) ** 2).item() for o, b in zip(outs, bursts)) / len(bursts))
+    kern = {k: tot / max(cnt, 1) for k, (tot, cnt) in stages.items()}
+    n, hp = d0.n_frames, (d0.height // 2) * (d0.width // 2)
+    adj_ops = OPS_ADJ_SAMPLE * n * d0.out_height * d0.out_width + OPS_ADJ_OMEGA * n * hp
+    adj_achieved = adj_ops / (kern["k_merge_bwd"] / 1e3) / 1e12
     g_t = torch.stack([g[0] for g in grads]).sum(0).cpu().tolist()
     in_mp = sum(b.desc.n_frames * b.desc.height * b.desc.width for b in bursts) / 1e6
     return {"workload": f"16 bursts, {d0.n_frames} frames {d0.width}x{d0.height} RGGB, scale {d0.scale}, "
                         "L2 loss against the synthetic scene",
             "input_MP": round(in_mp, 1), "ms_fwd": round(ms_f, 3), "ms_fwd_bwd": round(ms_fb, 3),
             "MPs_fwd": round(in_mp / (ms_f / 1e3), 1), "MPs_fwd_bwd": round(in_mp / (ms_fb / 1e3), 1),
-            "kernels_ms_per_burst": {k: round(tot / max(cnt, 1), 4) for k, (tot, cnt) in stages.items()},
+            "kernels_ms_per_burst": {k: round(v, 4) for k, v in kern.items()},
+            "roofline_adjoint": {"bound": "alu", "kernel": "k_merge_bwd", "achieved": round(adj_achieved, 3),
+                                 "peak": round(ALU_PEAK_TOPS, 2), "unit": "Top/s",
+                                 "frac": round(adj_achieved / ALU_PEAK_TOPS, 4), "algorithmic_ops": adj_ops},
             "mean_loss": loss,
             "grad_tuning_sum": dict(zip(binding.GRAD_NAMES, [float(f"{v:.6g}") for v in g_t]))}
 
