@@ -26,15 +26,20 @@ constexpr int GU_CAP = 1150;                     // frame-n guide window and row
 constexpr int TT_X = RR_W / 4 + 2, TT_Y = RR_H / 4 + 2;  // alignment tiles spanned (T >= 8)
 constexpr int THREADS = 256;
 
+// Raw value at parity position pos (row-major in the 2x2 quad) from the quad's
+// two 32-bit rows; pos is uniform, so this is a select and a shift.
+__device__ __forceinline__ uint32_t quad_at(uint32_t top, uint32_t bot, int pos) {
+  return ((pos & 2) ? bot : top) >> ((pos & 1) * 16) & 0xffffu;
+}
+
 // Guide pixel (I, J) of a frame in raw units: R, mean of the two greens, B.
 __device__ __forceinline__ void load_guide(const uint16_t* f, const Geometry& g, int I, int J,
                                            float& r, float& gr, float& b) {
   const uint32_t top = *(const uint32_t*)(f + (size_t)(2 * I) * g.W + 2 * J);
   const uint32_t bot = *(const uint32_t*)(f + (size_t)(2 * I + 1) * g.W + 2 * J);
-  const int q[4] = {(int)(top & 0xffff), (int)(top >> 16), (int)(bot & 0xffff), (int)(bot >> 16)};
-  r = (float)q[g.red_pos];
-  gr = (float)(q[g.green_pos[0]] + q[g.green_pos[1]]) * 0.5f;
-  b = (float)q[g.blue_pos];
+  r = (float)quad_at(top, bot, g.red_pos);
+  gr = (float)(quad_at(top, bot, g.green_pos[0]) + quad_at(top, bot, g.green_pos[1])) * 0.5f;
+  b = (float)quad_at(top, bot, g.blue_pos);
 }
 
 struct Bounds4 {
@@ -50,7 +55,8 @@ struct RobustSmem {
   float sTmp[RR_H * RB_W];
   int sTyR[RR_H], sTxR[RR_W];  // alignment tile of each region row / column
   int sRlo[TT_Y], sRhi[TT_Y], sClo[TT_X], sChi[TT_X];
-  float2 sV[TT_X * TT_Y];
+  int2 sO[TT_X * TT_Y];     // floor(v / 2): integer part of the half-res displacement
+  float2 sF[TT_X * TT_Y];   // v / 2 - floor(v / 2): the bilinear fractions, exact
   float sS[TT_X * TT_Y];
   Bounds4 sTB[TT_X * TT_Y];
   int sRed[4];
@@ -76,7 +82,8 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
   int* sRhi = sm.sRhi;
   int* sClo = sm.sClo;
   int* sChi = sm.sChi;
-  float2* sV = sm.sV;
+  int2* sO = sm.sO;
+  float2* sF = sm.sF;
   float* sS = sm.sS;
   Bounds4* sTB = sm.sTB;
   int* sRed = sm.sRed;
@@ -161,28 +168,44 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
     if (n == g.ref) continue;
     const uint16_t* f = frames + (size_t)n * g.H * g.W;
     __syncthreads();
-    if (tid < ntiles) {
-      const int ky = tid / ntx, kx = tid - ky * ntx;
-      const size_t t = ((size_t)n * g.TY + tyA + ky) * g.TX + txA + kx;
-      const float* p = motion + 2 * t;
-      // clamping keeps non-finite or huge vectors finite and changes no result
-      sV[tid] = make_float2(fminf(fmaxf(p[0], -vlim), vlim), fminf(fmaxf(p[1], -vlim), vlim));
-      sS[tid] = s_tile[t];
-    }
-    if (tid < 4) sRed[tid] = 0x7fffffff;
-    __syncthreads();
-    // footprint of each alignment tile (monotonic in the pixel position)
-    if (tid < ntiles) {
-      const int ky = tid / ntx, kx = tid - ky * ntx;
-      const float2 v = sV[tid];
-      Bounds4 b;
-      b.x0 = (int)floor((double)clampi(ca0 + sClo[kx], 0, g.w - 1) + (double)v.x * 0.5);
-      b.x1 = (int)floor((double)clampi(ca0 + sChi[kx], 0, g.w - 1) + (double)v.x * 0.5);
-      b.y0 = (int)floor((double)clampi(ra0 + sRlo[ky], 0, g.h - 1) + (double)v.y * 0.5);
-      b.y1 = (int)floor((double)clampi(ra0 + sRhi[ky], 0, g.h - 1) + (double)v.y * 0.5);
-      sTB[tid] = b;
-      atomicMin(&sRed[0], b.x0); atomicMin(&sRed[1], -b.x1);
-      atomicMin(&sRed[2], b.y0); atomicMin(&sRed[3], -b.y1);
+    // per alignment tile: the bilinear base corner of u + v/2 is u + floor(v/2)
+    // (u integer) with the same fractions for every pixel of the tile; and the
+    // tile's footprint (monotonic in the pixel position). Wave 0 reduces the
+    // footprints without atomics.
+    if (tid < 64) {
+      Bounds4 acc = {0x7fffffff, -0x7fffffff, 0x7fffffff, -0x7fffffff};
+      for (int k = tid; k < ntiles; k += 64) {
+        const int ky = k / ntx, kx = k - ky * ntx;
+        const size_t t = ((size_t)n * g.TY + tyA + ky) * g.TX + txA + kx;
+        const float* p = motion + 2 * t;
+        // clamping keeps non-finite or huge vectors finite and changes no result
+        const float hx = fminf(fmaxf(p[0], -vlim), vlim) * 0.5f, hy = fminf(fmaxf(p[1], -vlim), vlim) * 0.5f;
+        const float fx = floorf(hx), fy = floorf(hy);
+        const int2 o = make_int2((int)fx, (int)fy);
+        sO[k] = o;
+        sF[k] = make_float2(hx - fx, hy - fy);  // exact: v/2 has at most 24 significant bits
+        sS[k] = s_tile[t];
+        Bounds4 b;
+        b.x0 = clampi(ca0 + sClo[kx], 0, g.w - 1) + o.x;
+        b.x1 = clampi(ca0 + sChi[kx], 0, g.w - 1) + o.x;
+        b.y0 = clampi(ra0 + sRlo[ky], 0, g.h - 1) + o.y;
+        b.y1 = clampi(ra0 + sRhi[ky], 0, g.h - 1) + o.y;
+        sTB[k] = b;
+        acc.x0 = min(acc.x0, b.x0);
+        acc.x1 = max(acc.x1, b.x1);
+        acc.y0 = min(acc.y0, b.y0);
+        acc.y1 = max(acc.y1, b.y1);
+      }
+      acc.x0 = wave_min(acc.x0);
+      acc.x1 = -wave_min(-acc.x1);
+      acc.y0 = wave_min(acc.y0);
+      acc.y1 = -wave_min(-acc.y1);
+      if (tid == 0) {
+        sRed[0] = acc.x0;
+        sRed[1] = -acc.x1;
+        sRed[2] = acc.y0;
+        sRed[3] = -acc.y1;
+      }
     }
     __syncthreads();
     bool whole = true;
@@ -248,11 +271,10 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
           const int kt = (sTyR[rr] - tyA) * ntx + (sTxR[cc] - txA);
           if (!whole && kt != seg) continue;
           const int I = clampi(ra0 + rr, 0, g.h - 1), J = clampi(ca0 + cc, 0, g.w - 1);
-          const float2 v = sV[kt];
-          const double hx = (double)J + (double)v.x * 0.5, hy = (double)I + (double)v.y * 0.5;
-          const double fhx = floor(hx), fhy = floor(hy);
-          const float fx = (float)(hx - fhx), fy = (float)(hy - fhy);
-          const int ya = ((int)fhy - mr0) * mw + ((int)fhx - mc0);
+          const int2 o = sO[kt];
+          const float2 fr = sF[kt];
+          const float fx = fr.x, fy = fr.y;
+          const int ya = (I + o.y - mr0) * mw + (J + o.x - mc0);
           float num = 0.f;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
