@@ -443,8 +443,16 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
   }
 }
 
+// Minimum resident waves per SIMD (the second launch bound), i.e. the VGPR
+// budget: 4 (128 VGPRs) when a thread keeps at most four pixel rows of
+// accumulators, 2 (256) otherwise.
 template <int MH, int THREADS>
-__global__ __launch_bounds__(THREADS, (MH / (THREADS / 64) <= 4) ? 4 : 2) void k_merge(
+constexpr int waves_per_simd() {
+  return (MH / (THREADS / 64) <= 4) ? 4 : 2;
+}
+
+template <int MH, int THREADS>
+__global__ __launch_bounds__(THREADS, (waves_per_simd<MH, THREADS>())) void k_merge(
     const uint16_t* __restrict__ frames, const float* __restrict__ motion,
     const float* __restrict__ rmin, Geometry g, MergeConsts mc, float* __restrict__ out) {
   __shared__ MergeSmem<MH> sm;
@@ -464,7 +472,7 @@ __global__ __launch_bounds__(256, 2) void k_merge_save(
 // until the list is exhausted; every workgroup leaves the loop once the
 // counter passes the item count.
 template <int MH, int THREADS>
-__global__ __launch_bounds__(THREADS, (MH / (THREADS / 64) <= 4) ? 4 : 2) void k_merge_batch(
+__global__ __launch_bounds__(THREADS, (waves_per_simd<MH, THREADS>())) void k_merge_batch(
     const BurstArgs* __restrict__ bursts, const WorkItem* __restrict__ items, int n_items,
     int* __restrict__ counter) {
   __shared__ MergeSmem<MH> sm;
