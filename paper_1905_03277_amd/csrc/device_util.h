@@ -20,4 +20,15 @@ __device__ __forceinline__ int wave_min(int v) {
 // every k < 2^16.
 __device__ __forceinline__ int split_row(int k, float inv) { return (int)(((float)k + 0.5f) * inv); }
 
+// Workgroups of a launch are dispatched round-robin over the XCDs, each with
+// its own L2. Tile of linear workgroup id b among n: XCD x = b % XCDS takes a
+// contiguous run of tiles (row-major), so neighbouring tiles, which share
+// footprint halos, meet in the same L2. A bijection on [0, n).
+constexpr int XCDS = 8;
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int q = n / XCDS, r = n - q * XCDS;
+  const int x = b % XCDS, l = b / XCDS;
+  return x * q + min(x, r) + l;
+}
+
 }  // namespace hmfsr

@@ -456,7 +456,9 @@ __global__ __launch_bounds__(THREADS, (waves_per_simd<MH, THREADS>())) void k_me
     const uint16_t* __restrict__ frames, const float* __restrict__ motion,
     const float* __restrict__ rmin, Geometry g, MergeConsts mc, float* __restrict__ out) {
   __shared__ MergeSmem<MH> sm;
-  merge_tile<MH, THREADS, false>(frames, motion, rmin, g, mc, out, nullptr, blockIdx.x, blockIdx.y, sm);
+  const int tiles_x = (g.OW + MW - 1) / MW, n = tiles_x * ((g.OH + MH - 1) / MH);
+  const int t = xcd_tile(blockIdx.x, n);
+  merge_tile<MH, THREADS, false>(frames, motion, rmin, g, mc, out, nullptr, t % tiles_x, t / tiles_x, sm);
 }
 
 // Forward that also keeps the normaliser for the adjoint (float64 accumulation).
@@ -465,7 +467,9 @@ __global__ __launch_bounds__(256, 2) void k_merge_save(
     const float* __restrict__ rmin, Geometry g, MergeConsts mc, float* __restrict__ out,
     float* __restrict__ saved) {
   __shared__ MergeSmem<16> sm;
-  merge_tile<16, 256, true>(frames, motion, rmin, g, mc, out, saved, blockIdx.x, blockIdx.y, sm);
+  const int tiles_x = (g.OW + MW - 1) / MW, n = tiles_x * ((g.OH + 15) / 16);
+  const int t = xcd_tile(blockIdx.x, n);
+  merge_tile<16, 256, true>(frames, motion, rmin, g, mc, out, saved, t % tiles_x, t / tiles_x, sm);
 }
 
 // Persistent form: workgroups pull (burst, tile) items from a global counter
@@ -492,7 +496,7 @@ __global__ __launch_bounds__(THREADS, (waves_per_simd<MH, THREADS>())) void k_me
 template <int MH, int THREADS>
 hipError_t launch_variant(const Geometry& g, const MergeConsts& mc, const uint16_t* frames,
                           const float* motion, const float* rmin, float* out, hipStream_t stream) {
-  const dim3 grid((g.OW + MW - 1) / MW, (g.OH + MH - 1) / MH);
+  const dim3 grid(((g.OW + MW - 1) / MW) * ((g.OH + MH - 1) / MH));
   hipLaunchKernelGGL((k_merge<MH, THREADS>), grid, dim3(THREADS), 0, stream, frames, motion, rmin, g,
                      mc, out);
   return hipGetLastError();
@@ -517,7 +521,7 @@ hipError_t launch_merge(int variant, const Geometry& g, const MergeConsts& mc, c
                         const float* motion, const float* rmin, float* out, float* saved,
                         hipStream_t stream) {
   if (saved) {  // one tile shape keeps the normaliser
-    const dim3 grid((g.OW + MW - 1) / MW, (g.OH + 15) / 16);
+    const dim3 grid(((g.OW + MW - 1) / MW) * ((g.OH + 15) / 16));
     hipLaunchKernelGGL(k_merge_save, grid, dim3(256), 0, stream, frames, motion, rmin, g, mc, out, saved);
     return hipGetLastError();
   }

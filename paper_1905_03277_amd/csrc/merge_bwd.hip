@@ -93,8 +93,8 @@ __global__ __launch_bounds__(BTHREADS, 2) void k_merge_bwd(
     double* __restrict__ part_theta, double* __restrict__ part_mo, float* __restrict__ part_rh) {
   __shared__ BwdSmem sm;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tile_x = blockIdx.x, tile_y = blockIdx.y;
-  const int tile = tile_y * bc.tiles_x + tile_x;
+  const int tile = xcd_tile(blockIdx.x, bc.n_tiles);
+  const int tile_x = tile % bc.tiles_x, tile_y = tile / bc.tiles_x;
   const int C0 = tile_x * MW, R0 = tile_y * BMH;
   const int ncol = min(MW, g.OW - C0), nrow = min(BMH, g.OH - R0);
 
@@ -931,7 +931,7 @@ hipError_t launch_merge_bwd(const Geometry& g, const MergeConsts& mc, const BwdC
                             const uint16_t* frames, const float* motion, const float* rmin,
                             const float* saved, const float* grad_out, const BwdWork& w,
                             hipStream_t stream) {
-  const dim3 grid(bc.tiles_x, bc.tiles_y);
+  const dim3 grid(bc.n_tiles);
   hipLaunchKernelGGL(k_merge_bwd, grid, dim3(BTHREADS), 0, stream, frames, motion, rmin, saved, grad_out,
                      g, mc, bc, w.part_theta, w.part_mo, w.part_rh);
   return hipGetLastError();

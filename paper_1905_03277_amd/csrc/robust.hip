@@ -42,6 +42,9 @@ __device__ __forceinline__ void load_guide(const uint16_t* f, const Geometry& g,
   b = (float)quad_at(top, bot, g.blue_pos);
 }
 
+__host__ __device__ __forceinline__ int robust_tiles_x_(const Geometry& g) { return (g.w + RB_W - 1) / RB_W; }
+__host__ __device__ __forceinline__ int robust_tiles_y_(const Geometry& g) { return (g.h + RB_H - 1) / RB_H; }
+
 struct Bounds4 {
   int x0, x1, y0, y1;  // range of the bilinear base corner floor(u + v/2)
 };
@@ -325,7 +328,8 @@ __global__ __launch_bounds__(THREADS) void k_robust(const uint16_t* __restrict__
                                                     RobustConsts rc, float* __restrict__ rmin,
                                                     float* __restrict__ robust) {
   __shared__ RobustSmem sm;
-  robust_tile(frames, motion, s_tile, g, rc, rmin, robust, blockIdx.x, blockIdx.y, sm);
+  const int tx_n = robust_tiles_x_(g), t = xcd_tile(blockIdx.x, tx_n * robust_tiles_y_(g));
+  robust_tile(frames, motion, s_tile, g, rc, rmin, robust, t % tx_n, t / tx_n, sm);
 }
 
 // Persistent form over (burst, tile) items of a batch.
@@ -348,14 +352,14 @@ __global__ __launch_bounds__(THREADS) void k_robust_batch(const BurstArgs* __res
 
 }  // namespace
 
-int robust_tiles_x(const Geometry& g) { return (g.w + RB_W - 1) / RB_W; }
-int robust_tiles_y(const Geometry& g) { return (g.h + RB_H - 1) / RB_H; }
+int robust_tiles_x(const Geometry& g) { return robust_tiles_x_(g); }
+int robust_tiles_y(const Geometry& g) { return robust_tiles_y_(g); }
 
 hipError_t launch_robust(const Geometry& g, const RobustConsts& rc, const uint16_t* frames,
                          const float* motion, const float* s_tile, float* rmin, float* robust,
                          hipStream_t stream) {
   if (g.n < 2) return hipSuccess;
-  const dim3 grid(robust_tiles_x(g), robust_tiles_y(g));
+  const dim3 grid(robust_tiles_x(g) * robust_tiles_y(g));
   hipLaunchKernelGGL(k_robust, grid, dim3(THREADS), 0, stream, frames, motion, s_tile, g, rc, rmin,
                      robust);
   return hipGetLastError();
