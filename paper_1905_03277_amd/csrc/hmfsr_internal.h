@@ -129,6 +129,7 @@ struct BwdWork {
   double* part_mo;    // [tiles][n][kBwdVT][2] dL/dv of the alignment tiles each tile touches
   double* part_theta; // [tiles][6] dL/d(k_detail, k_denoise, d_th, d_tr, k_stretch, k_shrink), unscaled
   double* part_rob;   // [n][TY][TX][5] robustness part: dL/dvx, dL/dvy, dL/dt, dL/ds, dL/ds_motion
+  double* part_sum;   // [64][9] chunk sums of the tuning gradient
 };
 size_t bwd_bytes(const Geometry& g, bool need_saved);
 BwdWork bwd_carve(void* base, const Geometry& g, bool need_saved);

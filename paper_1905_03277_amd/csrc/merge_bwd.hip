@@ -606,28 +606,33 @@ __device__ __forceinline__ void guide_px(const uint16_t* f, const Geometry& g, i
   c[2] = (float)q[g.blue_pos];
 }
 
-// 3x3 box mean of the guide around (I, J), edge-clamped; optionally the
-// population variance too.
-__device__ __forceinline__ void box3(const uint16_t* f, const Geometry& g, int I, int J, float (&mu)[3],
-                                     float (*var)[3]) {
-  float v[9][3];
-#pragma unroll
+// 3x3 box mean of the guide around (I, J), edge-clamped.
+__device__ __forceinline__ void box3(const uint16_t* f, const Geometry& g, int I, int J, float (&mu)[3]) {
+  float s[3] = {0.f, 0.f, 0.f};
   for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      float c[3];
+      guide_px(f, g, clampi(I + a - 1, 0, g.h - 1), clampi(J + b - 1, 0, g.w - 1), c);
 #pragma unroll
-    for (int b = 0; b < 3; ++b) guide_px(f, g, clampi(I + a - 1, 0, g.h - 1), clampi(J + b - 1, 0, g.w - 1), v[a * 3 + b]);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    float s = 0.f;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) s += v[q][c];
-    mu[c] = s * (1.f / 9.f);
-    if (var) {
-      float sv = 0.f;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) sv = fmaf(v[q][c] - mu[c], v[q][c] - mu[c], sv);
-      (*var)[c] = sv * (1.f / 9.f);
+      for (int k = 0; k < 3; ++k) s[k] += c[k];
     }
-  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) mu[k] = s[k] * (1.f / 9.f);
+}
+
+// Its population variance about mu, summed in the same order as the forward.
+__device__ __forceinline__ void box3_var(const uint16_t* f, const Geometry& g, int I, int J,
+                                         const float (&mu)[3], float (&var)[3]) {
+  float s[3] = {0.f, 0.f, 0.f};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      float c[3];
+      guide_px(f, g, clampi(I + a - 1, 0, g.h - 1), clampi(J + b - 1, 0, g.w - 1), c);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s[k] = fmaf(c[k] - mu[k], c[k] - mu[k], s[k]);
+    }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) var[k] = s[k] * (1.f / 9.f);
 }
 
 __global__ __launch_bounds__(64) void k_robust_bwd(const uint16_t* __restrict__ frames,
@@ -732,7 +737,8 @@ __global__ __launch_bounds__(64) void k_robust_bwd(const uint16_t* __restrict__ 
         const float Rv = sR[i - bi0 + 4][j - bj0 + 4];
         if (gR != 0.f && Rv > 0.f && Rv < 1.f) {  // unclamped R of eq. (5)
           float mu_ref[3], var_ref[3];
-          box3(fref, g, i, j, mu_ref, &var_ref);
+          box3(fref, g, i, j, mu_ref);
+          box3_var(fref, g, i, j, mu_ref, var_ref);
           float den = 0.f;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
@@ -746,18 +752,30 @@ __global__ __launch_bounds__(64) void k_robust_bwd(const uint16_t* __restrict__ 
           const float fx = (float)(hx - fhx), fy = (float)(hy - fhy);
           const int xa = clampi((int)fhx, 0, g.w - 1), xb = clampi((int)fhx + 1, 0, g.w - 1);
           const int ya = clampi((int)fhy, 0, g.h - 1), yb = clampi((int)fhy + 1, 0, g.h - 1);
-          float m00[3], m01[3], m10[3], m11[3];
-          box3(fn, g, ya, xa, m00, nullptr);
-          box3(fn, g, ya, xb, m01, nullptr);
-          box3(fn, g, yb, xa, m10, nullptr);
-          box3(fn, g, yb, xb, m11, nullptr);
+          float top[3], bot[3], dtop[3], dbot[3];
+          {
+            float ma[3], mb[3];
+            box3(fn, g, ya, xa, ma);
+            box3(fn, g, ya, xb, mb);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              dtop[c] = mb[c] - ma[c];
+              top[c] = fmaf(fx, dtop[c], ma[c]);
+            }
+            box3(fn, g, yb, xa, ma);
+            box3(fn, g, yb, xb, mb);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              dbot[c] = mb[c] - ma[c];
+              bot[c] = fmaf(fx, dbot[c], ma[c]);
+            }
+          }
           float num = 0.f, dd[3], ddp[3], dmx[3], dmy[3];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const float top = fmaf(fx, m01[c] - m00[c], m00[c]), bot = fmaf(fx, m11[c] - m10[c], m10[c]);
-            const float mu_w = fmaf(fy, bot - top, top);
-            dmx[c] = fmaf(fy, (m11[c] - m10[c]) - (m01[c] - m00[c]), m01[c] - m00[c]);
-            dmy[c] = bot - top;
+            const float mu_w = fmaf(fy, bot[c] - top[c], top[c]);
+            dmx[c] = fmaf(fy, dbot[c] - dtop[c], dtop[c]);
+            dmy[c] = bot[c] - top[c];
             float var = fmaf(rc.a_r, fmaxf(mu_ref[c] - rc.black, 0.f), rc.b_r);
             if (c == 1) var *= 0.5f;
             const float dmd2 = var * (2.f / 9.f);
@@ -847,18 +865,26 @@ __global__ void k_grad_motion(const double* __restrict__ part_mo, const double* 
   out[1] = (float)(sy + rob[1]);
 }
 
-__global__ __launch_bounds__(256) void k_grad_tuning(const double* __restrict__ part_theta, int n_tiles,
-                                                     const double* __restrict__ part_rob, int n_rob,
-                                                     BwdConsts bc, float* __restrict__ grad_tuning) {
+// Tuning-gradient sums in two fixed-order stages: workgroup b adds the
+// contiguous chunk b of the per-tile and per-(frame, tile) partials, then one
+// workgroup adds the chunk sums in order and applies the factors left out of
+// the per-tile sums.
+constexpr int kSumGroups = 64;
+
+__global__ __launch_bounds__(256) void k_grad_tuning_part(const double* __restrict__ part_theta, int n_tiles,
+                                                          const double* __restrict__ part_rob, int n_rob,
+                                                          double* __restrict__ part_sum) {
   __shared__ double sS[4][9];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, b = blockIdx.x;
+  const int ct = (n_tiles + kSumGroups - 1) / kSumGroups, cr = (n_rob + kSumGroups - 1) / kSumGroups;
+  const int t0 = b * ct, t1 = min(n_tiles, t0 + ct), r0 = b * cr, r1 = min(n_rob, r0 + cr);
   double a[9];
 #pragma unroll
   for (int e = 0; e < 9; ++e) a[e] = 0.0;
-  for (int t = tid; t < n_tiles; t += 256)
+  for (int t = t0 + tid; t < t1; t += 256)
 #pragma unroll
     for (int e = 0; e < 6; ++e) a[e] += part_theta[(size_t)t * 6 + e];
-  for (int t = tid; t < n_rob; t += 256) {
+  for (int t = r0 + tid; t < r1; t += 256) {
     const double* r = part_rob + (size_t)t * 5;
     a[6] += r[3];
     a[7] += r[2];
@@ -870,20 +896,21 @@ __global__ __launch_bounds__(256) void k_grad_tuning(const double* __restrict__ 
     if (lane == 0) sS[wave][e] = v;
   }
   __syncthreads();
-  if (tid == 0) {
-    double s[9];
-    for (int e = 0; e < 9; ++e) s[e] = ((sS[0][e] + sS[1][e]) + sS[2][e]) + sS[3][e];
-    // sigma_1,2 are proportional to k_detail; the other factors were left out of the sums
-    grad_tuning[0] = (float)(s[0] / bc.kd);
-    grad_tuning[1] = (float)(s[1] * bc.kd);
-    grad_tuning[2] = (float)(s[2] * bc.kd);
-    grad_tuning[3] = (float)(s[3] * bc.kd);
-    grad_tuning[4] = (float)(s[4] * bc.kd);
-    grad_tuning[5] = (float)(-s[5] * bc.kd / (bc.ksh * bc.ksh));
-    grad_tuning[6] = (float)s[6];
-    grad_tuning[7] = (float)s[7];
-    grad_tuning[8] = (float)s[8];
-  }
+  if (tid < 9) part_sum[b * 9 + tid] = ((sS[0][tid] + sS[1][tid]) + sS[2][tid]) + sS[3][tid];
+}
+
+__global__ __launch_bounds__(64) void k_grad_tuning(const double* __restrict__ part_sum, BwdConsts bc,
+                                                    float* __restrict__ grad_tuning) {
+  const int e = threadIdx.x;
+  if (e >= 9) return;
+  double s = 0.0;
+  for (int b = 0; b < kSumGroups; ++b) s += part_sum[b * 9 + e];
+  // sigma_1,2 are proportional to k_detail; the other factors were left out of the sums
+  double g = s;
+  if (e == 0) g = s / bc.kd;
+  else if (e <= 4) g = s * bc.kd;
+  else if (e == 5) g = -s * bc.kd / (bc.ksh * bc.ksh);
+  grad_tuning[e] = (float)g;
 }
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
@@ -900,6 +927,7 @@ size_t bwd_bytes(const Geometry& g, bool need_saved) {
   b += align256(tiles * g.n * kBwdVT * 2 * sizeof(double));
   b += align256(tiles * 6 * sizeof(double));
   b += align256((size_t)g.n * g.TY * g.TX * 5 * sizeof(double));
+  b += align256((size_t)kSumGroups * 9 * sizeof(double));
   return b;
 }
 
@@ -924,6 +952,8 @@ BwdWork bwd_carve(void* base, const Geometry& g, bool need_saved) {
   w.part_theta = (double*)p;
   p += align256(tiles * 6 * sizeof(double));
   w.part_rob = (double*)p;
+  p += align256((size_t)g.n * g.TY * g.TX * 5 * sizeof(double));
+  w.part_sum = (double*)p;
   return w;
 }
 
@@ -953,8 +983,11 @@ hipError_t launch_grad_reduce(const Geometry& g, const BwdConsts& bc, const BwdW
                      g, bc, grad_motion);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_grad_tuning, dim3(1), dim3(256), 0, stream, w.part_theta, bc.n_tiles, w.part_rob,
-                     total, bc, grad_tuning);
+  hipLaunchKernelGGL(k_grad_tuning_part, dim3(kSumGroups), dim3(256), 0, stream, w.part_theta, bc.n_tiles,
+                     w.part_rob, total, w.part_sum);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grad_tuning, dim3(1), dim3(64), 0, stream, w.part_sum, bc, grad_tuning);
   return hipGetLastError();
 }
 
