@@ -635,7 +635,7 @@ __device__ __forceinline__ void box3_var(const uint16_t* f, const Geometry& g, i
   for (int k = 0; k < 3; ++k) var[k] = s[k] * (1.f / 9.f);
 }
 
-__global__ __launch_bounds__(64) void k_robust_bwd(const uint16_t* __restrict__ frames,
+__global__ __launch_bounds__(64, 4) void k_robust_bwd(const uint16_t* __restrict__ frames,
                                                    const float* __restrict__ motion,
                                                    const float* __restrict__ rmap,
                                                    const float* __restrict__ part_rh, Geometry g,
