@@ -110,7 +110,7 @@ hipError_t launch_omega_map(const Geometry& g, const OmegaConsts& oc, const uint
 // ---- adjoint ---------------------------------------------------------------
 
 // Output tile of the adjoint kernel: 64 x kBwdRows pixels.
-constexpr int kBwdRows = 16;
+constexpr int kBwdRows = 8;
 constexpr int kBwdVT = (64 / 8 + 2) * (kBwdRows / 8 + 2);   // alignment tiles per output tile, max
 constexpr int kBwdRH = (64 / 2 + 2) * (kBwdRows / 2 + 2);   // R_hat window cells per output tile, max
 

@@ -86,7 +86,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;  // lane 0 holds the sum, always added in the same order
 }
 
-__global__ __launch_bounds__(BTHREADS, 2) void k_merge_bwd(
+__global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
     const uint16_t* __restrict__ frames, const float* __restrict__ motion,
     const float* __restrict__ rmin, const float* __restrict__ saved,
     const float* __restrict__ grad_out, Geometry g, MergeConsts mc, BwdConsts bc,
