@@ -484,12 +484,16 @@ __global__ __launch_bounds__(THREADS, (waves_per_simd<MH, THREADS>())) void k_me
     __syncthreads();
     if (threadIdx.x == 0) sm.sItem = atomicAdd(counter, 1);
     __syncthreads();
-    const int it = sm.sItem;
+    // uniform across the workgroup: the item and its burst's arguments load
+    // through the scalar unit into SGPRs
+    const int it = __builtin_amdgcn_readfirstlane(sm.sItem);
     if (it >= n_items) break;
     const WorkItem w = items[it];
-    const BurstArgs& b = bursts[w.burst];
-    const int tx = w.tile % b.merge_tiles_x, ty = w.tile / b.merge_tiles_x;
-    merge_tile<MH, THREADS, false>(b.frames, b.motion, b.rmin, b.g, b.mc, b.out, nullptr, tx, ty, sm);
+    const BurstArgs* b = bursts + w.burst;
+    const Geometry g = b->g;
+    const MergeConsts mc = b->mc;
+    const int tx = w.tile % b->merge_tiles_x, ty = w.tile / b->merge_tiles_x;
+    merge_tile<MH, THREADS, false>(b->frames, b->motion, b->rmin, g, mc, b->out, nullptr, tx, ty, sm);
   }
 }
 

@@ -341,7 +341,7 @@ __global__ __launch_bounds__(THREADS) void k_robust_batch(const BurstArgs* __res
     __syncthreads();
     if (threadIdx.x == 0) sm.sItem = atomicAdd(counter, 1);
     __syncthreads();
-    const int it = sm.sItem;
+    const int it = __builtin_amdgcn_readfirstlane(sm.sItem);  // uniform: scalar loads below
     if (it >= n_items) break;
     const WorkItem w = items[it];
     const BurstArgs& b = bursts[w.burst];
