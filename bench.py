@@ -8,9 +8,10 @@ kernel's roofline position and the FP64 oracle's CPU rate on a bounded sample.
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
                     [--no-batch] [--no-grad]
 
-Two more legs follow the headline line's measurement and are reported inside
-it: the 64-burst batched workload (one graph replay vs per-burst launches) and
-the differentiation workload (16 bursts of 8 x 768 x 1024 at scale 2, forward
+More legs follow the headline measurement and are reported inside its line:
+the same burst merged frame by frame through the streaming calls, the
+64-burst batched workload (one graph replay vs per-burst launches) and the
+differentiation workload (16 bursts of 8 x 768 x 1024 at scale 2, forward
 plus adjoint).
 """
 import argparse
@@ -196,6 +197,41 @@ def bench_batch(dev, reps: int = 3) -> dict:
             "tuned_shapes": {f"{k[0]}/{k[1]}": v for k, v in tuned.items()}}
 
 
+def bench_stream(burst, out, reps: int = 5) -> dict:
+    """The 12 MP x 8 burst merged through the streaming calls: the base frame,
+    then one call per aligned frame into a fixed [9][OH][OW] state, then the
+    normalisation (each add copies its two frames into the library's
+    workspace)."""
+    import torch
+    from paper_1905_03277_amd import torch_ops
+
+    d = burst.desc
+    frames = [burst.frames[k] for k in range(d.n_frames)]
+    motion = [burst.motion[k].contiguous() for k in range(d.n_frames)]
+
+    def run():
+        sm = torch_ops.StreamingMerge(frames[d.ref_frame], d, burst.tuning)
+        for k in range(d.n_frames):
+            if k != d.ref_frame:
+                sm.add(frames[k], motion[k])
+        sm.result(out)
+
+    stream = torch.cuda.current_stream()
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    in_mp = d.n_frames * d.height * d.width / 1e6
+    return {"workload": "the 12 MP x 8 burst added frame by frame", "ms": round(ms, 3),
+            "MPs": round(in_mp / (ms / 1e3), 1),
+            "state_bytes": 9 * 4 * d.out_height * d.out_width}
+
+
 def bench_grad(dev, reps: int = 3) -> dict:
     """The differentiation workload: 16 bursts of 8 x 768 x 1024 RGGB at scale 2.
     One pass = for every burst, the forward merge (keeping the normaliser of
@@ -347,6 +383,7 @@ def main():
                 "frac": round(byts["total"] / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "wall_s_timed": round(wall, 3),
     }
+    line["streaming"] = bench_stream(burst, out)
     if not args.no_batch:
         line["batched"] = bench_batch(dev)
     if not args.no_grad:

@@ -159,6 +159,35 @@ hmfsr_status hmfsr_merge_backward(const hmfsr_desc* desc, const hmfsr_tuning* tu
                                   float* grad_tuning, float* grad_motion, void* stream);
 
 /*
+ * Streaming merge -- frames added one call at a time into a caller-owned
+ * accumulator state, so that memory does not grow with the frame count (the
+ * paper's online merge, Sec. 5.1 and 6.5). The result equals hmfsr_merge's
+ * with the 64 x 16 tile shape bit for bit when the frames are added in the
+ * order hmfsr_merge visits them (base frame, then the others in index order).
+ *  state  DEVICE float32 [9][out_height][out_width], caller-owned: per
+ *         channel the numerator and denominator of eq. (1) (raw units, scaled
+ *         by 2^-m) and the reference exponent m.
+ * The descriptor's n_frames and ref_frame are not used; the other fields,
+ * the tuning and the frame layout are as for hmfsr_merge.
+ *
+ * hmfsr_stream_begin -- initialise `state` with the base frame (weight 1).
+ * hmfsr_stream_add   -- add one aligned frame: `frame` DEVICE uint16 [H][W],
+ *                       `motion` DEVICE float32 [TY][TX][2] (its tile
+ *                       displacements), `base_frame` the same base frame as
+ *                       for begin (its statistics drive the robustness, eq.
+ *                       5-9). The frames are copied into a library workspace
+ *                       of two frames; calls on one device must share a stream.
+ * hmfsr_stream_end   -- normalise `state` into `out` (eq. 1), as hmfsr_merge.
+ */
+hmfsr_status hmfsr_stream_begin(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
+                                const uint16_t* base_frame, float* state, void* stream);
+hmfsr_status hmfsr_stream_add(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
+                              const uint16_t* base_frame, const uint16_t* frame,
+                              const float* motion, float* state, void* stream);
+hmfsr_status hmfsr_stream_end(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
+                              const float* state, float* out, void* stream);
+
+/*
  * hmfsr_merge_maps -- the per-frame intermediate maps of the merge, for
  * inspection (the paper visualises the accumulated robustness mask and the
  * kernel shapes). Same inputs as hmfsr_merge; h = height/2, w = width/2.

@@ -17,9 +17,10 @@ LIB_PATH = os.path.join(_HERE, "libhmfsr.so")
 HMFSR_OK, HMFSR_E_INVALID, HMFSR_E_UNSUPPORTED, HMFSR_E_HIP, HMFSR_E_NOMEM = 0, -1, -2, -3, -4
 
 # Every symbol include/hmfsr.h declares.
-EXPORTED = ("hmfsr_merge", "hmfsr_merge_backward", "hmfsr_merge_maps", "hmfsr_merge_batch",
-            "hmfsr_autotune", "hmfsr_profile_begin", "hmfsr_profile_end", "hmfsr_strerror",
-            "hmfsr_version", "hmfsr_release")
+EXPORTED = ("hmfsr_merge", "hmfsr_merge_backward", "hmfsr_stream_begin", "hmfsr_stream_add",
+            "hmfsr_stream_end", "hmfsr_merge_maps", "hmfsr_merge_batch", "hmfsr_autotune",
+            "hmfsr_profile_begin", "hmfsr_profile_end", "hmfsr_strerror", "hmfsr_version",
+            "hmfsr_release")
 
 STAGE_PRIOR, STAGE_ROBUST, STAGE_MERGE, STAGE_BATCH = 0, 1, 2, 3
 STAGE_MERGE_BWD, STAGE_ROBUST_BWD, STAGE_GRAD_REDUCE = 4, 5, 6
@@ -75,6 +76,12 @@ def lib() -> ctypes.CDLL:
         L.hmfsr_merge.restype = i32
         L.hmfsr_merge_backward.argtypes = [pd, pt, vp, vp, vp, vp, vp, vp, vp]
         L.hmfsr_merge_backward.restype = i32
+        L.hmfsr_stream_begin.argtypes = [pd, pt, vp, vp, vp]
+        L.hmfsr_stream_begin.restype = i32
+        L.hmfsr_stream_add.argtypes = [pd, pt, vp, vp, vp, vp, vp]
+        L.hmfsr_stream_add.restype = i32
+        L.hmfsr_stream_end.argtypes = [pd, pt, vp, vp, vp]
+        L.hmfsr_stream_end.restype = i32
         L.hmfsr_merge_maps.argtypes = [pd, pt, vp, vp, vp, vp, vp, vp, vp]
         L.hmfsr_merge_maps.restype = i32
         L.hmfsr_merge_batch.argtypes = [i32, pd, pt, ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -126,6 +133,22 @@ def hmfsr_merge_backward(desc: hmfsr_desc, tuning: hmfsr_tuning, frames: int, mo
     _check(lib().hmfsr_merge_backward(ctypes.byref(desc), ctypes.byref(tuning), frames, motion,
                                       saved or None, grad_out, grad_tuning, grad_motion,
                                       stream or None), "hmfsr_merge_backward")
+
+
+def hmfsr_stream_begin(desc, tuning, base_frame: int, state: int, stream: int = 0) -> None:
+    _check(lib().hmfsr_stream_begin(ctypes.byref(desc), ctypes.byref(tuning), base_frame, state,
+                                    stream or None), "hmfsr_stream_begin")
+
+
+def hmfsr_stream_add(desc, tuning, base_frame: int, frame: int, motion: int, state: int,
+                     stream: int = 0) -> None:
+    _check(lib().hmfsr_stream_add(ctypes.byref(desc), ctypes.byref(tuning), base_frame, frame, motion,
+                                  state, stream or None), "hmfsr_stream_add")
+
+
+def hmfsr_stream_end(desc, tuning, state: int, out: int, stream: int = 0) -> None:
+    _check(lib().hmfsr_stream_end(ctypes.byref(desc), ctypes.byref(tuning), state, out, stream or None),
+           "hmfsr_stream_end")
 
 
 def hmfsr_merge_maps(desc, tuning, frames: int, motion: int, omega: int, robust: int,

@@ -178,6 +178,10 @@ hmfsr_status bwd_workspace(int dev, size_t bytes, hipStream_t stream, void** out
   return grow(g_dev[dev].bwd_ws, g_dev[dev].bwd_ws_bytes, bytes, stream, out);
 }
 
+hmfsr_status stream_workspace(int dev, size_t bytes, hipStream_t stream, void** out) {
+  return grow(g_dev[dev].stream_ws, g_dev[dev].stream_ws_bytes, bytes, stream, out);
+}
+
 hmfsr_status run_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, const Geometry& g,
                        const uint16_t* frames, const float* motion, float* out, float* saved,
                        const Work& w, int variant, hipStream_t s) {
@@ -218,6 +222,82 @@ hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, con
   hipStream_t s = (hipStream_t)stream;
   if ((st = workspace(dev, work_bytes(g), s, &ws)) != HMFSR_OK) return st;
   return run_merge(desc, tuning, g, frames, motion, out, saved, work_carve(ws, g), merge_variant(g), s);
+}
+
+hmfsr_status hmfsr_stream_begin(const hmfsr_desc* desc, const hmfsr_tuning* tuning, const uint16_t* base_frame,
+                                float* state, void* stream) {
+  hmfsr_status st = validate(desc, tuning);
+  if (st != HMFSR_OK) return st;
+  if (!base_frame || !state || ((uintptr_t)base_frame & 3) || ((uintptr_t)state & 3)) return HMFSR_E_INVALID;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  int dev = 0;
+  if ((st = current_device(&dev)) != HMFSR_OK) return st;
+  Geometry g = make_geometry(desc);
+  g.n = 1;
+  g.ref = 0;
+  hipStream_t s = (hipStream_t)stream;
+  // the base frame alone: its weights are 1 and it reads no motion or R_hat
+  return timed(HMFSR_STAGE_MERGE, s, [&] {
+           return launch_merge_stream(g, make_merge(desc, tuning, g), base_frame, nullptr, nullptr, nullptr,
+                                      state, 0, s);
+         }) == hipSuccess
+             ? HMFSR_OK
+             : HMFSR_E_HIP;
+}
+
+hmfsr_status hmfsr_stream_add(const hmfsr_desc* desc, const hmfsr_tuning* tuning, const uint16_t* base_frame,
+                              const uint16_t* frame, const float* motion, float* state, void* stream) {
+  hmfsr_status st = validate(desc, tuning);
+  if (st != HMFSR_OK) return st;
+  if (!base_frame || !frame || !motion || !state) return HMFSR_E_INVALID;
+  for (const void* p : {(const void*)base_frame, (const void*)frame, (const void*)motion, (const void*)state})
+    if ((uintptr_t)p & 3) return HMFSR_E_INVALID;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  int dev = 0;
+  if ((st = current_device(&dev)) != HMFSR_OK) return st;
+  // a two-frame view [base, frame] in the library's stream workspace
+  Geometry g = make_geometry(desc);
+  g.n = 2;
+  g.ref = 0;
+  const size_t fbytes = (size_t)g.H * g.W * sizeof(uint16_t);
+  const size_t mbytes = (size_t)g.TY * g.TX * 2 * sizeof(float);
+  const size_t off_m = (2 * fbytes + 255) / 256 * 256, off_w = off_m + (2 * mbytes + 255) / 256 * 256;
+  hipStream_t s = (hipStream_t)stream;
+  void* ws = nullptr;
+  if ((st = stream_workspace(dev, off_w + work_bytes(g), s, &ws)) != HMFSR_OK) return st;
+  uint16_t* frames = (uint16_t*)ws;
+  float* mo = (float*)((char*)ws + off_m);
+  const Work w = work_carve((char*)ws + off_w, g);
+  if (hipMemcpyAsync(frames, base_frame, fbytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(frames + (size_t)g.H * g.W, frame, fbytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync((char*)mo + mbytes, motion, mbytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return HMFSR_E_HIP;
+  const PriorConsts pc = make_prior(tuning);
+  const RobustConsts rc = make_robust(desc, tuning);
+  const MergeConsts mc = make_merge(desc, tuning, g);
+  if (timed(HMFSR_STAGE_PRIOR, s, [&] { return launch_prior(g, pc, mo, w.s_tile, s); }) != hipSuccess ||
+      timed(HMFSR_STAGE_ROBUST, s, [&] {
+        return launch_robust(g, rc, frames, mo, w.s_tile, w.rmin, nullptr, s);
+      }) != hipSuccess ||
+      timed(HMFSR_STAGE_MERGE, s, [&] {
+        return launch_merge_stream(g, mc, frames, mo, w.rmin, state, state, 1, s);
+      }) != hipSuccess)
+    return HMFSR_E_HIP;
+  return HMFSR_OK;
+}
+
+hmfsr_status hmfsr_stream_end(const hmfsr_desc* desc, const hmfsr_tuning* tuning, const float* state, float* out,
+                              void* stream) {
+  hmfsr_status st = validate(desc, tuning);
+  if (st != HMFSR_OK) return st;
+  if (!state || !out || ((uintptr_t)state & 3) || ((uintptr_t)out & 3)) return HMFSR_E_INVALID;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  int dev = 0;
+  if ((st = current_device(&dev)) != HMFSR_OK) return st;
+  const Geometry g = make_geometry(desc);
+  return launch_stream_finish(g, make_merge(desc, tuning, g), state, out, (hipStream_t)stream) == hipSuccess
+             ? HMFSR_OK
+             : HMFSR_E_HIP;
 }
 
 hmfsr_status hmfsr_merge_backward(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
@@ -365,7 +445,8 @@ void hmfsr_release(void) {
   const bool have_cur = hipGetDevice(&cur) == hipSuccess;
   for (int d = 0; d < kMaxDevices; ++d) {
     DeviceState& st = g_dev[d];
-    if (!st.workspace && !st.batch_ws && !st.bwd_ws && !st.plan.exec && !st.capture_stream) continue;
+    if (!st.workspace && !st.batch_ws && !st.bwd_ws && !st.stream_ws && !st.plan.exec && !st.capture_stream)
+      continue;
     if (hipSetDevice(d) != hipSuccess) continue;
     if (st.plan.exec) hipGraphExecDestroy(st.plan.exec);
     if (st.plan.graph) hipGraphDestroy(st.plan.graph);
@@ -373,6 +454,9 @@ void hmfsr_release(void) {
     if (st.workspace) hipFree(st.workspace);
     if (st.batch_ws) hipFree(st.batch_ws);
     if (st.bwd_ws) hipFree(st.bwd_ws);
+    if (st.stream_ws) hipFree(st.stream_ws);
+    st.stream_ws = nullptr;
+    st.stream_ws_bytes = 0;
     if (st.capture_stream) hipStreamDestroy(st.capture_stream);
     st.workspace = st.batch_ws = st.bwd_ws = nullptr;
     st.workspace_bytes = st.batch_ws_bytes = st.bwd_ws_bytes = 0;

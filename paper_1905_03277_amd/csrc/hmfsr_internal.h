@@ -98,6 +98,14 @@ hipError_t launch_robust_batch(const BurstArgs* bursts, const WorkItem* items, i
 hipError_t launch_prior_batch(const BurstArgs* bursts, const int* first, int n_bursts, int total,
                               hipStream_t stream);
 int merge_tile_rows(int variant);
+// Streaming merge (64 x 16 tiles): frames from loop index `first` on are added
+// to the accumulator state [9][OH][OW] (numerator, denominator, reference
+// exponent per channel); state_in nullable (empty accumulators).
+hipError_t launch_merge_stream(const Geometry& g, const MergeConsts& mc, const uint16_t* frames,
+                               const float* motion, const float* rmin, const float* state_in, float* state_out,
+                               int first, hipStream_t stream);
+hipError_t launch_stream_finish(const Geometry& g, const MergeConsts& mc, const float* state, float* out,
+                                hipStream_t stream);
 int merge_batch_blocks_per_cu(int variant);
 int robust_batch_blocks_per_cu();
 int robust_tiles_x(const Geometry& g);

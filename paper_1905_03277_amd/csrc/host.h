@@ -30,6 +30,8 @@ struct DeviceState {
   size_t batch_ws_bytes = 0;
   void* bwd_ws = nullptr;     // adjoint workspace
   size_t bwd_ws_bytes = 0;
+  void* stream_ws = nullptr;  // streaming merge: two-frame view and its maps
+  size_t stream_ws_bytes = 0;
   hipStream_t capture_stream = nullptr;
   BatchPlan plan;
 };
@@ -71,6 +73,7 @@ OmegaConsts make_omega(const hmfsr_desc* d, const hmfsr_tuning* t);
 hmfsr_status current_device(int* dev_out);  // caller holds g_mutex
 hmfsr_status workspace(int dev, size_t bytes, hipStream_t stream, void** out);  // caller holds g_mutex
 hmfsr_status bwd_workspace(int dev, size_t bytes, hipStream_t stream, void** out);  // caller holds g_mutex
+hmfsr_status stream_workspace(int dev, size_t bytes, hipStream_t stream, void** out);  // caller holds g_mutex
 
 // Merge tile shape for a burst: HMFSR_MERGE_VARIANT, else the autotuned
 // choice for the burst's (scale, frame count) class, else the default.

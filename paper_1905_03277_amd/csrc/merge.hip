@@ -49,15 +49,31 @@ struct MergeSmem {
   int sItem;
 };
 
+// What a tile keeps besides the output:
+//   TILE_PLAIN   nothing;
+//   TILE_SAVE    the normaliser of eq. (1), accumulated in float64, for the adjoint;
+//   TILE_STREAM  the accumulators themselves, loaded from and stored to a
+//                caller's state, so that frames can be added one call at a time.
+enum { TILE_PLAIN = 0, TILE_SAVE = 1, TILE_STREAM = 2 };
+
+// Accumulator state of a streaming merge: [9][OH][OW] floats, per channel the
+// numerator and denominator of eq. (1) (raw units, scaled by 2^-m) and the
+// reference exponent m; `first` is the first frame (loop index) to add.
+struct StreamState {
+  const float* in;  // nullable: start from empty accumulators
+  float* out;
+  int first;
+};
+
 // One 64 x MH output tile (tile_x, tile_y) of one burst.
-// SAVE: accumulate the normaliser in float64 and store it for the adjoint.
-template <int MH, int THREADS, bool SAVE>
+template <int MH, int THREADS, int MODE>
 __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
                                            const float* __restrict__ motion,
                                            const float* __restrict__ rmin, const Geometry& g,
                                            const MergeConsts& mc, float* __restrict__ out,
-                                           float* __restrict__ saved, int tile_x, int tile_y,
-                                           MergeSmem<MH>& sm) {
+                                           float* __restrict__ saved, StreamState st, int tile_x,
+                                           int tile_y, MergeSmem<MH>& sm) {
+  constexpr bool SAVE = MODE == TILE_SAVE;
   constexpr int WAVES = THREADS / 64;
   constexpr int PX = MH / WAVES;
   static_assert(PX * WAVES == MH, "tile rows must split evenly over the waves");
@@ -155,8 +171,23 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
       den[p][c] = 0;
       M[p][c] = -INFINITY;
     }
+  if (MODE == TILE_STREAM && st.in && col_ok) {
+    const size_t plane = (size_t)g.OH * g.OW;
+#pragma unroll
+    for (int p = 0; p < PX; ++p) {
+      const int r = wave * PX + p;
+      if (r >= nrow) continue;
+      const size_t o = (size_t)(R0 + r) * g.OW + C;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        num[p][c] = st.in[o + c * plane];
+        den[p][c] = st.in[o + (3 + c) * plane];
+        M[p][c] = st.in[o + (6 + c) * plane];
+      }
+    }
+  }
 
-  for (int fi = 0; fi < g.n; ++fi) {
+  for (int fi = MODE == TILE_STREAM ? st.first : 0; fi < g.n; ++fi) {
     const int n = fi == 0 ? g.ref : (fi <= g.ref ? fi - 1 : fi);
     const bool is_ref = n == g.ref;
     const uint16_t* f = frames + (size_t)n * g.H * g.W;
@@ -439,6 +470,14 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
           saved[o + (9 + c) * plane] = M[p][c];
         }
       }
+      if (MODE == TILE_STREAM && st.out) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          st.out[o + c * plane] = (float)num[p][c];
+          st.out[o + (3 + c) * plane] = (float)den[p][c];
+          st.out[o + (6 + c) * plane] = M[p][c];
+        }
+      }
     }
   }
 }
@@ -458,7 +497,8 @@ __global__ __launch_bounds__(THREADS, (waves_per_simd<MH, THREADS>())) void k_me
   __shared__ MergeSmem<MH> sm;
   const int tiles_x = (g.OW + MW - 1) / MW, n = tiles_x * ((g.OH + MH - 1) / MH);
   const int t = xcd_tile(blockIdx.x, n);
-  merge_tile<MH, THREADS, false>(frames, motion, rmin, g, mc, out, nullptr, t % tiles_x, t / tiles_x, sm);
+  merge_tile<MH, THREADS, TILE_PLAIN>(frames, motion, rmin, g, mc, out, nullptr, StreamState{nullptr, nullptr, 0},
+                                      t % tiles_x, t / tiles_x, sm);
 }
 
 // Forward that also keeps the normaliser for the adjoint (float64 accumulation).
@@ -469,7 +509,29 @@ __global__ __launch_bounds__(256, 2) void k_merge_save(
   __shared__ MergeSmem<16> sm;
   const int tiles_x = (g.OW + MW - 1) / MW, n = tiles_x * ((g.OH + 15) / 16);
   const int t = xcd_tile(blockIdx.x, n);
-  merge_tile<16, 256, true>(frames, motion, rmin, g, mc, out, saved, t % tiles_x, t / tiles_x, sm);
+  merge_tile<16, 256, TILE_SAVE>(frames, motion, rmin, g, mc, out, saved, StreamState{nullptr, nullptr, 0},
+                                 t % tiles_x, t / tiles_x, sm);
+}
+
+// Streaming form: frames from loop index st.first on are added to the state.
+__global__ __launch_bounds__(256, 4) void k_merge_stream(
+    const uint16_t* __restrict__ frames, const float* __restrict__ motion,
+    const float* __restrict__ rmin, Geometry g, MergeConsts mc, StreamState st) {
+  __shared__ MergeSmem<16> sm;
+  const int tiles_x = (g.OW + MW - 1) / MW, n = tiles_x * ((g.OH + 15) / 16);
+  const int t = xcd_tile(blockIdx.x, n);
+  merge_tile<16, 256, TILE_STREAM>(frames, motion, rmin, g, mc, nullptr, nullptr, st, t % tiles_x, t / tiles_x,
+                                   sm);
+}
+
+// eq. (1) on a streaming state: C = num / den per channel, mapped to [0, 1].
+__global__ void k_stream_finish(const float* __restrict__ state, size_t plane, float black, float inv_range,
+                                float* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= plane) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    out[i + c * plane] = (state[i + c * plane] / state[i + (3 + c) * plane] - black) * inv_range;
 }
 
 // Persistent form: workgroups pull (burst, tile) items from a global counter
@@ -493,7 +555,8 @@ __global__ __launch_bounds__(THREADS, (waves_per_simd<MH, THREADS>())) void k_me
     const Geometry g = b->g;
     const MergeConsts mc = b->mc;
     const int tx = w.tile % b->merge_tiles_x, ty = w.tile / b->merge_tiles_x;
-    merge_tile<MH, THREADS, false>(b->frames, b->motion, b->rmin, g, mc, b->out, nullptr, tx, ty, sm);
+    merge_tile<MH, THREADS, TILE_PLAIN>(b->frames, b->motion, b->rmin, g, mc, b->out, nullptr,
+                                        StreamState{nullptr, nullptr, 0}, tx, ty, sm);
   }
 }
 
@@ -548,6 +611,23 @@ hipError_t launch_merge_batch(int variant, const BurstArgs* bursts, const WorkIt
 }
 
 int merge_tile_rows(int variant) { return kMergeVariants[variant].rows; }
+
+hipError_t launch_merge_stream(const Geometry& g, const MergeConsts& mc, const uint16_t* frames,
+                               const float* motion, const float* rmin, const float* state_in, float* state_out,
+                               int first, hipStream_t stream) {
+  const dim3 grid(((g.OW + MW - 1) / MW) * ((g.OH + 15) / 16));
+  hipLaunchKernelGGL(k_merge_stream, grid, dim3(256), 0, stream, frames, motion, rmin, g, mc,
+                     StreamState{state_in, state_out, first});
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_finish(const Geometry& g, const MergeConsts& mc, const float* state, float* out,
+                                hipStream_t stream) {
+  const size_t plane = (size_t)g.OH * g.OW;
+  hipLaunchKernelGGL(k_stream_finish, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, stream, state, plane,
+                     mc.black, mc.inv_range, out);
+  return hipGetLastError();
+}
 
 namespace {
 template <int MH, int THREADS>

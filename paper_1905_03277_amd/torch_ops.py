@@ -88,6 +88,49 @@ def merge_backward(frames: torch.Tensor, motion: torch.Tensor, desc, tuning,
     return g_tun, g_mot
 
 
+class StreamingMerge:
+    """Frames added one at a time into a fixed-size accumulator state
+    ([9][OH][OW] float32), then normalised: memory does not grow with the
+    frame count. Adding the frames in the order ``merge`` visits them (base
+    frame first, then the others by index) reproduces ``merge`` with the
+    64 x 16 tile shape bit for bit."""
+
+    def __init__(self, base_frame: torch.Tensor, desc, tuning):
+        if not base_frame.is_cuda or base_frame.dtype not in (torch.uint16, torch.int16) \
+                or tuple(base_frame.shape) != (desc.height, desc.width) or not base_frame.is_contiguous():
+            raise ValueError("base_frame must be a contiguous uint16 device tensor [H][W]")
+        self.desc, self.tuning, self.base = desc, tuning, base_frame
+        self.dev = base_frame.device
+        self.state = torch.empty((9, desc.out_height, desc.out_width), dtype=torch.float32, device=self.dev)
+        self.frames = 1
+        with torch.cuda.device(self.dev):
+            binding.hmfsr_stream_begin(binding.make_desc(desc), binding.make_tuning(tuning),
+                                       base_frame.data_ptr(), self.state.data_ptr(), _stream(self.dev))
+
+    def add(self, frame: torch.Tensor, motion: torch.Tensor) -> None:
+        d = self.desc
+        if frame.device != self.dev or frame.dtype != self.base.dtype or tuple(frame.shape) != (d.height, d.width) \
+                or not frame.is_contiguous():
+            raise ValueError("frame must be a contiguous tensor like the base frame")
+        ty, tx = -(-d.height // d.tile_size), -(-d.width // d.tile_size)
+        if motion.device != self.dev or motion.dtype != torch.float32 or tuple(motion.shape) != (ty, tx, 2) \
+                or not motion.is_contiguous():
+            raise ValueError(f"motion must be a contiguous float32 device tensor {(ty, tx, 2)}")
+        with torch.cuda.device(self.dev):
+            binding.hmfsr_stream_add(binding.make_desc(d), binding.make_tuning(self.tuning),
+                                     self.base.data_ptr(), frame.data_ptr(), motion.data_ptr(),
+                                     self.state.data_ptr(), _stream(self.dev))
+        self.frames += 1
+
+    def result(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        d = self.desc
+        out = _check_out(out, (3, d.out_height, d.out_width), self.dev, "out")
+        with torch.cuda.device(self.dev):
+            binding.hmfsr_stream_end(binding.make_desc(d), binding.make_tuning(self.tuning),
+                                     self.state.data_ptr(), out.data_ptr(), _stream(self.dev))
+        return out
+
+
 TUNING_FIELDS = binding.GRAD_NAMES + ("m_th",)
 
 

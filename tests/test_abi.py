@@ -105,3 +105,22 @@ def test_backward_rejects_invalid_tuning_and_pointers():
     assert _call_bwd(desc, tun, grad=6) == binding.HMFSR_E_INVALID   # misaligned
     with pytest.raises(binding.HmfsrError):
         binding.hmfsr_merge_backward(desc, tun, 4, 4, 0, 4, 0, 4)
+
+
+def test_stream_calls_validate_on_the_host():
+    desc, tun = _good()
+    L = binding.lib()
+    bad = binding.make_desc(synth.Desc(4, 63, 96))   # odd height
+    assert L.hmfsr_stream_begin(ctypes.byref(bad), ctypes.byref(tun), 4, 4, None) == binding.HMFSR_E_INVALID
+    assert L.hmfsr_stream_begin(ctypes.byref(desc), ctypes.byref(tun), None, 4, None) == binding.HMFSR_E_INVALID
+    assert L.hmfsr_stream_add(ctypes.byref(desc), ctypes.byref(tun), 4, 4, None, 4, None) == binding.HMFSR_E_INVALID
+    assert L.hmfsr_stream_add(ctypes.byref(desc), ctypes.byref(tun), 4, 6, 4, 4, None) == binding.HMFSR_E_INVALID
+    assert L.hmfsr_stream_end(ctypes.byref(desc), ctypes.byref(tun), 4, None, None) == binding.HMFSR_E_INVALID
+    tun.k_shrink = 0.0
+    assert L.hmfsr_stream_end(ctypes.byref(desc), ctypes.byref(tun), 4, 4, None) == binding.HMFSR_E_INVALID
+
+
+def test_merge_rejects_misaligned_saved_buffer():
+    desc, tun = _good()
+    assert binding.lib().hmfsr_merge(ctypes.byref(desc), ctypes.byref(tun), 4, 4, 4, 12, None) == \
+        binding.HMFSR_E_INVALID
