@@ -184,6 +184,22 @@ def _draw_scene(rng: np.random.Generator, height: int, width: int) -> SceneParam
     return SceneParams(base, g_dir, g_freq, g_phase, g_amp, g_gain, polys)
 
 
+def _draw_texture(rng: np.random.Generator, height: int, width: int, k: int = 48,
+                  f_lo: float = 0.01, f_hi: float = 0.1) -> SceneParams:
+    """Isotropic texture for alignment tests: ``k`` gratings in random
+    directions with log-uniform frequencies in [f_lo, f_hi] cycles/px (below
+    the half-resolution Nyquist limit, so the 2x2-quad luma is not aliased),
+    amplitudes U[0.02, 0.04] and per-channel gains U[0.3, 1]; no polygons."""
+    base = rng.uniform(0.3, 0.7, size=3)
+    ang = rng.uniform(0.0, math.pi, size=k)
+    g_dir = np.stack([np.cos(ang), np.sin(ang)], axis=1)
+    g_freq = np.exp(rng.uniform(math.log(f_lo), math.log(f_hi), size=k))
+    g_phase = rng.uniform(0.0, 2 * math.pi, size=k)
+    g_amp = rng.uniform(0.02, 0.04, size=k)
+    g_gain = rng.uniform(0.3, 1.0, size=(k, 3))
+    return SceneParams(base, g_dir, g_freq, g_phase, g_amp, g_gain, [])
+
+
 def eval_scene(sp: SceneParams, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
     """Scene colour at scene points (x, y) -> [3, *x.shape] float64 in [0.05, 0.95]."""
     dt = torch.float64
@@ -237,11 +253,17 @@ def make_burst(n_frames: int, height: int, width: int, *, seed: int, sigma_t: fl
                rot_sigma_deg: float = 0.3, noise_a: float = 1e-3, noise_b: float = 1e-6,
                scale: float = 1.0, tile_size: int = 16, cfa: int = CFA_RGGB,
                tuning: Tuning = TUNING_SNR22, occluder: bool = False, with_gt: bool = False,
+               scene: str = "default",
                device="cpu", rows_per_chunk: int = 512) -> Burst:
     """Draw one seeded burst. Frames are generated on ``device`` in row chunks."""
     assert height % 2 == 0 and width % 2 == 0
     rng = np.random.Generator(np.random.PCG64(seed))
-    sp = _draw_scene(rng, height, width)
+    if scene == "default":
+        sp = _draw_scene(rng, height, width)
+    elif scene == "texture":
+        sp = _draw_texture(rng, height, width)
+    else:
+        raise ValueError(f"unknown scene {scene!r}")
     thetas = rng.normal(0.0, math.radians(rot_sigma_deg), size=n_frames)
     trans = rng.normal(0.0, sigma_t, size=(n_frames, 2))
     occ = None

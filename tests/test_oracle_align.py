@@ -1,0 +1,222 @@
+"""Pins of the tile-alignment oracle (Sec. 3.2: pyramid block matching refined
+by three Lucas-Kanade iterations) against what the method and the geometry fix.
+
+A slip in the oracle (a wrong sign of the displacement, x and y swapped, a
+guess not doubled between levels, a gradient of the wrong image, a broken tie
+rule) fails at least one of these. No GPU involved.
+"""
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle.align as oa
+from paper_1905_03277_amd import synth
+
+
+def textured_canvas(size, seed):
+    """Seeded multi-scale random texture as 12-bit raw values."""
+    rng = np.random.default_rng(seed)
+    acc = np.zeros((size, size))
+    for sigma, wgt in ((1.5, 1.0), (3.0, 1.0), (6.0, 1.0), (12.0, 1.0)):
+        f = ndimage.gaussian_filter(rng.normal(size=(size, size)), sigma)
+        acc += wgt * f / f.std()
+    acc = (acc - acc.min()) / (acc.max() - acc.min())
+    return np.round(200 + 3500 * acc).astype(np.uint16)
+
+
+def shifted_frames(canvas, h, w, pad, shifts):
+    """frames[k] shows base position p at p + shifts[k] (Bayer pixels)."""
+    out = []
+    for vx, vy in shifts:
+        out.append(canvas[pad - vy:pad - vy + h, pad - vx:pad - vx + w])
+    return np.stack(out)
+
+
+DESC16 = dict(ref_frame=0, tile_size=16)
+
+
+# ----------------------------------------------------------------------------- pyramid
+def test_quad_sums_and_pyramid_against_loops():
+    rng = np.random.default_rng(1)
+    f = rng.integers(0, 4096, size=(38, 54)).astype(np.uint16)
+    g = oa.quad_sums(f)
+    assert g.shape == (19, 27)
+    for i in range(19):
+        for j in range(27):
+            assert g[i, j] == int(f[2 * i, 2 * j]) + int(f[2 * i, 2 * j + 1]) + \
+                int(f[2 * i + 1, 2 * j]) + int(f[2 * i + 1, 2 * j + 1])
+    pyr = oa.pyramid(g, 6, 4)
+    # 19x27 -> 9x13 -> 4x6 (holds a 4x4 block) -> 2x3 (does not): three levels
+    assert [p.shape for p in pyr] == [(19, 27), (9, 13), (4, 6)]
+    for lv in range(1, len(pyr)):
+        h, w = pyr[lv].shape
+        assert pyr[lv].sum() == pyr[lv - 1][:2 * h, :2 * w].sum()
+        assert pyr[lv][1, 2] == pyr[lv - 1][2:4, 4:6].sum()
+
+
+def test_pyramid_level_cap():
+    g = np.ones((256, 256), dtype=np.int64)
+    assert len(oa.pyramid(g, 4, 8)) == 4
+    assert len(oa.pyramid(g, 9, 8)) == 6        # 256 .. 8: six levels hold a block
+    assert len(oa.pyramid(g, 1, 8)) == 1
+
+
+# ----------------------------------------------------------------------------- block matching
+def _brute_match(base, img, block, by, bx, guess, radius):
+    h, w = len(base), len(base[0])
+    cands = []
+    k = 0
+    for dy in range(-radius, radius + 1):
+        for dx in range(-radius, radius + 1):
+            ssd = 0
+            for y in range(by * block, min(by * block + block, h)):
+                for x in range(bx * block, min(bx * block + block, w)):
+                    yy = min(max(y + guess[1] + dy, 0), h - 1)
+                    xx = min(max(x + guess[0] + dx, 0), w - 1)
+                    d = int(img[yy][xx]) - int(base[y][x])
+                    ssd += d * d
+            cands.append((ssd, dx * dx + dy * dy, k, guess[0] + dx, guess[1] + dy))
+            k += 1
+    best = min(cands)
+    return best[3], best[4]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_match_block_brute_force_with_ties(seed):
+    """Few grey levels make many exact ties, so the tie rules are exercised."""
+    rng = np.random.default_rng(seed)
+    base = rng.integers(0, 3, size=(21, 19)).astype(np.int64)
+    img = rng.integers(0, 3, size=(21, 19)).astype(np.int64)
+    for by in range(3):
+        for bx in range(3):
+            guess = (int(rng.integers(-3, 4)), int(rng.integers(-3, 4)))
+            got = oa.match_block(base, img, 8, by, bx, guess, 2)
+            assert got == _brute_match(base.tolist(), img.tolist(), 8, by, bx, guess, 2)
+
+
+def test_tie_prefers_smallest_offset_then_scan_order():
+    flat = np.full((16, 16), 5, dtype=np.int64)
+    assert oa.match_block(flat, flat, 8, 1, 0, (3, -2), 2) == (3, -2)
+    # period-2 columns: offsets dx = -2, 0, 2 tie on SSD; dx = 0 wins on distance
+    stripes = np.tile(np.array([0, 9], dtype=np.int64), (16, 8))
+    assert oa.match_block(stripes, stripes, 8, 0, 0, (0, 0), 2) == (0, 0)
+    # shifted by one column: dx = -1 and dx = +1 tie on SSD and distance, the
+    # first in row-major order (dx = -1) wins
+    img = np.roll(stripes, 1, axis=1)
+    assert oa.match_block(stripes, img, 8, 0, 1, (0, 0), 2) == (-1, 0)
+
+
+def test_guess_parent_is_block_holding_centre():
+    # fine blocks of 8 under coarse blocks of 8: centre 8b + 4 lies at 4b + 2 on
+    # the coarser level, inside coarse block (4b + 2) // 8 = b // 2
+    assert [oa.coarse_parent(b, 8, 8, 100) for b in range(6)] == [0, 0, 1, 1, 2, 2]
+    # fine tiles of 16 under coarse blocks of 8: centre (16b + 8) / 2 = 8b + 4 -> b
+    assert [oa.coarse_parent(b, 16, 8, 100) for b in range(4)] == [0, 1, 2, 3]
+    assert oa.coarse_parent(9, 8, 8, 2) == 1      # clamped to the last coarse block
+
+
+# ----------------------------------------------------------------------------- whole alignment
+def test_flat_frames_give_zero_motion():
+    frames = np.full((3, 64, 64), 1000, dtype=np.uint16)
+    m = oa.align(frames, DESC16)
+    assert m.shape == (3, 4, 4, 2)
+    assert not m.any()
+
+
+@pytest.mark.parametrize("shift", [(4, -2), (-6, 10), (40, -24)])
+def test_even_integer_shift_recovered_exactly(shift):
+    """An even Bayer shift is an integer half-res shift: block matching finds
+    it (through the pyramid for the large one) and Lucas-Kanade, whose error
+    image is then exactly zero, keeps it. Interior tiles only."""
+    h = w = 256
+    pad = 48
+    canvas = textured_canvas(h + 2 * pad, seed=5)
+    frames = shifted_frames(canvas, h, w, pad, [(0, 0), shift, (0, 0)])
+    m, steps = oa.align(frames, DESC16, debug=True)
+    vx, vy = shift
+    ty_n, tx_n = m.shape[1:3]
+    inner = []
+    for ty in range(ty_n):
+        for tx in range(tx_n):
+            y0, y1 = ty * 8 - 4, ty * 8 + 12
+            x0, x1 = tx * 8 - 4, tx * 8 + 12
+            if y0 + vy // 2 >= 0 and y1 + vy // 2 <= h // 2 and x0 + vx // 2 >= 0 \
+                    and x1 + vx // 2 <= w // 2 and y0 >= 0 and x0 >= 0:
+                inner.append((ty, tx))
+    assert len(inner) > 60
+    for ty, tx in inner:
+        assert tuple(steps[1]["block_match"][ty, tx]) == (vx // 2, vy // 2)
+        assert tuple(m[1, ty, tx]) == (float(vx), float(vy))
+    assert not m[0].any() and not m[2].any()       # base frame, identical frame
+
+
+def test_one_dimensional_texture_keeps_block_match():
+    """Vertical stripes have no y gradient: H is singular, LK is skipped and
+    the result is exactly twice the block-matching vector."""
+    x = np.arange(128)
+    row = np.round(2000 + 1500 * np.sin(2 * np.pi * x / 23.0)).astype(np.uint16)
+    base = np.tile(row, (64, 1))
+    moved = np.tile(np.roll(row, 3), (64, 1))
+    m, steps = oa.align(np.stack([base, moved]), DESC16, debug=True)
+    np.testing.assert_array_equal(m[1], 2.0 * steps[1]["block_match"])
+
+
+def test_subpixel_translation_recovered():
+    """Pure translation (no rotation, no noise) of a smooth texture: the
+    Lucas-Kanade refinement reaches a few hundredths of a pixel while block
+    matching alone is off by up to a pixel."""
+    b = synth.make_burst(6, 256, 256, seed=synth.config_seed(6, 7), scene="texture",
+                         rot_sigma_deg=0.0, noise_a=0.0, noise_b=1e-12, sigma_t=2.0)
+    f, gt = b.numpy()
+    m, steps = oa.align(f, b.desc, debug=True)
+    lk, bm = [], []
+    for k in range(1, 6):
+        lk.append(np.hypot(*(m[k] - gt[k])[1:-1, 1:-1].reshape(-1, 2).T))
+        bm.append(np.hypot(*(2.0 * steps[k]["block_match"] - gt[k])[1:-1, 1:-1].reshape(-1, 2).T))
+    lk, bm = np.concatenate(lk), np.concatenate(bm)
+    assert np.median(lk) < 0.03, np.median(lk)
+    assert np.percentile(lk, 99) < 0.1
+    assert np.median(bm) > 0.2
+
+
+def test_ground_truth_motion_recovered_at_high_snr():
+    """Handheld motion (translation + small rotation) of a textured scene at
+    high SNR: median error within 0.05 px, the smallest alignment corruption
+    the paper's robustness study applies (Sec. 6.2)."""
+    errs = []
+    for burst in range(2):
+        b = synth.make_burst(8, 256, 256, seed=synth.config_seed(6, burst), scene="texture",
+                             noise_a=1e-5, noise_b=1e-8)
+        f, gt = b.numpy()
+        m = oa.align(f, b.desc)
+        assert not m[0].any()
+        for k in range(1, 8):
+            errs.append(np.hypot(*(m[k] - gt[k])[1:-1, 1:-1].reshape(-1, 2).T))
+    e = np.concatenate(errs)
+    assert np.median(e) < 0.05, np.median(e)
+    assert np.percentile(e, 99) < 0.2
+
+
+def test_nonzero_reference_frame():
+    """Vectors are relative to the base frame, whichever index it has."""
+    h = w = 128
+    pad = 24
+    canvas = textured_canvas(h + 2 * pad, seed=9)
+    frames = shifted_frames(canvas, h, w, pad, [(2, 2), (0, 0), (-4, 6)])
+    m = oa.align(frames, dict(ref_frame=1, tile_size=16))
+    assert not m[1].any()
+    assert tuple(m[0, 5, 5]) == (2.0, 2.0)
+    assert tuple(m[2, 5, 5]) == (-4.0, 6.0)
+
+
+def test_sampled_tiles_equal_full_alignment():
+    b = synth.make_config(1)
+    f, _ = b.numpy()
+    m, steps = oa.align(f, b.desc, debug=True)
+    tiles = [(0, 0), (5, 7), (15, 15), (3, 12), (15, 0)]
+    for k in (0, 2, 6):
+        ms, bm = oa.align_sampled(f, b.desc, k, tiles)
+        for i, (ty, tx) in enumerate(tiles):
+            np.testing.assert_array_equal(ms[i], m[k, ty, tx])
+            if k:
+                np.testing.assert_array_equal(bm[i], steps[k]["block_match"][ty, tx])
