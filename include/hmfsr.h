@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define HMFSR_VERSION 110 /* 1.1.0 */
+#define HMFSR_VERSION 120 /* 1.2.0 */
 
 /* Colour filter array layout: colours of the 2x2 Bayer cell read row by row. */
 typedef enum {
@@ -188,6 +188,52 @@ hmfsr_status hmfsr_stream_end(const hmfsr_desc* desc, const hmfsr_tuning* tuning
                               const float* state, float* out, void* stream);
 
 /*
+ * Tile-alignment parameters (host struct). The paper fixes only the number of
+ * Lucas-Kanade iterations (three, Sec. 3.2); the other defaults are this
+ * library's choice.
+ *  levels         pyramid levels, 1..6 (default 4); fewer are built where a
+ *                 coarser level would not hold an 8 x 8 block
+ *  radius_coarse  search radius (pixels) on the coarsest level, 1..8 (default 4)
+ *  radius_fine    search radius on every finer level, 1..8 (default 2)
+ *  lk_iterations  Lucas-Kanade iterations, 0..16 (default 3)
+ */
+typedef struct {
+  int32_t levels, radius_coarse, radius_fine, lk_iterations;
+} hmfsr_align_params;
+
+/*
+ * hmfsr_align -- per-tile alignment vectors of every frame against the base
+ * frame (Sec. 3.2), in the layout hmfsr_merge reads, so that a raw burst goes
+ * to RGB through hmfsr_align then hmfsr_merge.
+ *  desc     as for hmfsr_merge; only n_frames, height, width, ref_frame and
+ *           tile_size are used, and tile_size must be <= 64 (S.2's largest).
+ *  params   NULL for the defaults.
+ *  frames   DEVICE uint16 [n_frames][height][width], 4-byte aligned.
+ *  motion   DEVICE float32 [n_frames][TY][TX][2], 8-byte aligned (output):
+ *           (vx, vy) in raw pixels such that base position X of tile (ty, tx)
+ *           is seen at X + v in the frame; 0 for the base frame.
+ *  block_match  NULL, or DEVICE int32 [n_frames][TY][TX][2], 8-byte aligned
+ *           (output): the integer block-matching vector of each tile on the
+ *           half-resolution grid, before the Lucas-Kanade refinement.
+ * Method (the paper leaves the details open; these are the library's):
+ * frames are reduced to integer 2x2-quad sums (half resolution, level 0);
+ * level l + 1 holds the 2x2 sums of level l. Blocks are the merge's tiles
+ * (tile_size / 2 on level 0) and 8 x 8 above. On each level, from the
+ * coarsest, every block takes the integer offset that minimises the sum of
+ * squared differences (edge-replicated frame) over guess + [-R, R]^2, ties to
+ * the smallest offset from the guess and then to the first in row-major
+ * order; the guess is twice the vector of the coarser block holding the
+ * block's centre (0 on the coarsest level). Each tile's vector is then
+ * refined by translation-only Lucas-Kanade on level 0 over the tile grown by
+ * half a tile on every side: central-difference gradients of the base frame,
+ * bilinear error image, v -= H^-1 b; tiles whose normal matrix H has
+ * det H <= 1e-9 (tr H)^2 keep their block-matching vector. The result is
+ * twice the level-0 vector. Workspace: about 1.4 bytes per raw pixel and frame.
+ */
+hmfsr_status hmfsr_align(const hmfsr_desc* desc, const hmfsr_align_params* params, const uint16_t* frames,
+                         float* motion, int32_t* block_match, void* stream);
+
+/*
  * hmfsr_merge_maps -- the per-frame intermediate maps of the merge, for
  * inspection (the paper visualises the accumulated robustness mask and the
  * kernel shapes). Same inputs as hmfsr_merge; h = height/2, w = width/2.
@@ -254,6 +300,7 @@ enum {
   HMFSR_STAGE_MERGE_BWD = 4,   /* adjoint of the accumulation              */
   HMFSR_STAGE_ROBUST_BWD = 5,  /* adjoint of the robustness                */
   HMFSR_STAGE_GRAD_REDUCE = 6, /* fixed-order sums of the gradient partials */
+  HMFSR_STAGE_ALIGN = 7,       /* tile alignment (pyramid, matching, Lucas-Kanade) */
   HMFSR_NUM_STAGES = 8
 };
 typedef struct {

@@ -18,16 +18,17 @@ HMFSR_OK, HMFSR_E_INVALID, HMFSR_E_UNSUPPORTED, HMFSR_E_HIP, HMFSR_E_NOMEM = 0, 
 
 # Every symbol include/hmfsr.h declares.
 EXPORTED = ("hmfsr_merge", "hmfsr_merge_backward", "hmfsr_stream_begin", "hmfsr_stream_add",
-            "hmfsr_stream_end", "hmfsr_merge_maps", "hmfsr_merge_batch", "hmfsr_autotune",
+            "hmfsr_stream_end", "hmfsr_align", "hmfsr_merge_maps", "hmfsr_merge_batch", "hmfsr_autotune",
             "hmfsr_profile_begin", "hmfsr_profile_end", "hmfsr_strerror", "hmfsr_version",
             "hmfsr_release")
 
 STAGE_PRIOR, STAGE_ROBUST, STAGE_MERGE, STAGE_BATCH = 0, 1, 2, 3
-STAGE_MERGE_BWD, STAGE_ROBUST_BWD, STAGE_GRAD_REDUCE = 4, 5, 6
+STAGE_MERGE_BWD, STAGE_ROBUST_BWD, STAGE_GRAD_REDUCE, STAGE_ALIGN = 4, 5, 6, 7
 NUM_STAGES = 8
 STAGE_NAMES = {STAGE_PRIOR: "k_prior", STAGE_ROBUST: "k_robust", STAGE_MERGE: "k_merge",
                STAGE_BATCH: "batch_graph", STAGE_MERGE_BWD: "k_merge_bwd",
-               STAGE_ROBUST_BWD: "k_robust_bwd", STAGE_GRAD_REDUCE: "k_grad_reduce"}
+               STAGE_ROBUST_BWD: "k_robust_bwd", STAGE_GRAD_REDUCE: "k_grad_reduce",
+               STAGE_ALIGN: "align"}
 
 # Order of hmfsr_merge_backward's grad_tuning.
 GRAD_NAMES = ("k_detail", "k_denoise", "d_th", "d_tr", "k_stretch", "k_shrink", "s", "t", "s_motion")
@@ -47,6 +48,14 @@ class hmfsr_tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_float) for n in
                 ("k_detail", "k_denoise", "d_th", "d_tr", "k_stretch", "k_shrink", "s", "t",
                  "s_motion", "m_th")]
+
+
+class hmfsr_align_params(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("radius_coarse", ctypes.c_int32),
+                ("radius_fine", ctypes.c_int32), ("lk_iterations", ctypes.c_int32)]
+
+
+ALIGN_DEFAULTS = dict(levels=4, radius_coarse=4, radius_fine=2, lk_iterations=3)
 
 
 class hmfsr_stage_times(ctypes.Structure):
@@ -82,6 +91,8 @@ def lib() -> ctypes.CDLL:
         L.hmfsr_stream_add.restype = i32
         L.hmfsr_stream_end.argtypes = [pd, pt, vp, vp, vp]
         L.hmfsr_stream_end.restype = i32
+        L.hmfsr_align.argtypes = [pd, ctypes.POINTER(hmfsr_align_params), vp, vp, vp, vp]
+        L.hmfsr_align.restype = i32
         L.hmfsr_merge_maps.argtypes = [pd, pt, vp, vp, vp, vp, vp, vp, vp]
         L.hmfsr_merge_maps.restype = i32
         L.hmfsr_merge_batch.argtypes = [i32, pd, pt, ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -149,6 +160,19 @@ def hmfsr_stream_add(desc, tuning, base_frame: int, frame: int, motion: int, sta
 def hmfsr_stream_end(desc, tuning, state: int, out: int, stream: int = 0) -> None:
     _check(lib().hmfsr_stream_end(ctypes.byref(desc), ctypes.byref(tuning), state, out, stream or None),
            "hmfsr_stream_end")
+
+
+def make_align_params(params=None) -> hmfsr_align_params:
+    """hmfsr_align_params from a dict (missing keys take the defaults)."""
+    p = dict(ALIGN_DEFAULTS)
+    p.update(params or {})
+    return hmfsr_align_params(*(int(p[f]) for f, _ in hmfsr_align_params._fields_))
+
+
+def hmfsr_align(desc, params, frames: int, motion: int, block_match: int = 0, stream: int = 0) -> None:
+    """params: hmfsr_align_params or None (the library's defaults)."""
+    _check(lib().hmfsr_align(ctypes.byref(desc), ctypes.byref(params) if params is not None else None,
+                             frames, motion, block_match or None, stream or None), "hmfsr_align")
 
 
 def hmfsr_merge_maps(desc, tuning, frames: int, motion: int, omega: int, robust: int,

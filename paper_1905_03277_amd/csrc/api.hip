@@ -40,8 +40,8 @@ double range_of(const hmfsr_desc* d) { return (double)d->white_level - (double)d
 
 }  // namespace
 
-hmfsr_status validate(const hmfsr_desc* d, const hmfsr_tuning* t) {
-  if (!d || !t) return HMFSR_E_INVALID;
+hmfsr_status validate_desc(const hmfsr_desc* d) {
+  if (!d) return HMFSR_E_INVALID;
   if (d->n_frames < 1 || d->n_frames > 4096) return HMFSR_E_INVALID;
   if (d->ref_frame < 0 || d->ref_frame >= d->n_frames) return HMFSR_E_INVALID;
   if (d->height < 4 || d->width < 4 || d->height > 32768 || d->width > 32768) return HMFSR_E_INVALID;
@@ -56,6 +56,15 @@ hmfsr_status validate(const hmfsr_desc* d, const hmfsr_tuning* t) {
   if (d->out_height != (int32_t)floor((double)d->height * s + 0.5) ||
       d->out_width != (int32_t)floor((double)d->width * s + 0.5))
     return HMFSR_E_INVALID;
+  int cols[4];
+  if (!cfa_colours(d->cfa, cols)) return HMFSR_E_UNSUPPORTED;
+  return HMFSR_OK;
+}
+
+hmfsr_status validate(const hmfsr_desc* d, const hmfsr_tuning* t) {
+  if (!d || !t) return HMFSR_E_INVALID;
+  const hmfsr_status st = validate_desc(d);
+  if (st != HMFSR_OK) return st;
   const float vals[10] = {t->k_detail, t->k_denoise, t->d_th, t->d_tr, t->k_stretch,
                           t->k_shrink, t->s, t->t, t->s_motion, t->m_th};
   for (float v : vals)
@@ -63,8 +72,6 @@ hmfsr_status validate(const hmfsr_desc* d, const hmfsr_tuning* t) {
   if (!(t->k_detail > 0.f) || !(t->k_denoise > 0.f) || !(t->d_tr > 0.f) || !(t->k_stretch > 0.f) ||
       !(t->k_shrink > 0.f) || t->s < 0.f || t->s_motion < 0.f || t->m_th < 0.f)
     return HMFSR_E_INVALID;
-  int cols[4];
-  if (!cfa_colours(d->cfa, cols)) return HMFSR_E_UNSUPPORTED;
   return HMFSR_OK;
 }
 
@@ -181,6 +188,53 @@ hmfsr_status bwd_workspace(int dev, size_t bytes, hipStream_t stream, void** out
 hmfsr_status stream_workspace(int dev, size_t bytes, hipStream_t stream, void** out) {
   return grow(g_dev[dev].stream_ws, g_dev[dev].stream_ws_bytes, bytes, stream, out);
 }
+
+hmfsr_status align_workspace(int dev, size_t bytes, hipStream_t stream, void** out) {
+  return grow(g_dev[dev].align_ws, g_dev[dev].align_ws_bytes, bytes, stream, out);
+}
+
+namespace {
+// Pyramid sizes and block grids: level l + 1 holds the 2x2 sums of level l
+// while it still holds a whole coarse block, up to params->levels levels.
+hmfsr_status make_align_geom(const hmfsr_desc* d, const hmfsr_align_params* p, AlignGeom* ag) {
+  if (d->tile_size > 64) return HMFSR_E_INVALID;
+  if (p->levels < 1 || p->levels > kAlignMaxLevels || p->radius_coarse < 1 || p->radius_coarse > 8 ||
+      p->radius_fine < 1 || p->radius_fine > 8 || p->lk_iterations < 0 || p->lk_iterations > 16)
+    return HMFSR_E_INVALID;
+  AlignGeom a;
+  memset(&a, 0, sizeof(a));
+  a.n = d->n_frames;
+  a.ref = d->ref_frame;
+  a.lh[0] = d->height / 2;
+  a.lw[0] = d->width / 2;
+  a.L = 1;
+  while (a.L < p->levels) {
+    const int nh = a.lh[a.L - 1] / 2, nw = a.lw[a.L - 1] / 2;
+    if (nh < kAlignCoarseBlock || nw < kAlignCoarseBlock) break;
+    a.lh[a.L] = nh;
+    a.lw[a.L] = nw;
+    ++a.L;
+  }
+  long long off = 0, voff = 0;
+  for (int l = 0; l < a.L; ++l) {
+    a.blk[l] = l == 0 ? d->tile_size / 2 : kAlignCoarseBlock;
+    a.gby[l] = (a.lh[l] + a.blk[l] - 1) / a.blk[l];
+    a.gbx[l] = (a.lw[l] + a.blk[l] - 1) / a.blk[l];
+    a.loff[l] = off;
+    off += (long long)a.lh[l] * a.lw[l];
+    a.voff[l] = voff;
+    voff += (long long)a.gby[l] * a.gbx[l];
+  }
+  a.fstride = (off + 63) / 64 * 64;
+  a.vstride = (voff + 31) / 32 * 32;
+  if ((long long)a.n * a.gby[0] * a.gbx[0] >= (1ll << 31)) return HMFSR_E_INVALID;  // work items are int
+  a.radius_coarse = p->radius_coarse;
+  a.radius_fine = p->radius_fine;
+  a.lk_iterations = p->lk_iterations;
+  *ag = a;
+  return HMFSR_OK;
+}
+}  // namespace
 
 hmfsr_status run_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, const Geometry& g,
                        const uint16_t* frames, const float* motion, float* out, float* saved,
@@ -394,6 +448,28 @@ hmfsr_status hmfsr_merge_maps(const hmfsr_desc* desc, const hmfsr_tuning* tuning
   return HMFSR_OK;
 }
 
+hmfsr_status hmfsr_align(const hmfsr_desc* desc, const hmfsr_align_params* params, const uint16_t* frames,
+                         float* motion, int32_t* block_match, void* stream) {
+  hmfsr_status st = validate_desc(desc);
+  if (st != HMFSR_OK) return st;
+  if (!frames || !motion || ((uintptr_t)frames & 3) || ((uintptr_t)motion & 7) || ((uintptr_t)block_match & 7))
+    return HMFSR_E_INVALID;
+  const hmfsr_align_params defaults = {4, 4, 2, 3};
+  AlignGeom ag;
+  if ((st = make_align_geom(desc, params ? params : &defaults, &ag)) != HMFSR_OK) return st;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  int dev = 0;
+  if ((st = current_device(&dev)) != HMFSR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  void* ws = nullptr;
+  if ((st = align_workspace(dev, align_bytes(ag), s, &ws)) != HMFSR_OK) return st;
+  return timed(HMFSR_STAGE_ALIGN, s, [&] {
+           return launch_align(ag, frames, desc->height, desc->width, ws, motion, block_match, s);
+         }) == hipSuccess
+             ? HMFSR_OK
+             : HMFSR_E_HIP;
+}
+
 const char* hmfsr_strerror(hmfsr_status status) {
   switch (status) {
     case HMFSR_OK: return "HMFSR_OK";
@@ -445,7 +521,8 @@ void hmfsr_release(void) {
   const bool have_cur = hipGetDevice(&cur) == hipSuccess;
   for (int d = 0; d < kMaxDevices; ++d) {
     DeviceState& st = g_dev[d];
-    if (!st.workspace && !st.batch_ws && !st.bwd_ws && !st.stream_ws && !st.plan.exec && !st.capture_stream)
+    if (!st.workspace && !st.batch_ws && !st.bwd_ws && !st.stream_ws && !st.align_ws && !st.plan.exec &&
+        !st.capture_stream)
       continue;
     if (hipSetDevice(d) != hipSuccess) continue;
     if (st.plan.exec) hipGraphExecDestroy(st.plan.exec);
@@ -457,6 +534,9 @@ void hmfsr_release(void) {
     if (st.stream_ws) hipFree(st.stream_ws);
     st.stream_ws = nullptr;
     st.stream_ws_bytes = 0;
+    if (st.align_ws) hipFree(st.align_ws);
+    st.align_ws = nullptr;
+    st.align_ws_bytes = 0;
     if (st.capture_stream) hipStreamDestroy(st.capture_stream);
     st.workspace = st.batch_ws = st.bwd_ws = nullptr;
     st.workspace_bytes = st.batch_ws_bytes = st.bwd_ws_bytes = 0;

@@ -152,4 +152,27 @@ hipError_t launch_robust_bwd(const Geometry& g, const RobustConsts& rc, const Pr
 hipError_t launch_grad_reduce(const Geometry& g, const BwdConsts& bc, const BwdWork& w,
                               float* grad_tuning, float* grad_motion, hipStream_t stream);
 
+// ---- tile alignment ----------------------------------------------------------
+
+constexpr int kAlignMaxLevels = 6;
+constexpr int kAlignCoarseBlock = 8;   // block edge on the levels above the finest
+
+// Pyramid and block grids of one burst's alignment, resolved on the host.
+struct AlignGeom {
+  int n, ref, L;                       // frames, base frame, pyramid levels built
+  int lh[kAlignMaxLevels], lw[kAlignMaxLevels];    // level sizes (level 0: half resolution)
+  int blk[kAlignMaxLevels];                        // block edge per level (level 0: T / 2)
+  int gby[kAlignMaxLevels], gbx[kAlignMaxLevels];  // block grid per level
+  long long loff[kAlignMaxLevels];     // int32 offset of each level in one frame's pyramid
+  long long fstride;                   // int32 words per frame pyramid
+  long long voff[kAlignMaxLevels];     // int2 offset of each level's vectors in one frame's set
+  long long vstride;                   // int2 vectors per frame
+  int radius_coarse, radius_fine, lk_iterations;
+};
+
+// Workspace: pyramids [n][fstride] int32, then vectors [n][vstride] int2.
+size_t align_bytes(const AlignGeom& ag);
+hipError_t launch_align(const AlignGeom& ag, const uint16_t* frames, int H, int W, void* ws,
+                        float* motion, int* block_match, hipStream_t stream);
+
 }  // namespace hmfsr

@@ -32,6 +32,8 @@ struct DeviceState {
   size_t bwd_ws_bytes = 0;
   void* stream_ws = nullptr;  // streaming merge: two-frame view and its maps
   size_t stream_ws_bytes = 0;
+  void* align_ws = nullptr;   // tile alignment: pyramids and block vectors
+  size_t align_ws_bytes = 0;
   hipStream_t capture_stream = nullptr;
   BatchPlan plan;
 };
@@ -64,6 +66,7 @@ hipError_t timed(int stage, hipStream_t s, F fn) {
   return err;
 }
 
+hmfsr_status validate_desc(const hmfsr_desc* d);
 hmfsr_status validate(const hmfsr_desc* d, const hmfsr_tuning* t);
 Geometry make_geometry(const hmfsr_desc* d);
 PriorConsts make_prior(const hmfsr_tuning* t);
@@ -74,6 +77,7 @@ hmfsr_status current_device(int* dev_out);  // caller holds g_mutex
 hmfsr_status workspace(int dev, size_t bytes, hipStream_t stream, void** out);  // caller holds g_mutex
 hmfsr_status bwd_workspace(int dev, size_t bytes, hipStream_t stream, void** out);  // caller holds g_mutex
 hmfsr_status stream_workspace(int dev, size_t bytes, hipStream_t stream, void** out);  // caller holds g_mutex
+hmfsr_status align_workspace(int dev, size_t bytes, hipStream_t stream, void** out);  // caller holds g_mutex
 
 // Merge tile shape for a burst: HMFSR_MERGE_VARIANT, else the autotuned
 // choice for the burst's (scale, frame count) class, else the default.

@@ -58,6 +58,35 @@ def merge(frames: torch.Tensor, motion: torch.Tensor, desc, tuning,
     return out
 
 
+def align(frames: torch.Tensor, desc, params=None, motion: torch.Tensor | None = None,
+          block_match: bool = False):
+    """Per-tile alignment vectors of every frame against the base frame
+    (float32 [N][TY][TX][2], the layout ``merge`` reads). ``params``: dict of
+    hmfsr_align_params fields (missing ones take the defaults). With
+    ``block_match`` also returns the integer block-matching vectors
+    (int32 [N][TY][TX][2], half-resolution pixels)."""
+    if not frames.is_cuda:
+        raise ValueError("frames must be a device tensor (no CPU path exists)")
+    if frames.dtype not in (torch.uint16, torch.int16):
+        raise ValueError(f"frames must be uint16 (or an int16 view), got {frames.dtype}")
+    n, h, w = desc.n_frames, desc.height, desc.width
+    if tuple(frames.shape) != (n, h, w) or not frames.is_contiguous():
+        raise ValueError(f"frames must be contiguous of shape {(n, h, w)}")
+    shape = (n, -(-h // desc.tile_size), -(-w // desc.tile_size), 2)
+    motion = _check_out(motion, shape, frames.device, "motion")
+    bm = torch.empty(shape, dtype=torch.int32, device=frames.device) if block_match else None
+    with torch.cuda.device(frames.device):
+        binding.hmfsr_align(binding.make_desc(desc), binding.make_align_params(params),
+                            frames.data_ptr(), motion.data_ptr(), 0 if bm is None else bm.data_ptr(),
+                            _stream(frames.device))
+    return (motion, bm) if block_match else motion
+
+
+def merge_raw(frames: torch.Tensor, desc, tuning, params=None) -> torch.Tensor:
+    """Raw burst to RGB: ``align`` then ``merge``."""
+    return merge(frames, align(frames, desc, params), desc, tuning)
+
+
 def saved_buffer(desc, device) -> torch.Tensor:
     """A buffer for the forward's normaliser: 12 words per output pixel (three
     float64 planes of C, three float32 planes each of the denominator and the

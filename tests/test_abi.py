@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version_and_strerror():
-    assert binding.hmfsr_version() == 110
+    assert binding.hmfsr_version() == 120
     assert "INVALID" in binding.strerror(binding.HMFSR_E_INVALID)
     assert "unknown" in binding.strerror(-99)
 
@@ -124,3 +124,37 @@ def test_merge_rejects_misaligned_saved_buffer():
     desc, tun = _good()
     assert binding.lib().hmfsr_merge(ctypes.byref(desc), ctypes.byref(tun), 4, 4, 4, 12, None) == \
         binding.HMFSR_E_INVALID
+
+
+def _align_call(desc, params, frames=8, motion=8, bm=None):
+    return binding.lib().hmfsr_align(ctypes.byref(desc), ctypes.byref(params) if params is not None else None,
+                                     frames, motion, bm, None)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("levels", 0), ("levels", 7), ("radius_coarse", 0), ("radius_coarse", 9), ("radius_fine", 0),
+    ("radius_fine", 9), ("lk_iterations", -1), ("lk_iterations", 17),
+])
+def test_align_rejects_invalid_params(field, value):
+    desc, _ = _good()
+    params = binding.make_align_params()
+    setattr(params, field, value)
+    assert _align_call(desc, params) == binding.HMFSR_E_INVALID
+
+
+def test_align_validates_descriptor_and_pointers():
+    desc, _ = _good()
+    p = binding.make_align_params()
+    for field, value in (("tile_size", 66), ("tile_size", 128), ("n_frames", 0), ("height", 63)):
+        d, _ = _good()
+        setattr(d, field, value)
+        assert _align_call(d, p) == binding.HMFSR_E_INVALID
+    assert _align_call(desc, p, frames=None) == binding.HMFSR_E_INVALID
+    assert _align_call(desc, p, motion=None) == binding.HMFSR_E_INVALID
+    assert _align_call(desc, p, frames=2) == binding.HMFSR_E_INVALID      # not 4-byte aligned
+    assert _align_call(desc, p, motion=4) == binding.HMFSR_E_INVALID      # not 8-byte aligned
+    assert _align_call(desc, p, bm=4) == binding.HMFSR_E_INVALID
+    with pytest.raises(binding.HmfsrError):
+        bad = binding.make_align_params({"levels": 0})
+        binding.hmfsr_align(desc, bad, 8, 8)
+    assert binding.make_align_params({"lk_iterations": 5}).lk_iterations == 5

@@ -1,0 +1,159 @@
+"""Tile alignment (hmfsr_align through the C ABI) against the oracle.
+
+Block-matching vectors are integer results of exact integer arithmetic: they
+must agree bit for bit. The refined vectors are float64 sums in another order,
+returned as float32: |got - want| <= 1e-5 + 1e-6 |want| pixels (float32
+rounding of |v| <= 50 is under 4e-6; the float64 reordering is far below).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle.align as oa
+import oracle.merge as om
+from parity_util import assert_parity
+from paper_1905_03277_amd import synth, torch_ops
+from test_oracle_align import shifted_frames, textured_canvas
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def motion_close(got, want, what):
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    err = np.abs(got - want)
+    tol = 1e-5 + 1e-6 * np.abs(want)
+    bad = err > tol
+    assert not bad.any(), f"{what}: {int(bad.sum())} values off, worst {err.max():.3g} at " \
+                          f"{np.unravel_index(int(err.argmax()), err.shape)}"
+
+
+def gpu_align(frames, desc, params=None):
+    f = torch.as_tensor(frames).to(DEV) if not torch.is_tensor(frames) else frames.to(DEV)
+    m, bm = torch_ops.align(f.contiguous(), desc, params, block_match=True)
+    torch.cuda.synchronize()
+    return m.cpu().numpy(), bm.cpu().numpy()
+
+
+def check_full(frames, desc, params=None, what=""):
+    print("[case]", what, tuple(frames.shape), desc.tile_size, desc.ref_frame, params, flush=True)
+    m, bm = gpu_align(torch.from_numpy(frames), desc, params)
+    want, steps = oa.align(frames, desc, params, debug=True)
+    for k in range(frames.shape[0]):
+        if k == desc.ref_frame:
+            assert not bm[k].any() and not m[k].any()
+        else:
+            np.testing.assert_array_equal(bm[k], steps[k]["block_match"], err_msg=f"{what} frame {k}")
+    motion_close(m, want, what)
+    return m, bm
+
+
+def test_workload_8x256x256():
+    b = synth.make_config(1)
+    f, _ = b.numpy()
+    check_full(f, b.desc, what="8x256x256 t16")
+
+
+@pytest.mark.parametrize("n,h,w,tile,ref,params", [
+    (6, 200, 264, 32, 2, None),                                     # ragged blocks on every level
+    (4, 256, 320, 64, 0, None),                                     # 32 x 32 tiles, 64 x 64 windows
+    (3, 64, 96, 8, 1, {"levels": 2, "radius_coarse": 3, "radius_fine": 1}),
+    (5, 150, 266, 16, 4, {"radius_coarse": 8, "radius_fine": 8}),    # odd level sizes, widest search
+    (3, 4, 6, 8, 0, None),                                           # smallest frame: one partial tile
+    (4, 128, 128, 16, 0, {"levels": 6}),                             # as many levels as fit
+])
+def test_shapes_and_params(n, h, w, tile, ref, params):
+    b = synth.make_burst(n, h, w, seed=5100 + h + w, tile_size=tile, scene="texture", sigma_t=2.5)
+    d = b.desc.replace(ref_frame=ref)
+    f, _ = b.numpy()
+    check_full(f, d, params, what=f"{n}x{h}x{w} t{tile}")
+
+
+def test_default_scene_nonzero_ref():
+    b = synth.make_burst(5, 192, 160, seed=5200, tile_size=16, occluder=True)
+    f, _ = b.numpy()
+    check_full(f, b.desc.replace(ref_frame=3), what="default scene ref 3")
+
+
+def test_without_refinement_and_pyramid():
+    b = synth.make_burst(4, 96, 128, seed=5300, tile_size=16, scene="texture")
+    f, _ = b.numpy()
+    m, bm = check_full(f, b.desc, {"levels": 1, "lk_iterations": 0}, what="L1 no LK")
+    np.testing.assert_array_equal(m, 2.0 * bm)
+
+
+def test_single_frame_gives_zero():
+    b = synth.make_burst(1, 64, 64, seed=5400, tile_size=16)
+    m, bm = gpu_align(b.frames, b.desc)
+    assert m.shape == (1, 4, 4, 2) and not m.any() and not bm.any()
+
+
+def test_flat_frames_give_zero():
+    f = np.full((3, 64, 96), 777, dtype=np.uint16)
+    d = synth.Desc(3, 64, 96, tile_size=16)
+    m, bm = gpu_align(torch.from_numpy(f), d)
+    assert not m.any() and not bm.any()
+
+
+def test_even_integer_shift_exact():
+    h = w = 256
+    pad = 48
+    canvas = textured_canvas(h + 2 * pad, seed=5)
+    frames = shifted_frames(canvas, h, w, pad, [(0, 0), (40, -24), (-6, 10)])
+    d = synth.Desc(3, h, w, tile_size=16)
+    m, bm = check_full(np.ascontiguousarray(frames), d, what="integer shifts")
+    assert tuple(m[1, 8, 4]) == (40.0, -24.0)
+    assert tuple(m[2, 8, 8]) == (-6.0, 10.0)
+
+
+def test_repeatable_bits():
+    b = synth.make_config(1)
+    m1, bm1 = gpu_align(b.frames, b.desc)
+    m2, bm2 = gpu_align(b.frames, b.desc)
+    np.testing.assert_array_equal(m1, m2)
+    np.testing.assert_array_equal(bm1, bm2)
+
+
+def test_ground_truth_recovery():
+    b = synth.make_burst(8, 256, 256, seed=synth.config_seed(6, 0), scene="texture",
+                         noise_a=1e-5, noise_b=1e-8)
+    m, _ = gpu_align(b.frames, b.desc)
+    _, gt = b.numpy()
+    e = np.hypot(*(m[1:] - gt[1:])[:, 1:-1, 1:-1].reshape(-1, 2).T)
+    assert np.median(e) < 0.05 and np.percentile(e, 99) < 0.2
+
+
+def test_align_then_merge_matches_oracle_merge():
+    """Raw burst to RGB: the merge of the library's own vectors equals the
+    oracle merge of the same vectors."""
+    b = synth.make_burst(6, 128, 160, seed=5500, tile_size=16, scale=1.5)
+    fr = b.frames.to(DEV)
+    m = torch_ops.align(fr, b.desc)
+    out = torch_ops.merge_raw(fr, b.desc, b.tuning)
+    torch.cuda.synchronize()
+    f, _ = b.numpy()
+    want = om.merge(f, m.cpu().numpy(), b.desc, b.tuning)
+    assert_parity(out.cpu().numpy(), want, "align + merge")
+
+
+def test_full_size_12mp_sampled_tiles():
+    """8 x 3024 x 4032 (with the moving occluder), the launch configuration
+    the benchmark times; tiles sampled over the grid, corners and edges
+    included, recomputed one by one by the oracle."""
+    b = synth.make_config(2, device=DEV)
+    d = b.desc
+    m, bm = gpu_align(b.frames, d)
+    f = b.frames.cpu().numpy()
+    rng = np.random.default_rng(77)
+    ty_n, tx_n = d.tiles_y, d.tiles_x
+    tiles = [(0, 0), (0, tx_n - 1), (ty_n - 1, 0), (ty_n - 1, tx_n - 1), (ty_n // 2, tx_n // 2)]
+    tiles += [(int(rng.integers(ty_n)), int(rng.integers(tx_n))) for _ in range(20)]
+    for k in (1, 5, 7):
+        print("[case] 12MP frame", k, flush=True)
+        want, want_bm = oa.align_sampled(f, d, k, tiles)
+        got = np.stack([m[k, ty, tx] for ty, tx in tiles])
+        got_bm = np.stack([bm[k, ty, tx] for ty, tx in tiles])
+        np.testing.assert_array_equal(got_bm, want_bm)
+        motion_close(got, want, f"12MP frame {k}")
+    assert not m[0].any()
