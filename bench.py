@@ -9,7 +9,8 @@ kernel's roofline position and the FP64 oracle's CPU rate on a bounded sample.
                     [--no-batch] [--no-grad]
 
 More legs follow the headline measurement and are reported inside its line:
-the same burst merged frame by frame through the streaming calls, the
+the same burst merged frame by frame through the streaming calls, its tile
+alignment and the raw-burst-to-RGB time (alignment then merge), the
 64-burst batched workload (one graph replay vs per-burst launches) and the
 differentiation workload (16 bursts of 8 x 768 x 1024 at scale 2, forward
 plus adjoint).
@@ -232,6 +233,53 @@ def bench_stream(burst, out, reps: int = 5) -> dict:
             "state_bytes": 9 * 4 * d.out_height * d.out_width}
 
 
+def bench_align(burst, out, reps: int = 10) -> dict:
+    """Tile alignment (Sec. 3.2) of the same 12 MP x 8 burst: pyramid, block
+    matching on every level, Lucas-Kanade; and raw burst to RGB (alignment then
+    merge). Per-stage time from the library's own event timing."""
+    import torch
+    from paper_1905_03277_amd import binding, torch_ops
+
+    d = burst.desc
+    motion = torch.empty_like(burst.motion)
+
+    def al():
+        torch_ops.align(burst.frames, d, motion=motion)
+
+    def raw():
+        al()
+        torch_ops.merge(burst.frames, motion, d, burst.tuning, out=out)
+
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, fn in (("align", al), ("raw_to_rgb", raw)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / reps
+    binding.hmfsr_profile_begin()
+    for _ in range(reps):
+        al()
+    st = binding.hmfsr_profile_end()
+    tot, cnt = st["align"]
+    in_mp = d.n_frames * d.height * d.width / 1e6
+    tiles = d.tiles_y * d.tiles_x
+    alg_bytes = 2 * d.n_frames * d.height * d.width + 8 * d.n_frames * tiles
+    return {"workload": "alignment of the 12 MP x 8 burst (4 levels, radii 4/2, 3 Lucas-Kanade "
+                        "iterations, 16 px tiles)",
+            "ms": round(res["align"], 3), "MPs": round(in_mp / (res["align"] / 1e3), 1),
+            "stage_ms": round(tot / max(cnt, 1), 3),
+            "hbm_algorithmic_bytes": alg_bytes,
+            "hbm_frac": round(alg_bytes / (res["align"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "raw_to_rgb_ms": round(res["raw_to_rgb"], 3),
+            "raw_to_rgb_MPs": round(in_mp / (res["raw_to_rgb"] / 1e3), 1)}
+
+
 def bench_grad(dev, reps: int = 3) -> dict:
     """The differentiation workload: 16 bursts of 8 x 768 x 1024 RGGB at scale 2.
     One pass = for every burst, the forward merge (keeping the normaliser of
@@ -384,6 +432,7 @@ def main():
         "wall_s_timed": round(wall, 3),
     }
     line["streaming"] = bench_stream(burst, out)
+    line["alignment"] = bench_align(burst, out)
     if not args.no_batch:
         line["batched"] = bench_batch(dev)
     if not args.no_grad:

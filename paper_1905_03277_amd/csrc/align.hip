@@ -9,6 +9,8 @@
 // the error image run in float64.
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "device_util.h"
 #include "hmfsr_internal.h"
 
@@ -16,7 +18,7 @@ namespace hmfsr {
 namespace {
 
 constexpr int kPyrEdge = 64;       // level-0 pixels per pyramid workgroup edge
-constexpr int kAlignThreads = 256;
+constexpr int kAlignThreads = 256;   // pyramid workgroup
 
 // ---- pyramid ------------------------------------------------------------------
 // Workgroup = a 64 x 64 region of level 0 (128 x 128 raw pixels) of one frame;
@@ -102,75 +104,179 @@ __device__ __forceinline__ Key shfl_key(const Key& a, int off) {
   return o;
 }
 
-// One wave per block of one non-base frame; the lanes take the candidates.
-// LDS per wave: the base block (B x B) and the frame's search region
-// ((B + 2R)^2, edge-replicated).
-__global__ __launch_bounds__(kAlignThreads) void k_align_match(const int32_t* __restrict__ pyr,
-                                                               int2* __restrict__ vecs, MatchLevel ml, int ref,
-                                                               long long fstride, long long vstride,
-                                                               int items) {
+// Persistent launches: kWaves independent waves per workgroup. Wave w of
+// workgroup b (XCD-aware order) takes the contiguous item range
+// [(4b + w) * chunk, (4b + w + 1) * chunk), so neighbouring items share an L2.
+// A wave synchronises only with itself: its LDS region is private.
+constexpr int kWaves = 4;
+constexpr int kGroupsPerCU = 8;
+
+// Cross-lane visibility of a wave's own LDS writes: the LDS executes one
+// wave's operations in order, so only compiler reordering must be fenced.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Raw buffer resource over n 32-bit words (word 3 as for gfx9 raw buffers).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t words_rsrc(const int32_t* p, long long n) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, 0, (int)(n * 4), 0x00020000);
+}
+
+__device__ __forceinline__ int32_t ld_word(__amdgpu_buffer_rsrc_t r, int idx) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0);
+}
+
+// A rows x cols window of one h x w level image (top-left (y0, x0), indices
+// clamped to the image) bound for LDS with row stride ld.
+struct Win {
+  __amdgpu_buffer_rsrc_t src;
+  int32_t* dst;
+  int ld, y0, x0, rows, cols;
+};
+
+// Copy two windows into LDS. Per round every lane issues up to U loads of each
+// window (slots past the window's end are skipped by a wave-uniform test; the
+// last slot's tail lanes load a clamped duplicate and do not store), and every
+// load of the round is issued before its stores, so a window of up to 64 U
+// words costs one memory round trip.
+template <int U>
+__device__ __forceinline__ void stage_pair(const Win& A, const Win& B, int h, int w, int lane) {
+  const int ta = A.rows * A.cols, tb = B.rows * B.cols;
+  const float ia = 1.0f / (float)A.cols, ib = 1.0f / (float)B.cols;
+  for (int i0 = 0; i0 < ta || i0 < tb; i0 += 64 * U) {
+    int va[U], vb[U], aa[U], ab[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      aa[u] = -1;
+      ab[u] = -1;
+      va[u] = 0;
+      vb[u] = 0;
+      const int i = i0 + u * 64 + lane;
+      if (i0 + u * 64 < ta) {
+        const int ic = min(i, ta - 1);
+        const int r = split_row(ic, ia), c = ic - r * A.cols;
+        if (i < ta) aa[u] = r * A.ld + c;
+        va[u] = ld_word(A.src, clampi(A.y0 + r, 0, h - 1) * w + clampi(A.x0 + c, 0, w - 1));
+      }
+      if (i0 + u * 64 < tb) {
+        const int ic = min(i, tb - 1);
+        const int r = split_row(ic, ib), c = ic - r * B.cols;
+        if (i < tb) ab[u] = r * B.ld + c;
+        vb[u] = ld_word(B.src, clampi(B.y0 + r, 0, h - 1) * w + clampi(B.x0 + c, 0, w - 1));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (aa[u] >= 0) A.dst[aa[u]] = va[u];
+      if (ab[u] >= 0) B.dst[ab[u]] = vb[u];
+    }
+  }
+}
+
+// Block matching of one level: one wave per block of one non-base frame. LDS
+// per wave: the base block (B x B), the frame's search region ((B + 2R)^2,
+// edge-replicated) and the partial costs. Tasks = candidates x G row groups
+// with a fixed lane assignment; the row-group partials of each candidate are
+// then added in a fixed order (groups past the block's last row add 0).
+// EXACT_F64: every level value is below 2^22 (levels 0-2 of 16-bit frames), so
+// squared differences and their sums stay below 2^53 and float64 adds them
+// exactly; coarser levels add in 64-bit integers.
+template <bool EXACT_F64>
+__global__ __launch_bounds__(64 * kWaves) void k_align_match(const int32_t* __restrict__ pyr, int2* __restrict__ vecs,
+                                                             MatchLevel ml, int ref, long long fstride,
+                                                             long long vstride, int items, int chunk) {
   extern __shared__ int32_t smem[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int B = ml.B, R = ml.R, E = B + 2 * R, D = 2 * R + 1;
-  int32_t* tpl = smem + wave * (B * B + E * E);
+  const int B = ml.B, R = ml.R, E = B + 2 * R, D = 2 * R + 1, K = D * D;
+  const int words = (B * B + E * E + 1) & ~1;
+  const int tasks_max = K >= 64 ? K : 64;
+  int32_t* tpl = smem + wave * (words + 2 * tasks_max);
   int32_t* reg = tpl + B * B;
-  const int blk = xcd_tile(blockIdx.x, gridDim.x);
-  const int item = blk * (blockDim.x >> 6) + wave;
-  const bool valid = item < items;
+  unsigned long long* part = (unsigned long long*)(tpl + words);
+  const int G = K >= 64 ? 1 : min(64 / K, B);
+  const int n_tasks = K * G;
+  // the lane's first task, fixed for every block
+  const int g0 = lane / K, k0 = lane - g0 * K;
+  const int dyi0 = k0 / D, dxi0 = k0 - dyi0 * D;
   const int per = ml.gby * ml.gbx;
-  const int fi = valid ? item / per : 0;
-  const int t = valid ? item - fi * per : 0;
-  const int by = t / ml.gbx, bx = t - (t / ml.gbx) * ml.gbx;
-  const int f = fi < ref ? fi : fi + 1;
-  const int32_t* base = pyr + (long long)ref * fstride + ml.loff;
-  const int32_t* img = pyr + (long long)f * fstride + ml.loff;
-  int gx = 0, gy = 0;
-  if (valid && ml.parent) {
-    const int cy = min(((2 * by + 1) * B) / (4 * ml.pB), ml.pgby - 1);
-    const int cx = min(((2 * bx + 1) * B) / (4 * ml.pB), ml.pgbx - 1);
-    const int2 pv = vecs[(long long)f * vstride + ml.pvoff + (long long)cy * ml.pgbx + cx];
-    gx = 2 * pv.x;
-    gy = 2 * pv.y;
-  }
-  const int y0 = by * B, x0 = bx * B;
-  const int nby = min(B, ml.h - y0), nbx = min(B, ml.w - x0);
-  if (valid) {
-    for (int r = 0; r < nby; ++r)
-      if (lane < nbx) tpl[r * B + lane] = base[(long long)(y0 + r) * ml.w + x0 + lane];
-    for (int r = 0; r < E; ++r) {
-      const int yy = clampi(y0 + gy - R + r, 0, ml.h - 1);
-      if (lane < E) {
-        const int xx = clampi(x0 + gx - R + lane, 0, ml.w - 1);
-        reg[r * E + lane] = img[(long long)yy * ml.w + xx];
-      }
+  const int gw = xcd_tile(blockIdx.x, gridDim.x) * kWaves + wave;
+  const int c0 = gw * chunk, c1 = min(items, c0 + chunk);
+  const long long lvl_words = (long long)ml.h * ml.w;
+  const __amdgpu_buffer_rsrc_t rs_base = words_rsrc(pyr + (long long)ref * fstride + ml.loff, lvl_words);
+  for (int item = c0; item < c1; ++item) {
+    const int fi = item / per;
+    const int t = item - fi * per;
+    const int by = t / ml.gbx, bx = t - (t / ml.gbx) * ml.gbx;
+    const int f = fi < ref ? fi : fi + 1;
+    int gx = 0, gy = 0;
+    if (ml.parent) {
+      const int cy = min(((2 * by + 1) * B) / (4 * ml.pB), ml.pgby - 1);
+      const int cx = min(((2 * bx + 1) * B) / (4 * ml.pB), ml.pgbx - 1);
+      const int2 pv = vecs[(long long)f * vstride + ml.pvoff + cy * ml.pgbx + cx];
+      gx = 2 * pv.x;
+      gy = 2 * pv.y;
     }
-  }
-  __syncthreads();
-  if (!valid) return;
-  Key best{~0ull, 0x7fffffff, 0x7fffffff};
-  for (int k = lane; k < D * D; k += 64) {
-    const int dyi = k / D, dxi = k - (k / D) * D;  // offsets + R
-    unsigned long long ssd = 0;
-    for (int r = 0; r < nby; ++r) {
-      const int32_t* tr = tpl + r * B;
-      const int32_t* rr = reg + (r + dyi) * E + dxi;
-      for (int c = 0; c < nbx; ++c) {
-        const long long d = (long long)(rr[c] - tr[c]);
-        ssd += (unsigned long long)(d * d);
-      }
+    const int nby = min(B, ml.h - by * B), nbx = min(B, ml.w - bx * B);
+    {
+      const Win A{rs_base, tpl, B, by * B, bx * B, nby, nbx};
+      const Win Bw{words_rsrc(pyr + (long long)f * fstride + ml.loff, lvl_words), reg, E, by * B + gy - R,
+                   bx * B + gx - R, E, E};
+      stage_pair<4>(A, Bw, ml.h, ml.w, lane);
     }
-    const int dx = dxi - R, dy = dyi - R;
-    const Key cand{ssd, dx * dx + dy * dy, k};
-    if (key_less(cand, best)) best = cand;
-  }
+    wave_sync();
+    for (int task = lane; task < n_tasks; task += 64) {
+      int g = g0, dyi = dyi0, dxi = dxi0;
+      if (task != lane) {
+        g = task / K;
+        const int k = task - g * K;
+        dyi = k / D;
+        dxi = k - dyi * D;
+      }
+      unsigned long long ssd = 0;
+      if (EXACT_F64) {
+        double acc = 0.0;
+        for (int r = g; r < nby; r += G) {
+          const int32_t* tr = tpl + r * B;
+          const int32_t* rr = reg + (r + dyi) * E + dxi;
+          for (int c = 0; c < nbx; ++c) {
+            const double d = (double)(rr[c] - tr[c]);
+            acc = fma(d, d, acc);
+          }
+        }
+        ssd = (unsigned long long)acc;
+      } else {
+        for (int r = g; r < nby; r += G) {
+          const int32_t* tr = tpl + r * B;
+          const int32_t* rr = reg + (r + dyi) * E + dxi;
+          for (int c = 0; c < nbx; ++c) {
+            const long long d = (long long)(rr[c] - tr[c]);
+            ssd += (unsigned long long)(d * d);
+          }
+        }
+      }
+      part[task] = ssd;
+    }
+    wave_sync();
+    Key best{~0ull, 0x7fffffff, 0x7fffffff};
+    for (int k = lane; k < K; k += 64) {
+      unsigned long long ssd = 0;
+      for (int g = 0; g < G; ++g) ssd += part[g * K + k];
+      const int dy = k / D, dx = k - dy * D;
+      const Key cand{ssd, (dx - R) * (dx - R) + (dy - R) * (dy - R), k};
+      if (key_less(cand, best)) best = cand;
+    }
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const Key o = shfl_key(best, off);
-    if (key_less(o, best)) best = o;
-  }
-  if (lane == 0) {
-    const int dyi = best.k / D, dxi = best.k - (best.k / D) * D;
-    vecs[(long long)f * vstride + ml.voff + t] = make_int2(gx + dxi - R, gy + dyi - R);
+    for (int off = 32; off >= 1; off >>= 1) {
+      const Key o = shfl_key(best, off);
+      if (key_less(o, best)) best = o;
+    }
+    if (lane == 0) {
+      const int dyi = best.k / D, dxi = best.k - (best.k / D) * D;
+      vecs[(long long)f * vstride + ml.voff + t] = make_int2(gx + dxi - R, gy + dyi - R);
+    }
+    wave_sync();  // the next block restages this wave's LDS
   }
 }
 
@@ -184,108 +290,264 @@ struct LkArgs {
   long long fstride, vstride, voff0;
 };
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+// Same value in every lane: make it a scalar.
+__device__ __forceinline__ double uniform(double v) {
+  const unsigned long long u = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(u & 0xffffffffull));
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-__device__ __forceinline__ long long wave_sum_ll(long long v) {
+// Lane exchanges with the partner whose lane index differs in bit BIT (and,
+// for BIT <= 3, possibly in lower bits too): bits 5 and 4 through the LDS
+// crossbar, bits 3..0 through DPP (row_mirror: i <-> 15 - i, row_half_mirror:
+// i <-> 7 - i, quad permutations [2,3,0,1] and [1,0,3,2]; gfx9 encodings).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const unsigned long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+template <int BIT>
+__device__ __forceinline__ double partner(double v) {
+  if constexpr (BIT == 5) return __shfl_xor(v, 32, 64);
+  else if constexpr (BIT == 4) return __shfl_xor(v, 16, 64);
+  else if constexpr (BIT == 3) return dpp_move<0x140>(v);
+  else if constexpr (BIT == 2) return dpp_move<0x141>(v);
+  else if constexpr (BIT == 1) return dpp_move<0x4E>(v);
+  else return dpp_move<0xB1>(v);
+}
+
+// Halving step: of N values a lane keeps the half its bit BIT selects, added
+// to the partner's copy of that half; the partner keeps the other half.
+template <int BIT, int N>
+__device__ __forceinline__ void halve(const double* in, double* out, int lane) {
+  const bool up = (lane >> BIT) & 1;
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const unsigned lo = __shfl_xor((unsigned)((unsigned long long)v & 0xffffffffull), off, 64);
-    const int hi = __shfl_xor((int)(v >> 32), off, 64);
-    v += (long long)(((unsigned long long)(unsigned)hi << 32) | lo);
+  for (int i = 0; i < N / 2; ++i) {
+    const double keep = up ? in[i + N / 2] : in[i], send = up ? in[i] : in[i + N / 2];
+    out[i] = keep + partner<BIT>(send);
   }
-  return v;
 }
 
-// One wave per (frame, tile). LDS per wave: the base window with a one-pixel
-// edge-replicated border, for the central differences. The butterfly sums
-// leave the same bits in every lane (addition commutes), so the update is
-// uniform across the wave.
-__global__ __launch_bounds__(kAlignThreads) void k_align_lk(const int32_t* __restrict__ pyr,
-                                                            const int2* __restrict__ vecs, LkArgs a,
-                                                            float2* __restrict__ motion,
-                                                            int2* __restrict__ bm_out, int items, int sw) {
+// Sums of 24 per-lane values over each group of LPG (16 or 64) lanes, written
+// to tbl[0..24) of the group by one lane per value. Each partner step pairs
+// lanes of disjoint orbits, so after log2(LPG) steps every sum covers the
+// whole group. Every value is an integer below 2^53: the sums are exact in any
+// order.
+template <int LPG>
+__device__ __forceinline__ void group_sum24(const double* v, double* tbl, int lane, bool write) {
+  constexpr int TOP = LPG == 16 ? 3 : 5;
+  double a[12], b[6], c[3];
+  halve<TOP, 24>(v, a, lane);
+  halve<TOP - 1, 12>(a, b, lane);
+  halve<TOP - 2, 6>(b, c, lane);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    if constexpr (TOP - 3 >= 2) c[j] += partner<2>(c[j]);
+    if constexpr (TOP - 3 >= 1) c[j] += partner<1>(c[j]);
+    c[j] += partner<0>(c[j]);
+  }
+  if (write && (lane & ((1 << (TOP - 2)) - 1)) == 0) {
+    const int i0 = 12 * ((lane >> TOP) & 1) + 6 * ((lane >> (TOP - 1)) & 1) + 3 * ((lane >> (TOP - 2)) & 1);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) tbl[i0 + j] = c[j];
+  }
+}
+
+// Copy the bordered base window and the frame's bordered patch of one tile
+// into LDS, by the LPG lanes of its group (l = lane within the group). Base
+// loads go through the base frame's buffer resource, frame loads through a
+// per-lane pointer (the groups of a wave may hold different frames).
+template <int LPG, int U>
+__device__ __forceinline__ void stage_tile(int32_t* SB, int32_t* SM, int SWW, int rows, __amdgpu_buffer_rsrc_t rs_base,
+                                           const int32_t* img, int h, int w, int by0, int bx0, int my0, int mx0,
+                                           bool base_too, int l) {
+  const int total = rows * SWW;
+  const float inv = 1.0f / (float)SWW;
+  for (int i0 = 0; i0 < total; i0 += LPG * U) {
+    int vb[U], vm[U], at[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      at[u] = -1;
+      vb[u] = 0;
+      vm[u] = 0;
+      const int i = i0 + u * LPG + l;
+      if (i < total) {
+        const int r = split_row(i, inv), c = i - r * SWW;
+        at[u] = r * SWW + c;
+        if (base_too) vb[u] = ld_word(rs_base, clampi(by0 + r, 0, h - 1) * w + clampi(bx0 + c, 0, w - 1));
+        vm[u] = img[clampi(my0 + r, 0, h - 1) * w + clampi(mx0 + c, 0, w - 1)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (at[u] >= 0) {
+        if (base_too) SB[at[u]] = vb[u];
+        SM[at[u]] = vm[u];
+      }
+  }
+}
+
+// Per-lane partial sums of one tile over the columns l, l + LPG, ... of its
+// window, each walked top to bottom with the 3 x 3 frame neighbourhood and
+// the base column kept in registers: [0, 9) sum D_x I(o), [9, 18) sum D_y I(o),
+// o = (oy + 1) * 3 + ox + 1; with BASE also 18, 19: sum D_x T, sum D_y T and
+// 20, 21, 22: sum D_x^2, D_x D_y, D_y^2. Products are below 2^37 and sums below
+// 2^49, so float64 keeps them exact.
+template <int LPG, bool BASE>
+__device__ __forceinline__ void tile_sums(const int32_t* SB, const int32_t* SM, int SWW, int WH, int WW, int l,
+                                          double* acc) {
+#pragma unroll
+  for (int i = 0; i < 24; ++i) acc[i] = 0.0;
+  for (int c = l; c < WW; c += LPG) {
+    const int32_t* b = SB + c + 1;
+    const int32_t* m = SM + c;
+    double m0[3], m1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      m0[k] = (double)m[k];
+      m1[k] = (double)m[SWW + k];
+    }
+    int bu = b[0], bc = b[SWW];
+    for (int r = 0; r < WH; ++r) {
+      const int32_t* m2p = m + (r + 2) * SWW;
+      const double m2[3] = {(double)m2p[0], (double)m2p[1], (double)m2p[2]};
+      const int32_t* brow = b + (r + 1) * SWW;
+      const int bd = b[(r + 2) * SWW];
+      const double dx = (double)(brow[1] - brow[-1]), dy = (double)(bd - bu);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        acc[k] = fma(dx, m0[k], acc[k]);
+        acc[3 + k] = fma(dx, m1[k], acc[3 + k]);
+        acc[6 + k] = fma(dx, m2[k], acc[6 + k]);
+        acc[9 + k] = fma(dy, m0[k], acc[9 + k]);
+        acc[12 + k] = fma(dy, m1[k], acc[12 + k]);
+        acc[15 + k] = fma(dy, m2[k], acc[15 + k]);
+      }
+      if (BASE) {
+        const double tv = (double)bc;
+        acc[18] = fma(dx, tv, acc[18]);
+        acc[19] = fma(dy, tv, acc[19]);
+        acc[20] = fma(dx, dx, acc[20]);
+        acc[21] = fma(dx, dy, acc[21]);
+        acc[22] = fma(dy, dy, acc[22]);
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        m0[k] = m1[k];
+        m1[k] = m2[k];
+      }
+      bu = bc;
+      bc = bd;
+    }
+  }
+}
+
+// Lucas-Kanade, LPG lanes per (frame, tile): 16 (four tiles per wave) for
+// tiles of up to 8 half-res pixels, else 64. The displacement is uniform over
+// the tile, so with D = 2 g the integer central differences of the base
+// window, the normal equations need only integer correlations:
+//   sum_p D(p) e(p) = sum_corners w_c sum_p D(p) I(p + o_c) - sum_p D(p) T(p),
+// o_c the four integer corners of the bilinear sample and w_c their weights.
+// The correlations at the 3 x 3 integer offsets around a centre (first the
+// block-matching vector) serve every iteration whose sample cell stays within
+// them; a step that leaves them re-centres that tile and recomputes. LDS per
+// group: the bordered base window and frame patch, and the 24 sums.
+template <int LPG>
+__global__ __launch_bounds__(256) void k_align_lk(const int32_t* __restrict__ pyr, const int2* __restrict__ vecs,
+                                                  LkArgs a, float2* __restrict__ motion, int2* __restrict__ bm_out,
+                                                  int items, int chunk, int sw) {
+  constexpr int GPW = 64 / LPG;  // tiles per wave
   extern __shared__ int32_t smem[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int32_t* S = smem + wave * sw * sw;
-  const int blk = xcd_tile(blockIdx.x, gridDim.x);
-  const int item = blk * (blockDim.x >> 6) + wave;
-  const bool valid = item < items;
+  const int g = lane / LPG, l = lane % LPG;
+  const int grp_words = 2 * sw * sw + 48;  // two windows, then 24 doubles (sw even keeps them aligned)
+  int32_t* SB = smem + (wave * GPW + g) * grp_words;
+  int32_t* SM = SB + sw * sw;
+  double* tbl = (double*)(SM + sw * sw);
   const int per = a.TY * a.TX;
-  const int f = valid ? item / per : 0;
-  const int t = valid ? item - f * per : 0;
-  const int ty = t / a.TX, tx = t - (t / a.TX) * a.TX;
-  const bool work = valid && f != a.ref;
-  const int wy0 = max(0, ty * a.B - a.m), wy1 = min(ty * a.B + a.B + a.m, a.h);
-  const int wx0 = max(0, tx * a.B - a.m), wx1 = min(tx * a.B + a.B + a.m, a.w);
-  const int WH = wy1 - wy0, WW = wx1 - wx0, SWW = WW + 2;
-  const int32_t* base = pyr + (long long)a.ref * a.fstride;
-  if (work) {
-    for (int r = 0; r < WH + 2; ++r) {
-      const int yy = clampi(wy0 - 1 + r, 0, a.h - 1);
-      for (int c = lane; c < SWW; c += 64) S[r * SWW + c] = base[(long long)yy * a.w + clampi(wx0 - 1 + c, 0, a.w - 1)];
+  const int gw = xcd_tile(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
+  const int c0 = gw * chunk, c1 = min(items, c0 + chunk);
+  const long long lvl_words = (long long)a.h * a.w;
+  const __amdgpu_buffer_rsrc_t rs_base = words_rsrc(pyr + (long long)a.ref * a.fstride, lvl_words);
+  for (int q0 = c0; q0 < c1; q0 += GPW) {
+    const int item = q0 + g;
+    const int f = item / per;
+    const bool valid = item < c1;
+    const bool work = valid && f != a.ref;
+    const int t = item - f * per;
+    const int ty = t / a.TX, tx = t - (t / a.TX) * a.TX;
+    const int wy0 = max(0, ty * a.B - a.m), wy1 = min(ty * a.B + a.B + a.m, a.h);
+    const int wx0 = max(0, tx * a.B - a.m), wx1 = min(tx * a.B + a.B + a.m, a.w);
+    const int WH = wy1 - wy0, WW = wx1 - wx0, SWW = WW + 2;
+    const int32_t* img = pyr + (long long)(work ? f : a.ref) * a.fstride;
+    int2 bm = make_int2(0, 0);
+    if (work) bm = vecs[(long long)f * a.vstride + a.voff0 + t];
+    int ccx = bm.x, ccy = bm.y;  // centre of the 3 x 3 correlation offsets
+    if (work)
+      stage_tile<LPG, LPG == 16 ? 11 : 8>(SB, SM, SWW, WH + 2, rs_base, img, a.h, a.w, wy0 - 1, wx0 - 1,
+                                           wy0 - 1 + ccy, wx0 - 1 + ccx, true, l);
+    wave_sync();
+    double acc[24];
+    if (work) tile_sums<LPG, true>(SB, SM, SWW, WH, WW, l, acc);
+    else {
+#pragma unroll
+      for (int i = 0; i < 24; ++i) acc[i] = 0.0;
     }
-  }
-  __syncthreads();
-  if (!valid) return;
-  if (!work) {
-    if (lane == 0) {
-      motion[item] = make_float2(0.f, 0.f);
-      if (bm_out) bm_out[item] = make_int2(0, 0);
-    }
-    return;
-  }
-  const int2 bm = vecs[(long long)f * a.vstride + a.voff0 + t];
-  const int n_px = WH * WW;
-  long long hxx = 0, hxy = 0, hyy = 0;
-  for (int i = lane; i < n_px; i += 64) {
-    const int r = i / WW, c = i - (i / WW) * WW;
-    const int32_t* s = S + (r + 1) * SWW + c + 1;
-    const long long dx = s[1] - s[-1], dy = s[SWW] - s[-SWW];
-    hxx += dx * dx;
-    hxy += dx * dy;
-    hyy += dy * dy;
-  }
-  const double Hxx = (double)wave_sum_ll(hxx), Hxy = (double)wave_sum_ll(hxy), Hyy = (double)wave_sum_ll(hyy);
-  // Singular-window test on the exact sums, rounded step by step as written
-  // (no fused multiply-add), so that it is decided identically everywhere.
-  const double tr = __dadd_rn(Hxx, Hyy);
-  const double det = __dsub_rn(__dmul_rn(Hxx, Hyy), __dmul_rn(Hxy, Hxy));
-  const double thr = __dmul_rn(__dmul_rn(1e-9, tr), tr);
-  double vx = bm.x, vy = bm.y;
-  if (tr > 0.0 && det > thr) {
-    const int32_t* img = pyr + (long long)f * a.fstride;
+    group_sum24<LPG>(acc, tbl, lane, true);
+    wave_sync();
+    const double Hxx = tbl[20], Hxy = tbl[21], Hyy = tbl[22], STx = tbl[18], STy = tbl[19];
+    // Singular-window test on the exact sums, rounded step by step as written
+    // (no fused multiply-add), so that it is decided identically everywhere.
+    const double tr = __dadd_rn(Hxx, Hyy);
+    const double det = __dsub_rn(__dmul_rn(Hxx, Hyy), __dmul_rn(Hxy, Hxy));
+    const double thr = __dmul_rn(__dmul_rn(1e-9, tr), tr);
+    const bool ok = work && tr > 0.0 && det > thr;
+    const double k2 = ok ? 2.0 / det : 0.0;  // H and b here are 4x and 2x the half-gradient ones
+    double vx = bm.x, vy = bm.y;
     for (int it = 0; it < a.iters; ++it) {
-      double sx = 0.0, sy = 0.0;
-      for (int i = lane; i < n_px; i += 64) {
-        const int r = i / WW, c = i - (i / WW) * WW;
-        const int32_t* s = S + (r + 1) * SWW + c + 1;
-        const double x = (double)(wx0 + c) + vx, y = (double)(wy0 + r) + vy;
-        const double xf = floor(x), yf = floor(y);
-        const double fx = x - xf, fy = y - yf;
-        const int xi = (int)fmax(fmin(xf, 1e9), -1e9), yi = (int)fmax(fmin(yf, 1e9), -1e9);
-        const int xa = clampi(xi, 0, a.w - 1), xb = clampi(xi + 1, 0, a.w - 1);
-        const long long ya = (long long)clampi(yi, 0, a.h - 1) * a.w;
-        const long long yb = (long long)clampi(yi + 1, 0, a.h - 1) * a.w;
-        const double top = (1.0 - fx) * (double)img[ya + xa] + fx * (double)img[ya + xb];
-        const double bot = (1.0 - fx) * (double)img[yb + xa] + fx * (double)img[yb + xb];
-        const double err = (1.0 - fy) * top + fy * bot - (double)s[0];
-        sx += (double)(s[1] - s[-1]) * err;
-        sy += (double)(s[SWW] - s[-SWW]) * err;
+      const double fxf = floor(vx), fyf = floor(vy);
+      const bool need = ok && (fxf < ccx - 1 || fxf > ccx || fyf < ccy - 1 || fyf > ccy);
+      if (__any(need)) {
+        // the sample cell left the correlated offsets: re-centre those tiles
+        wave_sync();
+        if (need) {
+          ccx = (int)fmax(fmin(fxf, 1e9), -1e9);
+          ccy = (int)fmax(fmin(fyf, 1e9), -1e9);
+          stage_tile<LPG, LPG == 16 ? 11 : 8>(SB, SM, SWW, WH + 2, rs_base, img, a.h, a.w, 0, 0, wy0 - 1 + ccy,
+                                               wx0 - 1 + ccx, false, l);
+        }
+        wave_sync();
+        double acc2[24];
+        if (need) tile_sums<LPG, false>(SB, SM, SWW, WH, WW, l, acc2);
+        else {
+#pragma unroll
+          for (int i = 0; i < 24; ++i) acc2[i] = 0.0;
+        }
+        // every lane takes part in the exchanges; only re-centred groups
+        // overwrite their table
+        group_sum24<LPG>(acc2, tbl, lane, need);
+        wave_sync();
       }
-      sx = wave_sum(sx);
-      sy = wave_sum(sy);
-      // H and b here are 4x and 2x those of the half-gradient form.
-      vx -= 2.0 * (Hyy * sx - Hxy * sy) / det;
-      vy -= 2.0 * (Hxx * sy - Hxy * sx) / det;
+      if (ok) {
+        const double fx = vx - fxf, fy = vy - fyf;
+        const int o00 = ((int)(fyf - ccy) + 1) * 3 + (int)(fxf - ccx) + 1;
+        const double w00 = (1.0 - fx) * (1.0 - fy), w01 = fx * (1.0 - fy), w10 = (1.0 - fx) * fy, w11 = fx * fy;
+        const double sx = w00 * tbl[o00] + w01 * tbl[o00 + 1] + w10 * tbl[o00 + 3] + w11 * tbl[o00 + 4] - STx;
+        const double sy =
+            w00 * tbl[9 + o00] + w01 * tbl[9 + o00 + 1] + w10 * tbl[9 + o00 + 3] + w11 * tbl[9 + o00 + 4] - STy;
+        vx -= k2 * (Hyy * sx - Hxy * sy);
+        vy -= k2 * (Hxx * sy - Hxy * sx);
+      }
     }
-  }
-  if (lane == 0) {
-    motion[item] = make_float2((float)(2.0 * vx), (float)(2.0 * vy));
-    if (bm_out) bm_out[item] = bm;
+    if (valid && l == 0) {
+      motion[item] = make_float2((float)(2.0 * vx), (float)(2.0 * vy));
+      if (bm_out) bm_out[item] = bm;
+    }
+    wave_sync();  // the next tiles restage this wave's LDS
   }
 }
 
@@ -306,6 +568,18 @@ hipError_t launch_align(const AlignGeom& ag, const uint16_t* frames, int H, int 
   hipLaunchKernelGGL(k_align_pyramid, pg, dim3(kAlignThreads), 0, stream, frames, H, W, pyr, ag);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
+  int cus = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  // persistent grid: at most kGroupsPerCU workgroups of kWaves waves per CU,
+  // each wave a contiguous chunk of items
+  auto plan = [&](long long items, unsigned* groups, int* chunk) {
+    const long long waves = std::min<long long>(items, (long long)cus * kGroupsPerCU * kWaves);
+    const long long c = (items + waves - 1) / waves;
+    *chunk = (int)c;
+    *groups = (unsigned)(((items + c - 1) / c + kWaves - 1) / kWaves);
+  };
   if (ag.n > 1) {
     for (int l = ag.L - 1; l >= 0; --l) {
       MatchLevel ml;
@@ -322,11 +596,20 @@ hipError_t launch_align(const AlignGeom& ag, const uint16_t* frames, int H, int 
       ml.pgby = ml.parent ? ag.gby[l + 1] : 1;
       ml.pgbx = ml.parent ? ag.gbx[l + 1] : 1;
       ml.pvoff = ml.parent ? ag.voff[l + 1] : 0;
-      const int E = ml.B + 2 * ml.R;
-      const size_t lds = (size_t)(kAlignThreads / 64) * (ml.B * ml.B + E * E) * 4;
+      const int E = ml.B + 2 * ml.R, K = (2 * ml.R + 1) * (2 * ml.R + 1);
+      const int tasks = K >= 64 ? K : 64;
+      const size_t lds = (size_t)kWaves * (((ml.B * ml.B + E * E + 1) & ~1) + 2 * tasks) * 4;
       const long long items = (long long)(ag.n - 1) * ml.gby * ml.gbx;
-      hipLaunchKernelGGL(k_align_match, dim3(cdiv(items, kAlignThreads / 64)), dim3(kAlignThreads), lds, stream,
-                         pyr, vecs, ml, ag.ref, ag.fstride, ag.vstride, (int)items);
+      unsigned groups;
+      int chunk;
+      plan(items, &groups, &chunk);
+      // levels 0-2 of 16-bit frames stay below 2^22 (sums of 4^(l+1) values)
+      if (l <= 2)
+        hipLaunchKernelGGL(k_align_match<true>, dim3(groups), dim3(64 * kWaves), lds, stream, pyr, vecs, ml,
+                           ag.ref, ag.fstride, ag.vstride, (int)items, chunk);
+      else
+        hipLaunchKernelGGL(k_align_match<false>, dim3(groups), dim3(64 * kWaves), lds, stream, pyr, vecs, ml,
+                           ag.ref, ag.fstride, ag.vstride, (int)items, chunk);
       if ((err = hipGetLastError()) != hipSuccess) return err;
     }
   }
@@ -342,12 +625,23 @@ hipError_t launch_align(const AlignGeom& ag, const uint16_t* frames, int H, int 
   a.fstride = ag.fstride;
   a.vstride = ag.vstride;
   a.voff0 = ag.voff[0];
-  const int sw = a.B + 2 * a.m + 2;  // window edge with its border, at most
-  const int waves = sw > 34 ? 2 : 4;  // keeps LDS within 64 KiB per workgroup
+  const int sw = ((a.B + 2 * a.m + 2) + 1) & ~1;  // window edge with its border, at most; even
   const long long items = (long long)ag.n * a.TY * a.TX;
-  const size_t lds = (size_t)waves * sw * sw * 4;
-  hipLaunchKernelGGL(k_align_lk, dim3(cdiv(items, waves)), dim3(64 * waves), lds, stream, pyr, vecs, a,
-                     (float2*)motion, (int2*)block_match, (int)items, sw);
+  const int lpg = a.B <= 8 ? 16 : 64;
+  const int gpw = 64 / lpg;
+  const int waves = a.B <= 16 ? kWaves : 1;  // keeps LDS within 64 KiB per workgroup
+  const size_t lds = (size_t)waves * gpw * (2 * sw * sw + 48) * 4;
+  const long long total_waves =
+      std::min<long long>((items + gpw - 1) / gpw, (long long)cus * kGroupsPerCU * kWaves);
+  long long chunk = (items + total_waves - 1) / total_waves;
+  chunk = (chunk + gpw - 1) / gpw * gpw;
+  const unsigned groups = (unsigned)(((items + chunk - 1) / chunk + waves - 1) / waves);
+  if (lpg == 16)
+    hipLaunchKernelGGL(k_align_lk<16>, dim3(groups), dim3(64 * waves), lds, stream, pyr, vecs, a, (float2*)motion,
+                       (int2*)block_match, (int)items, (int)chunk, sw);
+  else
+    hipLaunchKernelGGL(k_align_lk<64>, dim3(groups), dim3(64 * waves), lds, stream, pyr, vecs, a, (float2*)motion,
+                       (int2*)block_match, (int)items, (int)chunk, sw);
   return hipGetLastError();
 }
 
