@@ -81,29 +81,6 @@ struct MatchLevel {
   long long pvoff;
 };
 
-// Candidate key: cost, squared offset from the guess, scan index; the
-// lexicographic minimum wins.
-struct Key {
-  unsigned long long ssd;
-  int d2, k;
-};
-
-__device__ __forceinline__ bool key_less(const Key& a, const Key& b) {
-  if (a.ssd != b.ssd) return a.ssd < b.ssd;
-  if (a.d2 != b.d2) return a.d2 < b.d2;
-  return a.k < b.k;
-}
-
-__device__ __forceinline__ Key shfl_key(const Key& a, int off) {
-  Key o;
-  const unsigned lo = __shfl_xor((unsigned)(a.ssd & 0xffffffffull), off, 64);
-  const unsigned hi = __shfl_xor((unsigned)(a.ssd >> 32), off, 64);
-  o.ssd = ((unsigned long long)hi << 32) | lo;
-  o.d2 = __shfl_xor(a.d2, off, 64);
-  o.k = __shfl_xor(a.k, off, 64);
-  return o;
-}
-
 // Persistent launches: kWaves independent waves per workgroup. Wave w of
 // workgroup b (XCD-aware order) takes the contiguous item range
 // [(4b + w) * chunk, (4b + w + 1) * chunk), so neighbouring items share an L2.
@@ -128,90 +105,100 @@ __device__ __forceinline__ int32_t ld_word(__amdgpu_buffer_rsrc_t r, int idx) {
   return __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0);
 }
 
-// A rows x cols window of one h x w level image (top-left (y0, x0), indices
-// clamped to the image) bound for LDS with row stride ld.
-struct Win {
-  __amdgpu_buffer_rsrc_t src;
-  int32_t* dst;
-  int ld, y0, x0, rows, cols;
-};
-
-// Copy two windows into LDS. Per round every lane issues up to U loads of each
-// window (slots past the window's end are skipped by a wave-uniform test; the
-// last slot's tail lanes load a clamped duplicate and do not store), and every
-// load of the round is issued before its stores, so a window of up to 64 U
-// words costs one memory round trip.
-template <int U>
-__device__ __forceinline__ void stage_pair(const Win& A, const Win& B, int h, int w, int lane) {
-  const int ta = A.rows * A.cols, tb = B.rows * B.cols;
-  const float ia = 1.0f / (float)A.cols, ib = 1.0f / (float)B.cols;
-  for (int i0 = 0; i0 < ta || i0 < tb; i0 += 64 * U) {
+// Copy a block's base window (rows x cols from the base frame's buffer
+// resource) and its search region (E x E from the frame, per-lane pointer)
+// into LDS, by the LPG lanes of its group; all loads of a round before its
+// stores.
+template <int LPG, int U>
+__device__ __forceinline__ void stage_block(int32_t* tpl, int ldt, int rows, int cols, __amdgpu_buffer_rsrc_t rs_base,
+                                            int ty0, int tx0, int32_t* reg, int E, const int32_t* img, int ry0,
+                                            int rx0, int h, int w, int l) {
+  const int ta = rows * cols, tb = E * E;
+  const float ia = 1.0f / (float)cols, ib = 1.0f / (float)E;
+  for (int i0 = 0; i0 < ta || i0 < tb; i0 += LPG * U) {
     int va[U], vb[U], aa[U], ab[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * LPG + l;
       aa[u] = -1;
       ab[u] = -1;
       va[u] = 0;
       vb[u] = 0;
-      const int i = i0 + u * 64 + lane;
-      if (i0 + u * 64 < ta) {
-        const int ic = min(i, ta - 1);
-        const int r = split_row(ic, ia), c = ic - r * A.cols;
-        if (i < ta) aa[u] = r * A.ld + c;
-        va[u] = ld_word(A.src, clampi(A.y0 + r, 0, h - 1) * w + clampi(A.x0 + c, 0, w - 1));
+      if (i < ta) {
+        const int r = split_row(i, ia), c = i - r * cols;
+        aa[u] = r * ldt + c;
+        va[u] = ld_word(rs_base, clampi(ty0 + r, 0, h - 1) * w + clampi(tx0 + c, 0, w - 1));
       }
-      if (i0 + u * 64 < tb) {
-        const int ic = min(i, tb - 1);
-        const int r = split_row(ic, ib), c = ic - r * B.cols;
-        if (i < tb) ab[u] = r * B.ld + c;
-        vb[u] = ld_word(B.src, clampi(B.y0 + r, 0, h - 1) * w + clampi(B.x0 + c, 0, w - 1));
+      if (i < tb) {
+        const int r = split_row(i, ib), c = i - r * E;
+        ab[u] = i;
+        vb[u] = img[clampi(ry0 + r, 0, h - 1) * w + clampi(rx0 + c, 0, w - 1)];
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (aa[u] >= 0) A.dst[aa[u]] = va[u];
-      if (ab[u] >= 0) B.dst[ab[u]] = vb[u];
+      if (aa[u] >= 0) tpl[aa[u]] = va[u];
+      if (ab[u] >= 0) reg[ab[u]] = vb[u];
     }
   }
 }
 
-// Block matching of one level: one wave per block of one non-base frame. LDS
-// per wave: the base block (B x B), the frame's search region ((B + 2R)^2,
-// edge-replicated) and the partial costs. Tasks = candidates x G row groups
-// with a fixed lane assignment; the row-group partials of each candidate are
-// then added in a fixed order (groups past the block's last row add 0).
+// Candidate key packed for lane exchanges: cost, then (squared offset from
+// the guess) * 2^16 + scan index; the lexicographic minimum wins.
+struct PKey {
+  unsigned long long ssd;
+  int tie;
+};
+
+template <int CTRL>
+__device__ __forceinline__ PKey dpp_key(const PKey& a) {
+  PKey o;
+  o.ssd = ((unsigned long long)(unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(a.ssd >> 32), CTRL, 0xF, 0xF,
+                                                                      true)
+           << 32) |
+          (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(a.ssd & 0xffffffffull), CTRL, 0xF, 0xF, true);
+  o.tie = __builtin_amdgcn_update_dpp(0, a.tie, CTRL, 0xF, 0xF, true);
+  return o;
+}
+
+__device__ __forceinline__ void key_min(PKey& a, const PKey& b) {
+  if (b.ssd < a.ssd || (b.ssd == a.ssd && b.tie < a.tie)) a = b;
+}
+
+// Block matching of one level, four blocks per wave: the 16 lanes of group g
+// take block q0 + g of the wave's chunk and split its candidates (lane l takes
+// l, l + 16, ...); the group minimum of the keys is then exchanged over DPP
+// (row mirror, half mirror, quad permutations: disjoint orbits, so four steps
+// cover the 16 lanes). LDS per group: the base block (B x B) and the frame's
+// search region ((B + 2R)^2, edge-replicated).
 // EXACT_F64: every level value is below 2^22 (levels 0-2 of 16-bit frames), so
 // squared differences and their sums stay below 2^53 and float64 adds them
 // exactly; coarser levels add in 64-bit integers.
 template <bool EXACT_F64>
-__global__ __launch_bounds__(64 * kWaves) void k_align_match(const int32_t* __restrict__ pyr, int2* __restrict__ vecs,
-                                                             MatchLevel ml, int ref, long long fstride,
-                                                             long long vstride, int items, int chunk) {
+__global__ __launch_bounds__(256) void k_align_match(const int32_t* __restrict__ pyr, int2* __restrict__ vecs,
+                                                     MatchLevel ml, int ref, long long fstride, long long vstride,
+                                                     int items, int chunk) {
+  constexpr int LPG = 16, GPW = 4;
   extern __shared__ int32_t smem[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, l = lane & 15;
   const int B = ml.B, R = ml.R, E = B + 2 * R, D = 2 * R + 1, K = D * D;
-  const int words = (B * B + E * E + 1) & ~1;
-  const int tasks_max = K >= 64 ? K : 64;
-  int32_t* tpl = smem + wave * (words + 2 * tasks_max);
+  int32_t* tpl = smem + (wave * GPW + g) * (B * B + E * E);
   int32_t* reg = tpl + B * B;
-  unsigned long long* part = (unsigned long long*)(tpl + words);
-  const int G = K >= 64 ? 1 : min(64 / K, B);
-  const int n_tasks = K * G;
-  // the lane's first task, fixed for every block
-  const int g0 = lane / K, k0 = lane - g0 * K;
-  const int dyi0 = k0 / D, dxi0 = k0 - dyi0 * D;
   const int per = ml.gby * ml.gbx;
-  const int gw = xcd_tile(blockIdx.x, gridDim.x) * kWaves + wave;
+  const int gw = xcd_tile(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
   const int c0 = gw * chunk, c1 = min(items, c0 + chunk);
   const long long lvl_words = (long long)ml.h * ml.w;
   const __amdgpu_buffer_rsrc_t rs_base = words_rsrc(pyr + (long long)ref * fstride + ml.loff, lvl_words);
-  for (int item = c0; item < c1; ++item) {
-    const int fi = item / per;
-    const int t = item - fi * per;
+  for (int q0 = c0; q0 < c1; q0 += GPW) {
+    const int item = q0 + g;
+    const bool valid = item < c1;
+    const int fi = valid ? item / per : 0;
+    const int t = valid ? item - fi * per : 0;
     const int by = t / ml.gbx, bx = t - (t / ml.gbx) * ml.gbx;
     const int f = fi < ref ? fi : fi + 1;
     int gx = 0, gy = 0;
-    if (ml.parent) {
+    if (valid && ml.parent) {
       const int cy = min(((2 * by + 1) * B) / (4 * ml.pB), ml.pgby - 1);
       const int cx = min(((2 * bx + 1) * B) / (4 * ml.pB), ml.pgbx - 1);
       const int2 pv = vecs[(long long)f * vstride + ml.pvoff + cy * ml.pgbx + cx];
@@ -219,64 +206,50 @@ __global__ __launch_bounds__(64 * kWaves) void k_align_match(const int32_t* __re
       gy = 2 * pv.y;
     }
     const int nby = min(B, ml.h - by * B), nbx = min(B, ml.w - bx * B);
-    {
-      const Win A{rs_base, tpl, B, by * B, bx * B, nby, nbx};
-      const Win Bw{words_rsrc(pyr + (long long)f * fstride + ml.loff, lvl_words), reg, E, by * B + gy - R,
-                   bx * B + gx - R, E, E};
-      stage_pair<4>(A, Bw, ml.h, ml.w, lane);
-    }
+    if (valid)
+      stage_block<LPG, 9>(tpl, B, nby, nbx, rs_base, by * B, bx * B, reg, E, pyr + (long long)f * fstride + ml.loff,
+                          by * B + gy - R, bx * B + gx - R, ml.h, ml.w, l);
     wave_sync();
-    for (int task = lane; task < n_tasks; task += 64) {
-      int g = g0, dyi = dyi0, dxi = dxi0;
-      if (task != lane) {
-        g = task / K;
-        const int k = task - g * K;
-        dyi = k / D;
-        dxi = k - dyi * D;
-      }
-      unsigned long long ssd = 0;
-      if (EXACT_F64) {
-        double acc = 0.0;
-        for (int r = g; r < nby; r += G) {
-          const int32_t* tr = tpl + r * B;
-          const int32_t* rr = reg + (r + dyi) * E + dxi;
-          for (int c = 0; c < nbx; ++c) {
-            const double d = (double)(rr[c] - tr[c]);
-            acc = fma(d, d, acc);
+    PKey best{~0ull, 0x7fffffff};
+    if (valid) {
+      for (int k = l; k < K; k += LPG) {
+        const int dyi = k / D, dxi = k - (k / D) * D;
+        unsigned long long ssd = 0;
+        if (EXACT_F64) {
+          double acc = 0.0;
+          for (int r = 0; r < nby; ++r) {
+            const int32_t* tr = tpl + r * B;
+            const int32_t* rr = reg + (r + dyi) * E + dxi;
+            for (int c = 0; c < nbx; ++c) {
+              const double d = (double)(rr[c] - tr[c]);
+              acc = fma(d, d, acc);
+            }
+          }
+          ssd = (unsigned long long)acc;
+        } else {
+          for (int r = 0; r < nby; ++r) {
+            const int32_t* tr = tpl + r * B;
+            const int32_t* rr = reg + (r + dyi) * E + dxi;
+            for (int c = 0; c < nbx; ++c) {
+              const long long d = (long long)(rr[c] - tr[c]);
+              ssd += (unsigned long long)(d * d);
+            }
           }
         }
-        ssd = (unsigned long long)acc;
-      } else {
-        for (int r = g; r < nby; r += G) {
-          const int32_t* tr = tpl + r * B;
-          const int32_t* rr = reg + (r + dyi) * E + dxi;
-          for (int c = 0; c < nbx; ++c) {
-            const long long d = (long long)(rr[c] - tr[c]);
-            ssd += (unsigned long long)(d * d);
-          }
-        }
+        const int dx = dxi - R, dy = dyi - R;
+        key_min(best, PKey{ssd, ((dx * dx + dy * dy) << 16) | k});
       }
-      part[task] = ssd;
     }
-    wave_sync();
-    Key best{~0ull, 0x7fffffff, 0x7fffffff};
-    for (int k = lane; k < K; k += 64) {
-      unsigned long long ssd = 0;
-      for (int g = 0; g < G; ++g) ssd += part[g * K + k];
-      const int dy = k / D, dx = k - dy * D;
-      const Key cand{ssd, (dx - R) * (dx - R) + (dy - R) * (dy - R), k};
-      if (key_less(cand, best)) best = cand;
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const Key o = shfl_key(best, off);
-      if (key_less(o, best)) best = o;
-    }
-    if (lane == 0) {
-      const int dyi = best.k / D, dxi = best.k - (best.k / D) * D;
+    key_min(best, dpp_key<0x140>(best));
+    key_min(best, dpp_key<0x141>(best));
+    key_min(best, dpp_key<0x4E>(best));
+    key_min(best, dpp_key<0xB1>(best));
+    if (valid && l == 0) {
+      const int k = best.tie & 0xffff;
+      const int dyi = k / D, dxi = k - (k / D) * D;
       vecs[(long long)f * vstride + ml.voff + t] = make_int2(gx + dxi - R, gy + dyi - R);
     }
-    wave_sync();  // the next block restages this wave's LDS
+    wave_sync();  // the next blocks restage this wave's LDS
   }
 }
 
@@ -289,14 +262,6 @@ struct LkArgs {
   int ref;
   long long fstride, vstride, voff0;
 };
-
-// Same value in every lane: make it a scalar.
-__device__ __forceinline__ double uniform(double v) {
-  const unsigned long long u = __double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(u & 0xffffffffull));
-  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
 
 // Lane exchanges with the partner whose lane index differs in bit BIT (and,
 // for BIT <= 3, possibly in lower bits too): bits 5 and 4 through the LDS
@@ -572,14 +537,6 @@ hipError_t launch_align(const AlignGeom& ag, const uint16_t* frames, int H, int 
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
     cus = 256;
-  // persistent grid: at most kGroupsPerCU workgroups of kWaves waves per CU,
-  // each wave a contiguous chunk of items
-  auto plan = [&](long long items, unsigned* groups, int* chunk) {
-    const long long waves = std::min<long long>(items, (long long)cus * kGroupsPerCU * kWaves);
-    const long long c = (items + waves - 1) / waves;
-    *chunk = (int)c;
-    *groups = (unsigned)(((items + c - 1) / c + kWaves - 1) / kWaves);
-  };
   if (ag.n > 1) {
     for (int l = ag.L - 1; l >= 0; --l) {
       MatchLevel ml;
@@ -596,20 +553,21 @@ hipError_t launch_align(const AlignGeom& ag, const uint16_t* frames, int H, int 
       ml.pgby = ml.parent ? ag.gby[l + 1] : 1;
       ml.pgbx = ml.parent ? ag.gbx[l + 1] : 1;
       ml.pvoff = ml.parent ? ag.voff[l + 1] : 0;
-      const int E = ml.B + 2 * ml.R, K = (2 * ml.R + 1) * (2 * ml.R + 1);
-      const int tasks = K >= 64 ? K : 64;
-      const size_t lds = (size_t)kWaves * (((ml.B * ml.B + E * E + 1) & ~1) + 2 * tasks) * 4;
+      const int E = ml.B + 2 * ml.R;
+      const int waves = ml.B <= 8 ? kWaves : 1;  // keeps LDS within 64 KiB per workgroup
+      const size_t lds = (size_t)waves * 4 * (ml.B * ml.B + E * E) * 4;
       const long long items = (long long)(ag.n - 1) * ml.gby * ml.gbx;
-      unsigned groups;
-      int chunk;
-      plan(items, &groups, &chunk);
+      const long long total_waves = std::min<long long>((items + 3) / 4, (long long)cus * kGroupsPerCU * kWaves);
+      long long chunk = (items + total_waves - 1) / total_waves;
+      chunk = (chunk + 3) / 4 * 4;
+      const unsigned groups = (unsigned)(((items + chunk - 1) / chunk + waves - 1) / waves);
       // levels 0-2 of 16-bit frames stay below 2^22 (sums of 4^(l+1) values)
       if (l <= 2)
-        hipLaunchKernelGGL(k_align_match<true>, dim3(groups), dim3(64 * kWaves), lds, stream, pyr, vecs, ml,
-                           ag.ref, ag.fstride, ag.vstride, (int)items, chunk);
+        hipLaunchKernelGGL(k_align_match<true>, dim3(groups), dim3(64 * waves), lds, stream, pyr, vecs, ml, ag.ref,
+                           ag.fstride, ag.vstride, (int)items, (int)chunk);
       else
-        hipLaunchKernelGGL(k_align_match<false>, dim3(groups), dim3(64 * kWaves), lds, stream, pyr, vecs, ml,
-                           ag.ref, ag.fstride, ag.vstride, (int)items, chunk);
+        hipLaunchKernelGGL(k_align_match<false>, dim3(groups), dim3(64 * waves), lds, stream, pyr, vecs, ml, ag.ref,
+                           ag.fstride, ag.vstride, (int)items, (int)chunk);
       if ((err = hipGetLastError()) != hipSuccess) return err;
     }
   }
