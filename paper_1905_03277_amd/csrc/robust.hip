@@ -62,7 +62,7 @@ struct RobustSmem {
   float2 sF[TT_X * TT_Y];   // v / 2 - floor(v / 2): the bilinear fractions, exact
   float sS[TT_X * TT_Y];
   Bounds4 sTB[TT_X * TT_Y];
-  int sRed[4];
+  int sRed[5];
   int sItem;
 };
 
@@ -177,6 +177,7 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
     // footprints without atomics.
     if (tid < 64) {
       Bounds4 acc = {0x7fffffff, -0x7fffffff, 0x7fffffff, -0x7fffffff};
+      int need = 0;  // largest guide window of one tile, (mw + 2) (mh + 2)
       for (int k = tid; k < ntiles; k += 64) {
         const int ky = k / ntx, kx = k - ky * ntx;
         const size_t t = ((size_t)n * g.TY + tyA + ky) * g.TX + txA + kx;
@@ -194,6 +195,7 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
         b.y0 = clampi(ra0 + sRlo[ky], 0, g.h - 1) + o.y;
         b.y1 = clampi(ra0 + sRhi[ky], 0, g.h - 1) + o.y;
         sTB[k] = b;
+        need = max(need, (b.x1 - b.x0 + 4) * (b.y1 - b.y0 + 4));
         acc.x0 = min(acc.x0, b.x0);
         acc.x1 = max(acc.x1, b.x1);
         acc.y0 = min(acc.y0, b.y0);
@@ -203,7 +205,9 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
       acc.x1 = -wave_min(-acc.x1);
       acc.y0 = wave_min(acc.y0);
       acc.y1 = -wave_min(-acc.y1);
+      need = -wave_min(-need);
       if (tid == 0) {
+        sRed[4] = need;
         sRed[0] = acc.x0;
         sRed[1] = -acc.x1;
         sRed[2] = acc.y0;
@@ -211,15 +215,28 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
       }
     }
     __syncthreads();
-    bool whole = true;
-    int seg = 0;
-    while (true) {
-      Bounds4 bd;
+    // Either one window covers every tile's footprint, or the tiles are
+    // processed P at a time (one group of THREADS / P threads each, its own
+    // 1 / P of the window buffers; P as large as the largest tile window
+    // allows). The arithmetic per pixel is the same either way.
+    const bool whole = [&] {
+      const int mw = -sRed[1] - sRed[0] + 2, mh = -sRed[3] - sRed[2] + 2;
+      return mw * mh <= MU_CAP && (mw + 2) * (mh + 2) <= GU_CAP && (mh + 2) * mw <= GU_CAP;
+    }();
+    const int need = sRed[4];
+    const int P = whole ? 1 : need <= GU_CAP / 4 ? 4 : need <= GU_CAP / 2 ? 2 : 1;
+    const int gsz = THREADS / P, gi = tid / gsz, lt = tid - gi * gsz, cap = GU_CAP / P;
+    for (int s0 = 0; s0 < (whole ? 1 : ntiles); s0 += P) {
+      const int seg = s0 + gi;
+      const bool act = whole || seg < ntiles;
+      Bounds4 bd = {0, 0, 0, 0};
       if (whole) {
         bd.x0 = sRed[0]; bd.x1 = -sRed[1]; bd.y0 = sRed[2]; bd.y1 = -sRed[3];
-      } else {
+      } else if (act) {
         bd = sTB[seg];
       }
+      float* G[3] = {sGuide[0] + gi * cap, sGuide[1] + gi * cap, sGuide[2] + gi * cap};
+      float* Hs[3] = {sHs[0] + gi * cap, sHs[1] + gi * cap, sHs[2] + gi * cap};
       // box-mean window: every bilinear corner (unclamped; entries outside the
       // grid repeat the edge); guide window: their clamped 3x3 neighbourhoods.
       const int mc0 = bd.x0, mw = bd.x1 - bd.x0 + 2;
@@ -228,51 +245,55 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
       const int gr0 = clampi(mr0, 0, g.h - 1) - 1, gr1 = clampi(mr0 + mh - 1, 0, g.h - 1) + 1;
       const int gw = gc1 - gc0 + 1, gn = gw * (gr1 - gr0 + 1);
       const int gh = gr1 - gr0 + 1;
-      if (whole && (mw * mh > MU_CAP || gn > GU_CAP || gh * mw > GU_CAP)) {
-        whole = false;  // uniform decision: one alignment tile per pass
-        seg = 0;
-        continue;
-      }
-      {
+      if (act) {
         const float ginv = 1.f / (float)gw;
-        for (int k = tid; k < gn; k += THREADS) {
+        for (int k = lt; k < gn; k += gsz) {
           const int rr = split_row(k, ginv);
           float r, gg, b;
           load_guide(f, g, clampi(gr0 + rr, 0, g.h - 1), clampi(gc0 + k - rr * gw, 0, g.w - 1), r, gg, b);
-          sGuide[0][k] = r;
-          sGuide[1][k] = gg;
-          sGuide[2][k] = b;
+          G[0][k] = r;
+          G[1][k] = gg;
+          G[2][k] = b;
         }
       }
       __syncthreads();
       // 3x3 box mean, separable: row sums over the guide rows, then column sums
-      {
+      if (act) {
         const float minv = 1.f / (float)mw;
-        for (int k = tid; k < gh * mw; k += THREADS) {
+        for (int k = lt; k < gh * mw; k += gsz) {
           const int rr = split_row(k, minv), cc = k - rr * mw;
           const int q = rr * gw + clampi(mc0 + cc, 0, g.w - 1) - 1 - gc0;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) sHs[c][k] = (sGuide[c][q] + sGuide[c][q + 1]) + sGuide[c][q + 2];
+          for (int c = 0; c < 3; ++c) Hs[c][k] = (G[c][q] + G[c][q + 1]) + G[c][q + 2];
         }
       }
       __syncthreads();
-      {
+      if (act) {
         const float minv = 1.f / (float)mw;
-        for (int k = tid; k < mw * mh; k += THREADS) {
+        for (int k = lt; k < mw * mh; k += gsz) {
           const int rr = split_row(k, minv), cc = k - rr * mw;
           const int q = (clampi(mr0 + rr, 0, g.h - 1) - 1 - gr0) * mw + cc;
 #pragma unroll
-          for (int c = 0; c < 3; ++c)
-            sGuide[c][k] = ((sHs[c][q] + sHs[c][q + mw]) + sHs[c][q + 2 * mw]) * (1.f / 9.f);
+          for (int c = 0; c < 3; ++c) G[c][k] = ((Hs[c][q] + Hs[c][q + mw]) + Hs[c][q + 2 * mw]) * (1.f / 9.f);
         }
       }
       __syncthreads();
-      {
-        const float rinv = 1.f / (float)RR_W;
-        for (int k = tid; k < RR_N; k += THREADS) {
-          const int rr = split_row(k, rinv), cc = k - rr * RR_W;
+      if (act) {
+        // region pixels: all of them, or the tile's own rectangle
+        int rlo = 0, clo = 0, nr = RR_H, nc = RR_W;
+        if (!whole) {
+          const int ky = seg / ntx, kx = seg - (seg / ntx) * ntx;
+          rlo = sRlo[ky];
+          nr = sRhi[ky] - rlo + 1;
+          clo = sClo[kx];
+          nc = sChi[kx] - clo + 1;
+        }
+        const float cinv = 1.f / (float)nc;
+        for (int q = lt; q < nr * nc; q += gsz) {
+          const int qr = split_row(q, cinv);
+          const int rr = rlo + qr, cc = clo + q - qr * nc;
+          const int k = rr * RR_W + cc;
           const int kt = (sTyR[rr] - tyA) * ntx + (sTxR[cc] - txA);
-          if (!whole && kt != seg) continue;
           const int I = clampi(ra0 + rr, 0, g.h - 1), J = clampi(ca0 + cc, 0, g.w - 1);
           const int2 o = sO[kt];
           const float2 fr = sF[kt];
@@ -281,8 +302,8 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
           float num = 0.f;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const float m00 = sGuide[c][ya], m01 = sGuide[c][ya + 1];
-            const float m10 = sGuide[c][ya + mw], m11 = sGuide[c][ya + mw + 1];
+            const float m00 = G[c][ya], m01 = G[c][ya + 1];
+            const float m10 = G[c][ya + mw], m11 = G[c][ya + mw + 1];
             const float top = fmaf(fx, m01 - m00, m00), bot = fmaf(fx, m11 - m10, m10);
             const float mu_al = fmaf(fy, bot - top, top);
             const float mu_ref = sMuRef[c][k];
@@ -298,10 +319,8 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
           sR[k] = fminf(fmaxf(R, 0.f), 1.f);
         }
       }
-      if (whole || ++seg >= ntiles) break;
       __syncthreads();
     }
-    __syncthreads();
     // eq. (9): 5x5 minimum, separable (the region repeats edge pixels)
     const int ow = min(RB_W, g.w - J0), oh = min(RB_H, g.h - I0);
     for (int k = tid; k < RR_H * RB_W; k += THREADS) {
