@@ -6,7 +6,7 @@ resident in HBM. Prints one JSON line with input-Bayer MP/s, the dominant
 kernel's roofline position and the FP64 oracle's CPU rate on a bounded sample.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
-                    [--no-batch] [--no-grad]
+                    [--no-batch] [--no-grad] [--no-stream] [--no-align]
 
 More legs follow the headline measurement and are reported inside its line:
 the same burst merged frame by frame through the streaming calls, its tile
@@ -354,6 +354,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-burst batched leg")
     ap.add_argument("--no-grad", action="store_true", help="skip the forward + adjoint leg")
+    ap.add_argument("--no-stream", action="store_true", help="skip the frame-by-frame streaming leg")
+    ap.add_argument("--no-align", action="store_true", help="skip the alignment / raw-to-RGB leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus 1); the merge shards by "
@@ -431,8 +433,10 @@ def main():
                 "frac": round(byts["total"] / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "wall_s_timed": round(wall, 3),
     }
-    line["streaming"] = bench_stream(burst, out)
-    line["alignment"] = bench_align(burst, out)
+    if not args.no_stream:
+        line["streaming"] = bench_stream(burst, out)
+    if not args.no_align:
+        line["alignment"] = bench_align(burst, out)
     if not args.no_batch:
         line["batched"] = bench_batch(dev)
     if not args.no_grad:
