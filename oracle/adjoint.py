@@ -43,7 +43,9 @@ TUNING_FIELDS = GRAD_NAMES + ("m_th",)
 def tuning_dict(tuning) -> dict:
     """The tuning as a dict of float64 values (finite differences perturb it
     without the float32 rounding of the ABI structs)."""
-    return {f: float(om._get(tuning, f)) for f in TUNING_FIELDS}
+    d = {f: float(om._get(tuning, f)) for f in TUNING_FIELDS}
+    d["hf_ratio"] = float(om._opt(tuning, "hf_ratio", 0.0))
+    return d
 
 
 # --------------------------------------------------------------------------- #
@@ -156,6 +158,8 @@ def _robust_parts(maps, k, desc, tuning):
     moving = moving[ty, tx] > 0.5
     s = np.where(moving, float(om._get(tuning, "s_motion")), float(om._get(tuning, "s")))
     r_raw = s * np.exp(-r) - float(om._get(tuning, "t"))
+    # S.3 full rejection: R held at 0 there, like a clamp
+    r_raw = np.where(maps["hf_reject"][k], -1.0, r_raw)
     return dict(ty=ty, tx=tx, dmu_x=dmu_x, dmu_y=dmu_y, cells=cells, d_ms=d_ms, d_md_sq=d_md_sq,
                 d=d, sig2=sig2, r=r, s=s, moving=moving, r_raw=r_raw)
 

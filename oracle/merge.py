@@ -50,6 +50,13 @@ def _get(obj, name):
     return obj[name] if isinstance(obj, dict) else getattr(obj, name)
 
 
+def _opt(obj, name, default):
+    """Optional tuning value (absent in older tuning sets)."""
+    if isinstance(obj, dict):
+        return obj.get(name, default)
+    return getattr(obj, name, default)
+
+
 # --------------------------------------------------------------------------- #
 # step 1: normalisation                                                       #
 # --------------------------------------------------------------------------- #
@@ -176,6 +183,40 @@ def box3_mean_std(g):
 
 
 # --------------------------------------------------------------------------- #
+# supplement S.3: high-frequency variance loss                                #
+# --------------------------------------------------------------------------- #
+def variance_loss(frame_ref, cfa, hf_ratio):
+    """S.3: where the base frame's guide loses most of its local variance to
+    the local low-pass, True. With x the guide doubled to integers (2R, G1+G2,
+    2B per 2x2 quad) and S its 3x3 box sums (the low-pass, times 9), per
+    channel B = 9 sum x^2 - (sum x)^2 over the 3x3 window (81 x the variance
+    before) and A = 9 sum S^2 - (sum S)^2 over the 3x3 window of box sums
+    (81^2 x the variance after); windows edge-replicated on the half-res grid.
+    Loss where sum_c A < hf_ratio * (81 * sum_c B), exact integers compared in
+    float64. hf_ratio = 0 disables the test."""
+    f = np.asarray(frame_ref, dtype=np.int64)
+    h, w = f.shape[0] // 2, f.shape[1] // 2
+    if not hf_ratio > 0.0:
+        return np.zeros((h, w), dtype=bool)
+    cols = {0: (0, 1, 1, 2), 1: (1, 0, 2, 1), 2: (1, 2, 0, 1), 3: (2, 1, 1, 0)}[int(cfa)]
+    quads = [f[0::2, 0::2], f[0::2, 1::2], f[1::2, 0::2], f[1::2, 1::2]]
+    x = np.zeros((3, h, w), dtype=np.int64)
+    for pos, c in enumerate(cols):
+        x[c] += quads[pos] * (2 if c != 1 else 1)
+
+    def win3(m):
+        mp = np.pad(m, ((0, 0), (1, 1), (1, 1)), mode="edge")
+        return [mp[:, i:i + h, j:j + w] for i in range(3) for j in range(3)]
+
+    wx = win3(x)
+    s_box = sum(wx)                                           # [3][h][w] 3x3 sums
+    b_var = (9 * sum(v * v for v in wx) - s_box * s_box).sum(0)
+    ws = win3(s_box)
+    a_var = (9 * sum(v * v for v in ws) - sum(ws) ** 2).sum(0)
+    return a_var.astype(np.float64) < float(hf_ratio) * (81 * b_var).astype(np.float64)
+
+
+# --------------------------------------------------------------------------- #
 # helpers                                                                     #
 # --------------------------------------------------------------------------- #
 def bilinear(m, hx, hy):
@@ -231,7 +272,7 @@ def motion_prior(motion_n, s1, s2, m_th):
 # --------------------------------------------------------------------------- #
 # step 7: robustness                                                          #
 # --------------------------------------------------------------------------- #
-def robustness(mu_ref, sd_ref, mu_n, motion_n, s_tile, t, noise_a, noise_b, tile):
+def robustness(mu_ref, sd_ref, mu_n, motion_n, s_tile, t, noise_a, noise_b, tile, reject=None):
     """Robustness R on the base frame's half-resolution grid for one aligned
     frame, eqs. (5)-(6). Returns (R, R_hat) with R_hat the 5x5 minimum, eq. (9).
 
@@ -242,7 +283,8 @@ def robustness(mu_ref, sd_ref, mu_n, motion_n, s_tile, t, noise_a, noise_b, tile
     per-pixel guide sigma sigma_md = sqrt(var) and the expected difference of
     two 3x3 means d_md = sqrt(2 var / 9), evaluated at the base mean; the three
     colour channels combine as r = sum_c d_c^2 / sum_c sigma_c^2; R is clamped
-    to [0, 1]; the 5x5 minimum uses existing pixels only."""
+    to [0, 1]; the 5x5 minimum uses existing pixels only. ``reject`` (bool
+    [h][w], optional) forces R to 0 (the full rejection of S.3)."""
     h, w = mu_ref.shape[-2:]
     ii, jj = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
     ty = np.minimum((2 * ii) // tile, s_tile.shape[0] - 1)
@@ -261,6 +303,8 @@ def robustness(mu_ref, sd_ref, mu_n, motion_n, s_tile, t, noise_a, noise_b, tile
     r = (d * d).sum(0) / (sigma * sigma).sum(0)
     s = s_tile[ty, tx]
     R = np.clip(s * np.exp(-r) - float(t), 0.0, 1.0)              # eq. (5)
+    if reject is not None:
+        R = np.where(reject, 0.0, R)
     Rp = np.pad(R, 2, mode="edge")
     R_hat = np.min(np.stack([Rp[i:i + h, j:j + w] for i in range(5) for j in range(5)]), axis=0)
     return R, R_hat
@@ -290,16 +334,26 @@ def prepare(frames, motion, desc, tuning):
     r_raw = np.ones((n, h // 2, w // 2))
     s_tiles = np.zeros((n, ty_n, tx_n))
     m_tiles = np.zeros((n, ty_n, tx_n))
+    hf_loss = variance_loss(frames[ref], cfa, float(_opt(tuning, "hf_ratio", 0.0)))
+    hf_reject = np.zeros((n, h // 2, w // 2), dtype=bool)
     for k in range(n):
         if k == ref:
             continue
         s_tiles[k], m_tiles[k] = motion_prior(motion[k], _get(tuning, "s_motion"),
                                               _get(tuning, "s"), _get(tuning, "m_th"))
+        if hf_loss.any():
+            # S.3: variance loss where the vector field varies strongly (the
+            # motion prior's own decision, eq. 8) is fully rejected
+            moving, _ = motion_prior(motion[k], 1.0, 0.0, _get(tuning, "m_th"))
+            ii, jj = np.meshgrid(np.arange(h // 2), np.arange(w // 2), indexing="ij")
+            ty = np.minimum((2 * ii) // tile, ty_n - 1)
+            tx = np.minimum((2 * jj) // tile, tx_n - 1)
+            hf_reject[k] = hf_loss & (moving[ty, tx] > 0.5)
         r_raw[k], r_hat[k] = robustness(mu[ref], sd[ref], mu[k], motion[k], s_tiles[k],
                                         _get(tuning, "t"), _get(desc, "noise_a"),
-                                        _get(desc, "noise_b"), tile)
+                                        _get(desc, "noise_b"), tile, hf_reject[k])
     return dict(x=x, lum=lum, guide=guide, omega=omega, mu=mu, sd=sd, motion=motion,
-                r=r_raw, r_hat=r_hat, s_tiles=s_tiles, m_tiles=m_tiles,
+                r=r_raw, r_hat=r_hat, s_tiles=s_tiles, m_tiles=m_tiles, hf_reject=hf_reject,
                 colours=colour_map(h, w, cfa), ref=ref, tile=tile)
 
 

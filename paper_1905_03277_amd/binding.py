@@ -47,7 +47,7 @@ class hmfsr_desc(ctypes.Structure):
 class hmfsr_tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_float) for n in
                 ("k_detail", "k_denoise", "d_th", "d_tr", "k_stretch", "k_shrink", "s", "t",
-                 "s_motion", "m_th")]
+                 "s_motion", "m_th", "hf_ratio")]
 
 
 class hmfsr_align_params(ctypes.Structure):
@@ -129,7 +129,10 @@ def make_desc(d) -> hmfsr_desc:
 
 
 def make_tuning(t) -> hmfsr_tuning:
-    return hmfsr_tuning(*(getattr(t, f) for f, _ in hmfsr_tuning._fields_))
+    """hmfsr_tuning from any object with the same field names (hf_ratio may be
+    absent: 0, the high-frequency rejection off)."""
+    return hmfsr_tuning(*(getattr(t, f, 0.0) if f == "hf_ratio" else getattr(t, f)
+                          for f, _ in hmfsr_tuning._fields_))
 
 
 def hmfsr_merge(desc: hmfsr_desc, tuning: hmfsr_tuning, frames: int, motion: int, out: int,

@@ -67,6 +67,7 @@ class Tuning:
     t: float
     s_motion: float   # paper s_1 (local motion above the threshold)
     m_th: float       # paper M_th, in pixels
+    hf_ratio: float = 0.0   # S.3 variance-loss threshold (0: high-frequency rejection off)
 
     def __post_init__(self):
         # The C ABI carries these as float32: keep the canonical values rounded.

@@ -164,17 +164,20 @@ TUNING_FIELDS = binding.GRAD_NAMES + ("m_th",)
 
 
 class _TuningView:
-    """Attribute view of a 10-vector of tuning values (hmfsr_tuning order)."""
+    """Attribute view of a 10- or 11-vector of tuning values (hmfsr_tuning
+    order; the 11th, hf_ratio, defaults to 0)."""
 
     def __init__(self, values):
-        for name, v in zip(TUNING_FIELDS, values):
+        self.hf_ratio = 0.0
+        for name, v in zip(TUNING_FIELDS + ("hf_ratio",), values):
             setattr(self, name, float(v))
 
 
 class HmfsrMerge(torch.autograd.Function):
     """C = merge(frames, motion, tuning) with gradients for motion and the
     tuning vector [k_detail, k_denoise, d_th, d_tr, k_stretch, k_shrink, s, t,
-    s_motion, m_th] (m_th gets zero). The forward keeps the normaliser of
+    s_motion, m_th(, hf_ratio)] (the thresholds m_th and hf_ratio get zero).
+    The forward keeps the normaliser of
     eq. (1) so that the backward needs no second forward."""
 
     @staticmethod
@@ -186,6 +189,7 @@ class HmfsrMerge(torch.autograd.Function):
         ctx.save_for_backward(frames, motion_c, saved)
         ctx.desc, ctx.tun = desc, tun
         ctx.tuning_meta = (tuning_vec.device, tuning_vec.dtype)
+        ctx.n_tuning = tuning_vec.numel()
         return out
 
     @staticmethod
@@ -193,7 +197,8 @@ class HmfsrMerge(torch.autograd.Function):
         frames, motion, saved = ctx.saved_tensors
         g_tun, g_mot = merge_backward(frames, motion, ctx.desc, ctx.tun, grad_out, saved=saved)
         dev, dt = ctx.tuning_meta
-        g_vec = torch.cat([g_tun, g_tun.new_zeros(1)]).to(device=dev, dtype=dt)
+        extra = ctx.n_tuning - g_tun.numel()     # m_th (and hf_ratio): thresholds, no gradient
+        g_vec = torch.cat([g_tun, g_tun.new_zeros(extra)]).to(device=dev, dtype=dt)
         return None, g_mot, g_vec, None
 
 

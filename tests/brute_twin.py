@@ -121,8 +121,37 @@ def brute_merge(frames, motion, desc, tuning):
     mu = [[[[box_stats(n, ch, I, J)[0] for J in range(w)] for I in range(h)] for ch in range(3)]
           for n in range(n_fr)]
 
+    # -- supplement S.3: variance loss of the base frame's guide, doubled to
+    # integers (Python ints: exact), 3x3 windows edge-clamped
+    hf = float(getattr(tuning, "hf_ratio", 0.0))
+    loss = [[False] * w for _ in range(h)]
+    if hf > 0.0:
+        def g2(ch, I, J):
+            v = 0
+            for dr in (0, 1):
+                for dc in (0, 1):
+                    if colour(2 * I + dr, 2 * J + dc) == ch:
+                        v += int(frames[ref][2 * I + dr][2 * J + dc]) * (1 if ch == 1 else 2)
+            return v
+
+        def win(get, I, J):
+            return [get(_clamp(I + a, h), _clamp(J + b, w)) for a in (-1, 0, 1) for b in (-1, 0, 1)]
+
+        box = [[[sum(win(lambda i, j: g2(ch, i, j), I, J)) for J in range(w)] for I in range(h)]
+               for ch in range(3)]
+        for I in range(h):
+            for J in range(w):
+                A = B = 0
+                for ch in range(3):
+                    xs = win(lambda i, j: g2(ch, i, j), I, J)
+                    ss = win(lambda i, j: box[ch][i][j], I, J)
+                    B += 9 * sum(x * x for x in xs) - sum(xs) ** 2
+                    A += 9 * sum(x * x for x in ss) - sum(ss) ** 2
+                loss[I][J] = float(A) < hf * float(81 * B)
+
     # -- motion prior per (frame, tile)
     s_tile = [[[0.0] * TX for _ in range(TY)] for _ in range(n_fr)]
+    moving = [[[False] * TX for _ in range(TY)] for _ in range(n_fr)]
     for n in range(n_fr):
         for ty in range(TY):
             for tx in range(TX):
@@ -134,7 +163,8 @@ def brute_merge(frames, motion, desc, tuning):
                             xs.append(vx)
                             ys.append(vy)
                 mx, my = max(xs) - min(xs), max(ys) - min(ys)
-                s_tile[n][ty][tx] = tuning.s_motion if mx * mx + my * my > tuning.m_th ** 2 else tuning.s
+                moving[n][ty][tx] = mx * mx + my * my > tuning.m_th ** 2
+                s_tile[n][ty][tx] = tuning.s_motion if moving[n][ty][tx] else tuning.s
 
     # -- robustness and its 5x5 minimum on the base grid
     R = [[[1.0] * w for _ in range(h)] for _ in range(n_fr)]
@@ -158,6 +188,8 @@ def brute_merge(frames, motion, desc, tuning):
                     num += d * d
                     den += sig * sig
                 R[n][I][J] = min(1.0, max(0.0, s_tile[n][ty][tx] * math.exp(-num / den) - tuning.t))
+                if loss[I][J] and moving[n][ty][tx]:
+                    R[n][I][J] = 0.0
     Rh = [[[min(R[n][_clamp(I + a, h)][_clamp(J + b, w)] for a in range(-2, 3) for b in range(-2, 3))
             for J in range(w)] for I in range(h)] for n in range(n_fr)]
 
