@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define HMFSR_VERSION 120 /* 1.2.0 */
+#define HMFSR_VERSION 130 /* 1.3.0 */
 
 /* Colour filter array layout: colours of the 2x2 Bayer cell read row by row. */
 typedef enum {
@@ -98,12 +98,24 @@ typedef struct {
  *  t           robustness threshold of eq. (5)
  *  s_motion    robustness scale s_1 where the motion spread M exceeds m_th, >= 0
  *  m_th        motion-spread threshold M_th (px), >= 0
+ *  hf_ratio    high-frequency artefact rejection (supplement S.3), >= 0; 0
+ *              turns it off. A pixel of an aligned frame is fully rejected
+ *              (R = 0 before the 5x5 minimum of eq. 9) where its tile's motion
+ *              prior chose s_motion (M > M_th, eq. 8) and the base frame's guide
+ *              loses variance to the 3x3 low-pass: with x the guide doubled to
+ *              integers and S its 3x3 box sums, summed over the channels,
+ *              9 sum S^2 - (sum S)^2 < hf_ratio * 81 * (9 sum x^2 - (sum x)^2)
+ *              over the 3x3 windows (edge-replicated), in exact arithmetic.
+ *              The ratio of the two variances is 1/81 on a pixel checkerboard,
+ *              1 on a ramp and has a median near 0.06 on white noise; 0.02 is
+ *              a reasonable setting.
  * All finite.
  */
 typedef struct {
   float k_detail, k_denoise, d_th, d_tr, k_stretch, k_shrink, s, t;
   float s_motion;
   float m_th;
+  float hf_ratio;
 } hmfsr_tuning;
 
 /*
@@ -145,8 +157,9 @@ hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
  *            buffer a hmfsr_merge call on the same inputs filled.
  *  grad_out  DEVICE float32 [3][out_height][out_width]: dL/dC.
  *  grad_tuning  DEVICE float32 [9]: dL/d(k_detail, k_denoise, d_th, d_tr,
- *            k_stretch, k_shrink, s, t, s_motion). m_th is a threshold with
- *            zero derivative almost everywhere and gets none.
+ *            k_stretch, k_shrink, s, t, s_motion). m_th and hf_ratio are
+ *            thresholds with zero derivative almost everywhere and get none;
+ *            pixels the S.3 test rejects have R = 0 and pass no gradient.
  *  grad_motion  DEVICE float32 [n_frames][TY][TX][2]: dL/d(vx, vy); the
  *            base frame's vectors are ignored by the merge and get 0.
  * Kernel weights are recomputed, not stored. Sums are taken in a fixed order:

@@ -65,12 +65,12 @@ hmfsr_status validate(const hmfsr_desc* d, const hmfsr_tuning* t) {
   if (!d || !t) return HMFSR_E_INVALID;
   const hmfsr_status st = validate_desc(d);
   if (st != HMFSR_OK) return st;
-  const float vals[10] = {t->k_detail, t->k_denoise, t->d_th, t->d_tr, t->k_stretch,
-                          t->k_shrink, t->s, t->t, t->s_motion, t->m_th};
+  const float vals[11] = {t->k_detail, t->k_denoise, t->d_th, t->d_tr, t->k_stretch,
+                          t->k_shrink, t->s, t->t, t->s_motion, t->m_th, t->hf_ratio};
   for (float v : vals)
     if (!finite(v)) return HMFSR_E_INVALID;
   if (!(t->k_detail > 0.f) || !(t->k_denoise > 0.f) || !(t->d_tr > 0.f) || !(t->k_stretch > 0.f) ||
-      !(t->k_shrink > 0.f) || t->s < 0.f || t->s_motion < 0.f || t->m_th < 0.f)
+      !(t->k_shrink > 0.f) || t->s < 0.f || t->s_motion < 0.f || t->m_th < 0.f || t->hf_ratio < 0.f)
     return HMFSR_E_INVALID;
   return HMFSR_OK;
 }
@@ -125,6 +125,8 @@ RobustConsts make_robust(const hmfsr_desc* d, const hmfsr_tuning* t) {
   r.a_r = (float)((double)d->noise_a * range);
   r.b_r = (float)((double)d->noise_b * range * range);
   r.t = t->t;
+  r.hf = t->hf_ratio;
+  r.m_th = t->m_th;
   return r;
 }
 

@@ -34,6 +34,8 @@ struct RobustConsts {
   float a_r;  // noise_a * range: variance slope per raw unit of brightness
   float b_r;  // noise_b * range^2
   float t;
+  double hf;    // S.3 variance-loss threshold; 0 turns the rejection off
+  double m_th;  // the motion prior's threshold, for the S.3 test's tile decision
 };
 
 // Accumulation constants.

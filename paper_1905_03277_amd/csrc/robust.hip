@@ -12,8 +12,16 @@
 //
 // Colour statistics are kept in raw units (the black level enters only the
 // noise model's brightness): the ratio d^2 / sigma^2 of eq. (5) is scale-free.
+//
+// High-frequency rejection (supplement S.3, when rc.hf > 0): with x the base
+// guide doubled to integers and S its 3x3 box sums, per region pixel
+// B = sum_c 9 sum x^2 - (sum x)^2 over the 3x3 window and A = the same over the
+// 3x3 window of S (all integers below 2^53, so float64 holds them exactly);
+// where A < hf * 81 B (variance lost to the low-pass) and the tile's motion
+// prior chose s1 (eq. 8), R of the aligned frame is 0.
 #include "device_util.h"
 #include "hmfsr_internal.h"
+#include "prior.h"
 
 namespace hmfsr {
 namespace {
@@ -64,6 +72,8 @@ struct RobustSmem {
   Bounds4 sTB[TT_X * TT_Y];
   int sRed[5];
   int sItem;
+  int sLoss[RR_N];           // S.3 variance loss of the base guide per region pixel
+  int sMov[TT_X * TT_Y];     // motion prior's choice (s1) per alignment tile
 };
 
 // R_hat of one 32x16 half-res tile (tile_x, tile_y) of one burst, every aligned frame.
@@ -90,6 +100,8 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
   float* sS = sm.sS;
   Bounds4* sTB = sm.sTB;
   int* sRed = sm.sRed;
+  int* sLoss = sm.sLoss;
+  int* sMov = sm.sMov;
 
   const int tid = threadIdx.x;
   const int I0 = tile_y * RB_H, J0 = tile_x * RB_W;
@@ -118,9 +130,11 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
   // ---- base frame statistics, once ------------------------------------
   {
     const uint16_t* f = frames + (size_t)g.ref * g.H * g.W;
-    // guide rows/cols around the clamped region, edge-replicated one step further
-    const int gr0 = clampi(ra0, 0, g.h - 1) - 1, gr1 = clampi(ra0 + RR_H - 1, 0, g.h - 1) + 1;
-    const int gc0 = clampi(ca0, 0, g.w - 1) - 1, gc1 = clampi(ca0 + RR_W - 1, 0, g.w - 1) + 1;
+    // guide rows/cols around the clamped region, edge-replicated one step
+    // further (two with the S.3 test, whose box sums need a ring more)
+    const int ring = rc.hf > 0.0 ? 2 : 1;
+    const int gr0 = clampi(ra0, 0, g.h - 1) - ring, gr1 = clampi(ra0 + RR_H - 1, 0, g.h - 1) + ring;
+    const int gc0 = clampi(ca0, 0, g.w - 1) - ring, gc1 = clampi(ca0 + RR_W - 1, 0, g.w - 1) + ring;
     const int gw = gc1 - gc0 + 1, gn = gw * (gr1 - gr0 + 1);
     const float ginv = 1.f / (float)gw;
     for (int k = tid; k < gn; k += THREADS) {
@@ -163,6 +177,55 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
       }
       sInvDen[k] = 1.f / den;
     }
+    if (rc.hf > 0.0) {
+      // box sums of the doubled guide at the image positions rows
+      // [clamp(ra0) - 1, clamp(ra0 + RR_H - 1) + 1], columns alike (integers
+      // below 2^24: exact in float whatever the order)
+      const int sr0 = clampi(ra0, 0, g.h - 1) - 1, sc0 = clampi(ca0, 0, g.w - 1) - 1;
+      const int sh = clampi(ra0 + RR_H - 1, 0, g.h - 1) + 1 - sr0 + 1;
+      const int swd = clampi(ca0 + RR_W - 1, 0, g.w - 1) + 1 - sc0 + 1;
+      const float sinv = 1.f / (float)swd;
+      for (int k = tid; k < sh * swd; k += THREADS) {
+        const int q = split_row(k, sinv);
+        const int P = sr0 + q, Q = sc0 + k - q * swd;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          float sum = 0.f;
+#pragma unroll
+          for (int a = -1; a <= 1; ++a)
+#pragma unroll
+            for (int b = -1; b <= 1; ++b)
+              sum += 2.f * sGuide[c][(clampi(P + a, 0, g.h - 1) - gr0) * gw + clampi(Q + b, 0, g.w - 1) - gc0];
+          sHs[c][k] = sum;
+        }
+      }
+      __syncthreads();
+      const float rinv2 = 1.f / (float)RR_W;
+      for (int k = tid; k < RR_N; k += THREADS) {
+        const int rr = split_row(k, rinv2), cc = k - rr * RR_W;
+        const int I = clampi(ra0 + rr, 0, g.h - 1), J = clampi(ca0 + cc, 0, g.w - 1);
+        double A = 0.0, B = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          double sx = 0.0, sxx = 0.0, ss = 0.0, sss = 0.0;
+#pragma unroll
+          for (int a = -1; a <= 1; ++a)
+#pragma unroll
+            for (int b = -1; b <= 1; ++b) {
+              const int y = clampi(I + a, 0, g.h - 1), x = clampi(J + b, 0, g.w - 1);
+              const double xv = 2.0 * (double)sGuide[c][(y - gr0) * gw + x - gc0];
+              const double sv = (double)sHs[c][(y - sr0) * swd + x - sc0];
+              sx += xv;
+              sxx += xv * xv;
+              ss += sv;
+              sss += sv * sv;
+            }
+          B += 9.0 * sxx - sx * sx;
+          A += 9.0 * sss - ss * ss;
+        }
+        sLoss[k] = A < rc.hf * (81.0 * B);
+      }
+    }
   }
 
   // ---- aligned frames -------------------------------------------------
@@ -189,6 +252,7 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
         sO[k] = o;
         sF[k] = make_float2(hx - fx, hy - fy);  // exact: v/2 has at most 24 significant bits
         sS[k] = s_tile[t];
+        if (rc.hf > 0.0) sMov[k] = prior_moving(motion, g, rc.m_th, n, tyA + ky, txA + kx);
         Bounds4 b;
         b.x0 = clampi(ca0 + sClo[kx], 0, g.w - 1) + o.x;
         b.x1 = clampi(ca0 + sChi[kx], 0, g.w - 1) + o.x;
@@ -316,7 +380,7 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
             num = fmaf(dd, dd, num);
           }
           const float R = sS[kt] * __expf(-num * sInvDen[k]) - rc.t;  // eq. (5)
-          sR[k] = fminf(fmaxf(R, 0.f), 1.f);
+          sR[k] = rc.hf > 0.0 && sLoss[k] && sMov[kt] ? 0.f : fminf(fmaxf(R, 0.f), 1.f);
         }
       }
       __syncthreads();

@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version_and_strerror():
-    assert binding.hmfsr_version() == 120
+    assert binding.hmfsr_version() == 130
     assert "INVALID" in binding.strerror(binding.HMFSR_E_INVALID)
     assert "unknown" in binding.strerror(-99)
 
@@ -57,6 +57,7 @@ def test_invalid_descriptor_rejected(field, value):
 @pytest.mark.parametrize("field,value", [
     ("k_detail", 0.0), ("k_denoise", -1.0), ("d_tr", 0.0), ("k_stretch", 0.0),
     ("k_shrink", float("inf")), ("t", float("nan")), ("s", -1.0), ("m_th", -0.1),
+    ("hf_ratio", -0.1), ("hf_ratio", float("nan")),
 ])
 def test_invalid_tuning_rejected(field, value):
     desc, tun = _good()
