@@ -280,6 +280,28 @@ def bench_align(burst, out, reps: int = 10) -> dict:
             "raw_to_rgb_MPs": round(in_mp / (res["raw_to_rgb"] / 1e3), 1)}
 
 
+def bench_hf(burst, out, reps: int = 10) -> dict:
+    """The same 12 MP x 8 merge with the high-frequency artefact rejection of
+    S.3 switched on (hf_ratio 0.02): per-stage times from the library's event
+    timing, with the generator's vectors and with the aligner's own."""
+    import torch
+    from paper_1905_03277_amd import binding, torch_ops
+
+    d = burst.desc
+    tun = burst.tuning.replace(hf_ratio=0.02)
+    aligned = torch_ops.align(burst.frames, d)
+    res = {"workload": "12 MP x 8 merge with S.3 rejection (hf_ratio 0.02)"}
+    for name, motion in (("given_vectors", burst.motion), ("aligned_vectors", aligned)):
+        torch_ops.merge(burst.frames, motion, d, tun, out=out)
+        torch.cuda.synchronize()
+        binding.hmfsr_profile_begin()
+        for _ in range(reps):
+            torch_ops.merge(burst.frames, motion, d, tun, out=out)
+        st = binding.hmfsr_profile_end()
+        res[name] = {k: round(tot / max(cnt, 1), 4) for k, (tot, cnt) in st.items() if cnt}
+    return res
+
+
 def bench_grad(dev, reps: int = 3) -> dict:
     """The differentiation workload: 16 bursts of 8 x 768 x 1024 RGGB at scale 2.
     One pass = for every burst, the forward merge (keeping the normaliser of
@@ -437,6 +459,7 @@ def main():
         line["streaming"] = bench_stream(burst, out)
     if not args.no_align:
         line["alignment"] = bench_align(burst, out)
+        line["hf_rejection"] = bench_hf(burst, out)
     if not args.no_batch:
         line["batched"] = bench_batch(dev)
     if not args.no_grad:

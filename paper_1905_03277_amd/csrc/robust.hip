@@ -21,7 +21,6 @@
 // prior chose s1 (eq. 8), R of the aligned frame is 0.
 #include "device_util.h"
 #include "hmfsr_internal.h"
-#include "prior.h"
 
 namespace hmfsr {
 namespace {
@@ -74,6 +73,7 @@ struct RobustSmem {
   int sItem;
   int sLoss[RR_N];           // S.3 variance loss of the base guide per region pixel
   int sMov[TT_X * TT_Y];     // motion prior's choice (s1) per alignment tile
+  float2 sMv[(TT_X + 2) * (TT_Y + 2)];  // the frame's vectors of those tiles and a ring
 };
 
 // R_hat of one 32x16 half-res tile (tile_x, tile_y) of one burst, every aligned frame.
@@ -102,6 +102,7 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
   int* sRed = sm.sRed;
   int* sLoss = sm.sLoss;
   int* sMov = sm.sMov;
+  float2* sMv = sm.sMv;
 
   const int tid = threadIdx.x;
   const int I0 = tile_y * RB_H, J0 = tile_x * RB_W;
@@ -230,10 +231,25 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
 
   // ---- aligned frames -------------------------------------------------
   const float vlim = (float)(max(g.W, g.H) + 16);
+  const int mvw = ntx + 2, mvn = (nty + 2) * (ntx + 2);
   for (int n = 0; n < g.n; ++n) {
     if (n == g.ref) continue;
     const uint16_t* f = frames + (size_t)n * g.H * g.W;
     __syncthreads();
+    if (rc.hf > 0.0) {
+      // the S.3 test takes the motion prior's decision (eq. 8) per tile: stage
+      // the tiles' vectors and their ring once, in one round of loads
+      for (int k = tid; k < mvn; k += THREADS) {
+        const int y = tyA - 1 + k / mvw, x = txA - 1 + k % mvw;
+        float2 v = make_float2(0.f, 0.f);
+        if (y >= 0 && y < g.TY && x >= 0 && x < g.TX) {
+          const float* p = motion + (((size_t)n * g.TY + y) * g.TX + x) * 2;  // 4-byte aligned
+          v = make_float2(p[0], p[1]);
+        }
+        sMv[k] = v;
+      }
+      __syncthreads();
+    }
     // per alignment tile: the bilinear base corner of u + v/2 is u + floor(v/2)
     // (u integer) with the same fractions for every pixel of the tile; and the
     // tile's footprint (monotonic in the pixel position). Wave 0 reduces the
@@ -252,7 +268,23 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
         sO[k] = o;
         sF[k] = make_float2(hx - fx, hy - fy);  // exact: v/2 has at most 24 significant bits
         sS[k] = s_tile[t];
-        if (rc.hf > 0.0) sMov[k] = prior_moving(motion, g, rc.m_th, n, tyA + ky, txA + kx);
+        if (rc.hf > 0.0) {
+          // eq. (7)-(8) as the motion prior takes them: spread over the existing
+          // 3x3 tiles in float64, M^2 > M_th^2 rounded operation by operation
+          double xmax = -INFINITY, xmin = INFINITY, ymax = -INFINITY, ymin = INFINITY;
+          for (int a = -1; a <= 1; ++a)
+            for (int b = -1; b <= 1; ++b) {
+              const int y = tyA + ky + a, x = txA + kx + b;
+              if (y < 0 || y >= g.TY || x < 0 || x >= g.TX) continue;
+              const float2 v = sMv[(ky + 1 + a) * mvw + kx + 1 + b];
+              xmax = fmax(xmax, (double)v.x);
+              xmin = fmin(xmin, (double)v.x);
+              ymax = fmax(ymax, (double)v.y);
+              ymin = fmin(ymin, (double)v.y);
+            }
+          const double mx = xmax - xmin, my = ymax - ymin;
+          sMov[k] = __dadd_rn(__dmul_rn(mx, mx), __dmul_rn(my, my)) > __dmul_rn(rc.m_th, rc.m_th);
+        }
         Bounds4 b;
         b.x0 = clampi(ca0 + sClo[kx], 0, g.w - 1) + o.x;
         b.x1 = clampi(ca0 + sChi[kx], 0, g.w - 1) + o.x;
