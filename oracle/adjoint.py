@@ -145,9 +145,8 @@ def _robust_parts(maps, k, desc, tuning):
     v = motion[k][ty, tx]
     mu_w, dmu_x, dmu_y, cells = bilinear_grad(mu[k], jj + v[..., 0] / 2.0, ii + v[..., 1] / 2.0)
     mu_ref, sd_ref = mu[ref], sd[ref]
-    var = float(om._get(desc, "noise_a")) * np.maximum(mu_ref, 0.0) + float(om._get(desc, "noise_b"))
-    var[1] = var[1] / 2.0
-    d_md_sq = 2.0 * var / 9.0
+    var, d_md_sq = om.noise_terms(mu_ref, om._get(desc, "noise_a"), om._get(desc, "noise_b"),
+                                  om.desc_table(desc))
     sigma = np.maximum(sd_ref, np.sqrt(var))
     d_ms = mu_ref - mu_w
     d = d_ms * (d_ms * d_ms) / (d_ms * d_ms + d_md_sq)

@@ -272,7 +272,34 @@ def motion_prior(motion_n, s1, s2, m_th):
 # --------------------------------------------------------------------------- #
 # step 7: robustness                                                          #
 # --------------------------------------------------------------------------- #
-def robustness(mu_ref, sd_ref, mu_n, motion_n, s_tile, t, noise_a, noise_b, tile, reject=None):
+def noise_terms(mu_ref, noise_a, noise_b, table=None):
+    """Modelled guide variance sigma_md^2 and squared difference of two 3x3
+    means d_md^2 per channel at the base brightness mu_ref [3][h][w] (Sec.
+    5.2.2): from a Monte-Carlo table [bins][4] (R/B columns 0-1, green 2-3;
+    ``oracle.noise``) when given, else the unclipped closed forms
+    var = a max(mu, 0) + b (halved for the two-green mean), d_md^2 = 2 var / 9."""
+    if table is not None:
+        from oracle import noise as on
+        t = np.asarray(table, dtype=np.float64)
+        sig2 = np.stack([on.table_lookup(t, mu_ref[c], 2 if c == 1 else 0) for c in range(3)])
+        dmd2 = np.stack([on.table_lookup(t, mu_ref[c], 3 if c == 1 else 1) for c in range(3)])
+        return sig2, dmd2
+    var = float(noise_a) * np.maximum(mu_ref, 0.0) + float(noise_b)
+    var[1] = var[1] / 2.0                      # guide green = mean of two greens
+    return var, 2.0 * var / 9.0
+
+
+def desc_table(desc):
+    """The descriptor's noise table as a numpy array, or None."""
+    t = _opt(desc, "noise_table", None)
+    if t is None:
+        return None
+    if hasattr(t, "detach"):
+        t = t.detach().cpu().numpy()
+    return np.asarray(t, dtype=np.float64)
+
+
+def robustness(mu_ref, sd_ref, mu_n, motion_n, s_tile, t, noise_a, noise_b, tile, reject=None, table=None):
     """Robustness R on the base frame's half-resolution grid for one aligned
     frame, eqs. (5)-(6). Returns (R, R_hat) with R_hat the 5x5 minimum, eq. (9).
 
@@ -292,11 +319,8 @@ def robustness(mu_ref, sd_ref, mu_n, motion_n, s_tile, t, noise_a, noise_b, tile
     v = np.asarray(motion_n, dtype=np.float64)[ty, tx]           # [h][w][2]
     mu_w = bilinear(mu_n, jj + v[..., 0] / 2.0, ii + v[..., 1] / 2.0)   # [3][h][w]
 
-    bright = np.maximum(mu_ref, 0.0)
-    var = float(noise_a) * bright + float(noise_b)
-    var[1] = var[1] / 2.0                      # guide green = mean of two greens
+    var, d_md_sq = noise_terms(mu_ref, noise_a, noise_b, table)
     sigma_md = np.sqrt(var)
-    d_md_sq = 2.0 * var / 9.0
     sigma = np.maximum(sd_ref, sigma_md)                           # eq. (6), first line
     d_ms = mu_ref - mu_w
     d = d_ms * (d_ms * d_ms) / (d_ms * d_ms + d_md_sq)             # eq. (6), second line
@@ -351,7 +375,7 @@ def prepare(frames, motion, desc, tuning):
             hf_reject[k] = hf_loss & (moving[ty, tx] > 0.5)
         r_raw[k], r_hat[k] = robustness(mu[ref], sd[ref], mu[k], motion[k], s_tiles[k],
                                         _get(tuning, "t"), _get(desc, "noise_a"),
-                                        _get(desc, "noise_b"), tile, hf_reject[k])
+                                        _get(desc, "noise_b"), tile, hf_reject[k], desc_table(desc))
     return dict(x=x, lum=lum, guide=guide, omega=omega, mu=mu, sd=sd, motion=motion,
                 r=r_raw, r_hat=r_hat, s_tiles=s_tiles, m_tiles=m_tiles, hf_reject=hf_reject,
                 colours=colour_map(h, w, cfa), ref=ref, tile=tile)

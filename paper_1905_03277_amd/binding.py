@@ -41,7 +41,8 @@ class hmfsr_desc(ctypes.Structure):
                 ("white_level", ctypes.c_float), ("noise_a", ctypes.c_float),
                 ("noise_b", ctypes.c_float), ("tile_size", ctypes.c_int32),
                 ("scale", ctypes.c_float), ("out_height", ctypes.c_int32),
-                ("out_width", ctypes.c_int32)]
+                ("out_width", ctypes.c_int32), ("noise_table", ctypes.c_void_p),
+                ("noise_bins", ctypes.c_int32)]
 
 
 class hmfsr_tuning(ctypes.Structure):
@@ -124,8 +125,26 @@ def _check(status: int, what: str):
 
 
 def make_desc(d) -> hmfsr_desc:
-    """hmfsr_desc from any object with the same field names."""
-    return hmfsr_desc(*(getattr(d, f) for f, _ in hmfsr_desc._fields_))
+    """hmfsr_desc from any object with the same field names. ``noise_table``
+    (optional) must be a contiguous float32 device tensor [bins][4]; the bin
+    count is taken from its shape."""
+    vals = []
+    table = getattr(d, "noise_table", None)
+    for f, _ in hmfsr_desc._fields_:
+        if f == "noise_table":
+            if table is None:
+                vals.append(None)
+            else:
+                if not (hasattr(table, "is_cuda") and table.is_cuda and table.is_contiguous()
+                        and str(table.dtype) == "torch.float32" and table.dim() == 2
+                        and table.shape[1] == 4):
+                    raise ValueError("noise_table must be a contiguous float32 device tensor [bins][4]")
+                vals.append(table.data_ptr())
+        elif f == "noise_bins":
+            vals.append(0 if table is None else int(table.shape[0]))
+        else:
+            vals.append(getattr(d, f))
+    return hmfsr_desc(*vals)
 
 
 def make_tuning(t) -> hmfsr_tuning:

@@ -106,6 +106,9 @@ class Desc:
     scale: float = 1.0
     out_height: int = 0
     out_width: int = 0
+    # Monte-Carlo noise table float32 [bins][4] (None: the closed forms); a
+    # device tensor for the library, any array for the oracle
+    noise_table: object = field(default=None, compare=False, repr=False)
 
     def __post_init__(self):
         for name in ("black_level", "white_level", "noise_a", "noise_b", "scale"):
