@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define HMFSR_VERSION 130 /* 1.3.0 */
+#define HMFSR_VERSION 140 /* 1.4.0 */
 
 /* Colour filter array layout: colours of the 2x2 Bayer cell read row by row. */
 typedef enum {
@@ -75,6 +75,18 @@ typedef enum {
  *               must equal floor(height * scale + 0.5), floor(width * scale + 0.5).
  *               Output pixel (R, C) sits at base-frame position
  *               ((C + 1/2) / s, (R + 1/2) / s) in pixel-edge coordinates.
+ *  noise_bins, noise_table
+ *               0 and NULL: the robustness uses the closed forms of the noise
+ *               model, sigma_md^2 = var and d_md^2 = 2 var / 9 with
+ *               var = a x + b at the base brightness x (halved for the guide's
+ *               two-green mean). Else a DEVICE float32 table [noise_bins][4],
+ *               4-byte aligned, 2 <= noise_bins <= 65536, as hmfsr_noise_table
+ *               writes it: per brightness x_i = i / (noise_bins - 1)
+ *               (normalised units), sigma_md^2 and d_md^2 of an R or B guide
+ *               pixel, then of the green mean (Sec. 5.2.2's Monte-Carlo
+ *               tables); it is interpolated linearly at the base brightness
+ *               clamped to [0, 1], and read by every call that takes the
+ *               descriptor.
  */
 typedef struct {
   int32_t n_frames, height, width;
@@ -85,6 +97,8 @@ typedef struct {
   int32_t tile_size;
   float scale;
   int32_t out_height, out_width;
+  int32_t noise_bins;
+  const float* noise_table;
 } hmfsr_desc;
 
 /*
@@ -245,6 +259,44 @@ typedef struct {
  */
 hmfsr_status hmfsr_align(const hmfsr_desc* desc, const hmfsr_align_params* params, const uint16_t* frames,
                          float* motion, int32_t* block_match, void* stream);
+
+/*
+ * hmfsr_noise_table -- the Monte-Carlo noise tables of Sec. 5.2.2 for the
+ * descriptor's noise model (noise_a, noise_b) and raw range (black_level,
+ * white_level), written to `table` (DEVICE float32 [bins][4], 4-byte aligned)
+ * in the layout hmfsr_desc.noise_table reads. The paper simulates constant
+ * patches per brightness level so that clipping at the white point is
+ * accounted for and gives no further detail; this library's simulation:
+ * brightness x_i = i / (bins - 1); per patch two frames of nine guide pixels
+ * (an R or B pixel is one raw sample, the green guide the mean of two), raw
+ * samples x + sqrt(a max(x, 0) + b) z clipped to the raw range
+ * [-black / (white - black), 1]; sigma_md^2 = the mean of the two frames'
+ * unbiased 3x3 variances and d_md^2 = the mean squared difference of their
+ * 3x3 means, over `patches` patches. Normals: Philox4x32-10 (Salmon et al.,
+ * SC 2011) with counter (patch, bin, 16 class + j, 0), key (seed low 32 bits,
+ * high 32 bits), four uniforms (u + 1/2) 2^-32 per call paired by Box-Muller;
+ * sums in float64, in a fixed order (repeated calls give the same bits).
+ *  bins 2..65536, patches 1..2^24.
+ */
+hmfsr_status hmfsr_noise_table(const hmfsr_desc* desc, int32_t bins, int32_t patches, uint64_t seed,
+                               float* table, void* stream);
+
+/*
+ * hmfsr_auto_tuning -- SNR-dependent tuning (Sec. 7.2, supplement S.2): the
+ * base frame's SNR x / sqrt(a max(x, 0) + b), x its mean normalised raw value
+ * (an exact integer sum on the device), and tuning values piecewise linear in
+ * the SNR over [6, 30] between S.2's printed ends (the paper prints no
+ * breakpoints): with s = clamp((SNR - 6) / 24, 0, 1) and v = (1 - s) v_6 +
+ * s v_30, k_detail 0.33 -> 0.25, k_denoise 5 -> 3, d_th 0.010 -> 0.001,
+ * d_tr 0.020 -> 0.006; k_stretch 4, k_shrink 2, s 2, t 0.12, s_motion 12,
+ * m_th 0.8 and hf_ratio 0 fixed; tile size 64 below SNR 14, 32 below 22, else
+ * 16. Synchronises `stream` (the results are host values).
+ *  frames   DEVICE uint16 [n_frames][height][width] (only the base frame is read).
+ *  tuning   HOST, receives the tuning values.
+ *  tile_size, snr  HOST, nullable: the suggested tile size and the SNR.
+ */
+hmfsr_status hmfsr_auto_tuning(const hmfsr_desc* desc, const uint16_t* frames, hmfsr_tuning* tuning,
+                               int32_t* tile_size, double* snr, void* stream);
 
 /*
  * hmfsr_merge_maps -- the per-frame intermediate maps of the merge, for

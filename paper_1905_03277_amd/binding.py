@@ -18,7 +18,8 @@ HMFSR_OK, HMFSR_E_INVALID, HMFSR_E_UNSUPPORTED, HMFSR_E_HIP, HMFSR_E_NOMEM = 0, 
 
 # Every symbol include/hmfsr.h declares.
 EXPORTED = ("hmfsr_merge", "hmfsr_merge_backward", "hmfsr_stream_begin", "hmfsr_stream_add",
-            "hmfsr_stream_end", "hmfsr_align", "hmfsr_merge_maps", "hmfsr_merge_batch", "hmfsr_autotune",
+            "hmfsr_stream_end", "hmfsr_align", "hmfsr_noise_table", "hmfsr_auto_tuning",
+            "hmfsr_merge_maps", "hmfsr_merge_batch", "hmfsr_autotune",
             "hmfsr_profile_begin", "hmfsr_profile_end", "hmfsr_strerror", "hmfsr_version",
             "hmfsr_release")
 
@@ -41,8 +42,8 @@ class hmfsr_desc(ctypes.Structure):
                 ("white_level", ctypes.c_float), ("noise_a", ctypes.c_float),
                 ("noise_b", ctypes.c_float), ("tile_size", ctypes.c_int32),
                 ("scale", ctypes.c_float), ("out_height", ctypes.c_int32),
-                ("out_width", ctypes.c_int32), ("noise_table", ctypes.c_void_p),
-                ("noise_bins", ctypes.c_int32)]
+                ("out_width", ctypes.c_int32), ("noise_bins", ctypes.c_int32),
+                ("noise_table", ctypes.c_void_p)]
 
 
 class hmfsr_tuning(ctypes.Structure):
@@ -94,6 +95,10 @@ def lib() -> ctypes.CDLL:
         L.hmfsr_stream_end.restype = i32
         L.hmfsr_align.argtypes = [pd, ctypes.POINTER(hmfsr_align_params), vp, vp, vp, vp]
         L.hmfsr_align.restype = i32
+        L.hmfsr_noise_table.argtypes = [pd, i32, i32, ctypes.c_uint64, vp, vp]
+        L.hmfsr_noise_table.restype = i32
+        L.hmfsr_auto_tuning.argtypes = [pd, vp, pt, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), vp]
+        L.hmfsr_auto_tuning.restype = i32
         L.hmfsr_merge_maps.argtypes = [pd, pt, vp, vp, vp, vp, vp, vp, vp]
         L.hmfsr_merge_maps.restype = i32
         L.hmfsr_merge_batch.argtypes = [i32, pd, pt, ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -195,6 +200,21 @@ def hmfsr_align(desc, params, frames: int, motion: int, block_match: int = 0, st
     """params: hmfsr_align_params or None (the library's defaults)."""
     _check(lib().hmfsr_align(ctypes.byref(desc), ctypes.byref(params) if params is not None else None,
                              frames, motion, block_match or None, stream or None), "hmfsr_align")
+
+
+def hmfsr_noise_table(desc, bins: int, patches: int, seed: int, table: int, stream: int = 0) -> None:
+    _check(lib().hmfsr_noise_table(ctypes.byref(desc), int(bins), int(patches), int(seed), table,
+                                   stream or None), "hmfsr_noise_table")
+
+
+def hmfsr_auto_tuning(desc, frames: int, stream: int = 0):
+    """(hmfsr_tuning, tile size, SNR) for the burst's base frame."""
+    tun = hmfsr_tuning()
+    tile = ctypes.c_int32(0)
+    snr = ctypes.c_double(0.0)
+    _check(lib().hmfsr_auto_tuning(ctypes.byref(desc), frames, ctypes.byref(tun), ctypes.byref(tile),
+                                   ctypes.byref(snr), stream or None), "hmfsr_auto_tuning")
+    return tun, tile.value, snr.value
 
 
 def hmfsr_merge_maps(desc, tuning, frames: int, motion: int, omega: int, robust: int,

@@ -56,6 +56,9 @@ hmfsr_status validate_desc(const hmfsr_desc* d) {
   if (d->out_height != (int32_t)floor((double)d->height * s + 0.5) ||
       d->out_width != (int32_t)floor((double)d->width * s + 0.5))
     return HMFSR_E_INVALID;
+  if (d->noise_table ? (d->noise_bins < 2 || d->noise_bins > 65536 || ((uintptr_t)d->noise_table & 3))
+                     : d->noise_bins != 0)
+    return HMFSR_E_INVALID;
   int cols[4];
   if (!cfa_colours(d->cfa, cols)) return HMFSR_E_UNSUPPORTED;
   return HMFSR_OK;
@@ -127,6 +130,10 @@ RobustConsts make_robust(const hmfsr_desc* d, const hmfsr_tuning* t) {
   r.t = t->t;
   r.hf = t->hf_ratio;
   r.m_th = t->m_th;
+  r.ntab = d->noise_table;
+  r.nbins = d->noise_bins;
+  r.inv_range = (float)(1.0 / range);
+  r.range2 = (float)(range * range);
   return r;
 }
 
@@ -193,6 +200,10 @@ hmfsr_status stream_workspace(int dev, size_t bytes, hipStream_t stream, void** 
 
 hmfsr_status align_workspace(int dev, size_t bytes, hipStream_t stream, void** out) {
   return grow(g_dev[dev].align_ws, g_dev[dev].align_ws_bytes, bytes, stream, out);
+}
+
+hmfsr_status grow_buffer(void*& buf, size_t& have, size_t bytes, hipStream_t stream, void** out) {
+  return grow(buf, have, bytes, stream, out);
 }
 
 namespace {
@@ -472,6 +483,79 @@ hmfsr_status hmfsr_align(const hmfsr_desc* desc, const hmfsr_align_params* param
              : HMFSR_E_HIP;
 }
 
+hmfsr_status hmfsr_noise_table(const hmfsr_desc* desc, int32_t bins, int32_t patches, uint64_t seed, float* table,
+                               void* stream) {
+  hmfsr_status st = validate_desc(desc);
+  if (st != HMFSR_OK) return st;
+  if (bins < 2 || bins > 65536 || patches < 1 || patches > (1 << 24) || !table || ((uintptr_t)table & 3))
+    return HMFSR_E_INVALID;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  int dev = 0;
+  if ((st = current_device(&dev)) != HMFSR_OK) return st;
+  const double lo = -(double)desc->black_level / ((double)desc->white_level - (double)desc->black_level);
+  return launch_noise_table((double)desc->noise_a, (double)desc->noise_b, lo, bins, patches,
+                            (unsigned long long)seed, table, (hipStream_t)stream) == hipSuccess
+             ? HMFSR_OK
+             : HMFSR_E_HIP;
+}
+
+hmfsr_status hmfsr_auto_tuning(const hmfsr_desc* desc, const uint16_t* frames, hmfsr_tuning* tuning,
+                               int32_t* tile_size, double* snr_out, void* stream) {
+  hmfsr_status st = validate_desc(desc);
+  if (st != HMFSR_OK) return st;
+  if (!frames || ((uintptr_t)frames & 3) || !tuning) return HMFSR_E_INVALID;
+  unsigned long long total = 0;
+  {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    int dev = 0;
+    if ((st = current_device(&dev)) != HMFSR_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    void* ws = nullptr;
+    DeviceState& ds = g_dev[dev];
+    if ((st = grow_buffer(ds.sum_ws, ds.sum_ws_bytes, (kFrameSumGroups + 1) * sizeof(unsigned long long), s, &ws)) !=
+        HMFSR_OK)
+      return st;
+    unsigned long long* parts = (unsigned long long*)ws;
+    const long long n = (long long)desc->height * desc->width;
+    if (launch_frame_sum(frames + (size_t)desc->ref_frame * n, n, parts, parts + kFrameSumGroups, s) != hipSuccess ||
+        hipMemcpyAsync(&total, parts + kFrameSumGroups, sizeof(total), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return HMFSR_E_HIP;
+  }
+  // SNR at the mean brightness, rounded operation by operation (one statement
+  // per operation: no contraction)
+  const double n = (double)desc->height * (double)desc->width;
+  const double mean_raw = (double)total / n;
+  const double black = desc->black_level, white = desc->white_level;
+  const double mu = (mean_raw - black) / (white - black);
+  double var = (double)desc->noise_a * fmax(mu, 0.0);
+  var = var + (double)desc->noise_b;
+  const double snr = mu / sqrt(var);
+  double f = (snr - 6.0) / (30.0 - 6.0);
+  f = fmin(fmax(f, 0.0), 1.0);
+  auto lerp = [f](double lo, double hi) {
+    const double p = (1.0 - f) * lo;
+    const double q = f * hi;
+    return (float)(p + q);
+  };
+  hmfsr_tuning t;
+  t.k_detail = lerp(0.33, 0.25);
+  t.k_denoise = lerp(5.0, 3.0);
+  t.d_th = lerp(0.010, 0.001);
+  t.d_tr = lerp(0.020, 0.006);
+  t.k_stretch = 4.f;
+  t.k_shrink = 2.f;
+  t.s = 2.f;
+  t.t = 0.12f;
+  t.s_motion = 12.f;
+  t.m_th = 0.8f;
+  t.hf_ratio = 0.f;
+  *tuning = t;
+  if (tile_size) *tile_size = snr < 14.0 ? 64 : (snr < 22.0 ? 32 : 16);
+  if (snr_out) *snr_out = snr;
+  return HMFSR_OK;
+}
+
 const char* hmfsr_strerror(hmfsr_status status) {
   switch (status) {
     case HMFSR_OK: return "HMFSR_OK";
@@ -523,8 +607,8 @@ void hmfsr_release(void) {
   const bool have_cur = hipGetDevice(&cur) == hipSuccess;
   for (int d = 0; d < kMaxDevices; ++d) {
     DeviceState& st = g_dev[d];
-    if (!st.workspace && !st.batch_ws && !st.bwd_ws && !st.stream_ws && !st.align_ws && !st.plan.exec &&
-        !st.capture_stream)
+    if (!st.workspace && !st.batch_ws && !st.bwd_ws && !st.stream_ws && !st.align_ws && !st.sum_ws &&
+        !st.plan.exec && !st.capture_stream)
       continue;
     if (hipSetDevice(d) != hipSuccess) continue;
     if (st.plan.exec) hipGraphExecDestroy(st.plan.exec);
@@ -539,6 +623,9 @@ void hmfsr_release(void) {
     if (st.align_ws) hipFree(st.align_ws);
     st.align_ws = nullptr;
     st.align_ws_bytes = 0;
+    if (st.sum_ws) hipFree(st.sum_ws);
+    st.sum_ws = nullptr;
+    st.sum_ws_bytes = 0;
     if (st.capture_stream) hipStreamDestroy(st.capture_stream);
     st.workspace = st.batch_ws = st.bwd_ws = nullptr;
     st.workspace_bytes = st.batch_ws_bytes = st.bwd_ws_bytes = 0;

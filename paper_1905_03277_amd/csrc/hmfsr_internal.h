@@ -36,6 +36,10 @@ struct RobustConsts {
   float t;
   double hf;    // S.3 variance-loss threshold; 0 turns the rejection off
   double m_th;  // the motion prior's threshold, for the S.3 test's tile decision
+  const float* ntab;  // Monte-Carlo noise table [nbins][4] (normalised units), or null
+  int nbins;
+  float inv_range;    // 1 / (white - black)
+  float range2;       // (white - black)^2
 };
 
 // Accumulation constants.
@@ -176,5 +180,16 @@ struct AlignGeom {
 size_t align_bytes(const AlignGeom& ag);
 hipError_t launch_align(const AlignGeom& ag, const uint16_t* frames, int H, int W, void* ws,
                         float* motion, int* block_match, hipStream_t stream);
+
+// ---- noise model ----------------------------------------------------------------
+
+// Monte-Carlo noise table into `table` [bins][4] (float32).
+hipError_t launch_noise_table(double a, double b, double lo, int bins, int patches, unsigned long long seed,
+                              float* table, hipStream_t stream);
+// Sum of one frame's raw values into *sum (device, one 64-bit word); `parts`
+// holds one word per workgroup of the first pass (at most kFrameSumGroups).
+constexpr int kFrameSumGroups = 1024;
+hipError_t launch_frame_sum(const uint16_t* frame, long long n, unsigned long long* parts,
+                            unsigned long long* sum, hipStream_t stream);
 
 }  // namespace hmfsr

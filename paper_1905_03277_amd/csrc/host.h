@@ -34,6 +34,8 @@ struct DeviceState {
   size_t stream_ws_bytes = 0;
   void* align_ws = nullptr;   // tile alignment: pyramids and block vectors
   size_t align_ws_bytes = 0;
+  void* sum_ws = nullptr;     // frame sums for the SNR-dependent tuning
+  size_t sum_ws_bytes = 0;
   hipStream_t capture_stream = nullptr;
   BatchPlan plan;
 };
@@ -78,6 +80,8 @@ hmfsr_status workspace(int dev, size_t bytes, hipStream_t stream, void** out);  
 hmfsr_status bwd_workspace(int dev, size_t bytes, hipStream_t stream, void** out);  // caller holds g_mutex
 hmfsr_status stream_workspace(int dev, size_t bytes, hipStream_t stream, void** out);  // caller holds g_mutex
 hmfsr_status align_workspace(int dev, size_t bytes, hipStream_t stream, void** out);  // caller holds g_mutex
+// Grow a per-device buffer (caller holds g_mutex).
+hmfsr_status grow_buffer(void*& buf, size_t& have, size_t bytes, hipStream_t stream, void** out);
 
 // Merge tile shape for a burst: HMFSR_MERGE_VARIANT, else the autotuned
 // choice for the burst's (scale, frame count) class, else the default.

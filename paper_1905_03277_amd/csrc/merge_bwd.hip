@@ -33,6 +33,7 @@
 
 #include "device_util.h"
 #include "hmfsr_internal.h"
+#include "noise.h"
 #include "merge_common.h"
 #include "omega.h"
 #include "prior.h"
@@ -742,9 +743,9 @@ __global__ __launch_bounds__(64, 4) void k_robust_bwd(const uint16_t* __restrict
           float den = 0.f;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            float var = fmaf(rc.a_r, fmaxf(mu_ref[c] - rc.black, 0.f), rc.b_r);
-            if (c == 1) var *= 0.5f;
-            den += fmaxf(var_ref[c], var);
+            float sig2, dmd2;
+            noise_md(rc, mu_ref[c], c, sig2, dmd2);
+            den += fmaxf(var_ref[c], sig2);
           }
           // mu_w: frame n's box mean sampled bilinearly at (j, i) + v / 2
           const double hx = (double)j + (double)vx * 0.5, hy = (double)i + (double)vy * 0.5;
@@ -776,9 +777,8 @@ __global__ __launch_bounds__(64, 4) void k_robust_bwd(const uint16_t* __restrict
             const float mu_w = fmaf(fy, bot[c] - top[c], top[c]);
             dmx[c] = fmaf(fy, dbot[c] - dtop[c], dtop[c]);
             dmy[c] = bot[c] - top[c];
-            float var = fmaf(rc.a_r, fmaxf(mu_ref[c] - rc.black, 0.f), rc.b_r);
-            if (c == 1) var *= 0.5f;
-            const float dmd2 = var * (2.f / 9.f);
+            float sig2, dmd2;
+            noise_md(rc, mu_ref[c], c, sig2, dmd2);
             const float dms = mu_ref[c] - mu_w, dms2 = dms * dms;
             const float q = 1.f / (dms2 + dmd2);
             dd[c] = dms * dms2 * q;  // eq. (6) shrinkage

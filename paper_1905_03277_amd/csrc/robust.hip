@@ -21,6 +21,7 @@
 // prior chose s1 (eq. 8), R of the aligned frame is 0.
 #include "device_util.h"
 #include "hmfsr_internal.h"
+#include "noise.h"
 
 namespace hmfsr {
 namespace {
@@ -169,10 +170,10 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
 #pragma unroll
         for (int q = 0; q < 9; ++q) var_ms = fmaf(v[q] - mu, v[q] - mu, var_ms);
         var_ms *= (1.f / 9.f);
-        // noise model in raw units at the base brightness; the guide green is
-        // the mean of two greens, so its variance is halved.
-        float var_md = fmaf(rc.a_r, fmaxf(mu - rc.black, 0.f), rc.b_r);
-        if (c == 1) var_md *= 0.5f;
+        // noise model in raw units at the base brightness (the guide green is
+        // the mean of two greens)
+        float var_md, dmd2_unused;
+        noise_md(rc, mu, c, var_md, dmd2_unused);
         sMuRef[c][k] = mu;
         den += fmaxf(var_ms, var_md);  // sigma = max(sigma_ms, sigma_md), eq. (6)
       }
@@ -403,12 +404,12 @@ __device__ __forceinline__ void robust_tile(const uint16_t* __restrict__ frames,
             const float top = fmaf(fx, m01 - m00, m00), bot = fmaf(fx, m11 - m10, m10);
             const float mu_al = fmaf(fy, bot - top, top);
             const float mu_ref = sMuRef[c][k];
-            float var = fmaf(rc.a_r, fmaxf(mu_ref - rc.black, 0.f), rc.b_r);
-            if (c == 1) var *= 0.5f;
+            float sig2, dmd2;
+            noise_md(rc, mu_ref, c, sig2, dmd2);
             const float dms = mu_ref - mu_al;
             const float dms2 = dms * dms;
-            // Wiener shrinkage of eq. (6): d = d_ms^3 / (d_ms^2 + d_md^2), d_md^2 = 2 var / 9
-            const float dd = dms * dms2 * __builtin_amdgcn_rcpf(fmaf(var, 2.f / 9.f, dms2));
+            // Wiener shrinkage of eq. (6): d = d_ms^3 / (d_ms^2 + d_md^2)
+            const float dd = dms * dms2 * __builtin_amdgcn_rcpf(dms2 + dmd2);
             num = fmaf(dd, dd, num);
           }
           const float R = sS[kt] * __expf(-num * sInvDen[k]) - rc.t;  // eq. (5)

@@ -82,6 +82,40 @@ def align(frames: torch.Tensor, desc, params=None, motion: torch.Tensor | None =
     return (motion, bm) if block_match else motion
 
 
+def noise_table(desc, device, bins: int = 64, patches: int = 4096, seed: int = 0) -> torch.Tensor:
+    """Monte-Carlo noise table float32 [bins][4] for the descriptor's noise
+    model and raw range (Sec. 5.2.2); set it as ``desc.noise_table``."""
+    table = torch.empty((bins, 4), dtype=torch.float32, device=device)
+    with torch.cuda.device(table.device):
+        plain = dataclass_replace_table(desc, None)
+        binding.hmfsr_noise_table(binding.make_desc(plain), bins, patches, seed, table.data_ptr(),
+                                  _stream(table.device))
+    return table
+
+
+def dataclass_replace_table(desc, table):
+    """A copy of ``desc`` with another noise table (descriptors with a
+    ``replace`` method, else the same object when no table is involved)."""
+    if hasattr(desc, "replace"):
+        return desc.replace(noise_table=table)
+    if getattr(desc, "noise_table", None) is not None:
+        raise ValueError("descriptor has a noise table but no replace()")
+    return desc
+
+
+def auto_tuning(frames: torch.Tensor, desc):
+    """SNR-dependent tuning of the burst (Sec. 7.2, S.2): returns
+    (synth.Tuning, suggested tile size, SNR)."""
+    from .synth import Tuning
+    if not frames.is_cuda:
+        raise ValueError("frames must be a device tensor (no CPU path exists)")
+    with torch.cuda.device(frames.device):
+        tun, tile, snr = binding.hmfsr_auto_tuning(binding.make_desc(desc), frames.data_ptr(),
+                                                   _stream(frames.device))
+    vals = {f: getattr(tun, f) for f, _ in binding.hmfsr_tuning._fields_}
+    return Tuning(**vals), tile, snr
+
+
 def merge_raw(frames: torch.Tensor, desc, tuning, params=None) -> torch.Tensor:
     """Raw burst to RGB: ``align`` then ``merge``."""
     return merge(frames, align(frames, desc, params), desc, tuning)

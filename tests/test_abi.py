@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version_and_strerror():
-    assert binding.hmfsr_version() == 130
+    assert binding.hmfsr_version() == 140
     assert "INVALID" in binding.strerror(binding.HMFSR_E_INVALID)
     assert "unknown" in binding.strerror(-99)
 
@@ -159,3 +159,36 @@ def test_align_validates_descriptor_and_pointers():
         bad = binding.make_align_params({"levels": 0})
         binding.hmfsr_align(desc, bad, 8, 8)
     assert binding.make_align_params({"lk_iterations": 5}).lk_iterations == 5
+
+
+def test_noise_table_fields_validated():
+    desc, tun = _good()
+    desc.noise_bins = 4                      # bins without a table
+    assert _call(desc, tun) == binding.HMFSR_E_INVALID
+    desc, tun = _good()
+    desc.noise_table = 8
+    desc.noise_bins = 1                      # too few bins
+    assert _call(desc, tun) == binding.HMFSR_E_INVALID
+    desc.noise_bins = 70000
+    assert _call(desc, tun) == binding.HMFSR_E_INVALID
+    desc.noise_bins = 16
+    desc.noise_table = 6                     # not 4-byte aligned
+    assert _call(desc, tun) == binding.HMFSR_E_INVALID
+
+
+def test_noise_table_and_auto_tuning_validate_on_the_host():
+    L = binding.lib()
+    desc, _ = _good()
+    for bins, patches, table in ((1, 16, 8), (65537, 16, 8), (8, 0, 8), (8, 1 << 25, 8), (8, 16, None), (8, 16, 2)):
+        assert L.hmfsr_noise_table(ctypes.byref(desc), bins, patches, 0, table, None) == binding.HMFSR_E_INVALID
+    t = binding.hmfsr_tuning()
+    assert L.hmfsr_auto_tuning(ctypes.byref(desc), None, ctypes.byref(t), None, None, None) == binding.HMFSR_E_INVALID
+    assert L.hmfsr_auto_tuning(ctypes.byref(desc), 8, None, None, None, None) == binding.HMFSR_E_INVALID
+    bad, _ = _good()
+    bad.height = 63
+    assert L.hmfsr_auto_tuning(ctypes.byref(bad), 8, ctypes.byref(t), None, None, None) == binding.HMFSR_E_INVALID
+
+
+def test_desc_struct_has_no_padding():
+    # the batch graph compares descriptors with memcmp
+    assert ctypes.sizeof(binding.hmfsr_desc) == 14 * 4 + 8
