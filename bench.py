@@ -302,6 +302,39 @@ def bench_hf(burst, out, reps: int = 10) -> dict:
     return res
 
 
+def bench_noise(burst, out, reps: int = 10) -> dict:
+    """Noise model: the Monte-Carlo table (64 bins x 4096 patches), the
+    12 MP x 8 merge reading it, and the SNR-dependent tuning of the burst."""
+    import torch
+    from paper_1905_03277_amd import binding, torch_ops
+
+    d = burst.desc
+    stream = torch.cuda.current_stream()
+    table = torch_ops.noise_table(d, burst.frames.device, bins=64, patches=4096)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        torch_ops.noise_table(d, burst.frames.device, bins=64, patches=4096)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_table = e0.elapsed_time(e1) / reps
+    dt = d.replace(noise_table=table)
+    torch_ops.merge(burst.frames, burst.motion, dt, burst.tuning, out=out)
+    binding.hmfsr_profile_begin()
+    for _ in range(reps):
+        torch_ops.merge(burst.frames, burst.motion, dt, burst.tuning, out=out)
+    st = binding.hmfsr_profile_end()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        tun, tile, snr = torch_ops.auto_tuning(burst.frames, d)
+    ms_tune = (time.perf_counter() - t0) * 1e3 / reps
+    return {"table_ms": round(ms_table, 3), "table": "64 bins x 4096 patches x 2 frames x 9 guide px",
+            "merge_with_table_kernels_ms": {k: round(tot / max(cnt, 1), 4) for k, (tot, cnt) in st.items() if cnt},
+            "auto_tuning_ms_host_clock": round(ms_tune, 3), "snr": round(snr, 2), "suggested_tile": tile,
+            "k_detail": round(tun.k_detail, 4)}
+
+
 def bench_grad(dev, reps: int = 3) -> dict:
     """The differentiation workload: 16 bursts of 8 x 768 x 1024 RGGB at scale 2.
     One pass = for every burst, the forward merge (keeping the normaliser of
@@ -460,6 +493,7 @@ def main():
     if not args.no_align:
         line["alignment"] = bench_align(burst, out)
         line["hf_rejection"] = bench_hf(burst, out)
+        line["noise_model"] = bench_noise(burst, out)
     if not args.no_batch:
         line["batched"] = bench_batch(dev)
     if not args.no_grad:
