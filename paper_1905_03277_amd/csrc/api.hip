@@ -258,7 +258,7 @@ hmfsr_status run_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, const
   if (timed(HMFSR_STAGE_PRIOR, s, [&] { return launch_prior(g, pc, motion, w.s_tile, s); }) != hipSuccess)
     return HMFSR_E_HIP;
   if (timed(HMFSR_STAGE_ROBUST, s, [&] {
-        return launch_robust(g, rc, frames, motion, w.s_tile, w.rmin, nullptr, s);
+        return launch_robust(g, rc, frames, motion, w, w.rmin, nullptr, s);
       }) != hipSuccess)
     return HMFSR_E_HIP;
   if (timed(HMFSR_STAGE_MERGE, s, [&] {
@@ -344,7 +344,7 @@ hmfsr_status hmfsr_stream_add(const hmfsr_desc* desc, const hmfsr_tuning* tuning
   const MergeConsts mc = make_merge(desc, tuning, g);
   if (timed(HMFSR_STAGE_PRIOR, s, [&] { return launch_prior(g, pc, mo, w.s_tile, s); }) != hipSuccess ||
       timed(HMFSR_STAGE_ROBUST, s, [&] {
-        return launch_robust(g, rc, frames, mo, w.s_tile, w.rmin, nullptr, s);
+        return launch_robust(g, rc, frames, mo, w, w.rmin, nullptr, s);
       }) != hipSuccess ||
       timed(HMFSR_STAGE_MERGE, s, [&] {
         return launch_merge_stream(g, mc, frames, mo, w.rmin, state, state, 1, s);
@@ -402,7 +402,7 @@ hmfsr_status hmfsr_merge_backward(const hmfsr_desc* desc, const hmfsr_tuning* tu
   if (timed(HMFSR_STAGE_PRIOR, s, [&] { return launch_prior(g, pc, motion, w.fwd.s_tile, s); }) != hipSuccess)
     return HMFSR_E_HIP;
   if (timed(HMFSR_STAGE_ROBUST, s, [&] {
-        return launch_robust(g, rc, frames, motion, w.fwd.s_tile, w.fwd.rmin, w.rmap, s);
+        return launch_robust(g, rc, frames, motion, w.fwd, w.fwd.rmin, w.rmap, s);
       }) != hipSuccess)
     return HMFSR_E_HIP;
   if (need_saved) {
@@ -447,7 +447,7 @@ hmfsr_status hmfsr_merge_maps(const hmfsr_desc* desc, const hmfsr_tuning* tuning
     return HMFSR_E_HIP;
   if (launch_prior(g, make_prior(tuning), motion, w.s_tile, s) != hipSuccess) return HMFSR_E_HIP;
   float* rmin = robust_min ? robust_min : w.rmin;
-  if (launch_robust(g, make_robust(desc, tuning), frames, motion, w.s_tile, rmin, robust, s) !=
+  if (launch_robust(g, make_robust(desc, tuning), frames, motion, w, rmin, robust, s) !=
       hipSuccess)
     return HMFSR_E_HIP;
   // the base frame's robustness is 1 by definition

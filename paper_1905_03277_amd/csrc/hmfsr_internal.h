@@ -56,6 +56,8 @@ struct BurstArgs {
   float* out;
   float* s_tile;  // workspace [n][TY][TX]
   float* rmin;    // workspace [n][h][w]
+  float* gmu;     // workspace [n][3][h][w]
+  float* gref;    // workspace [h][w]
   Geometry g;
   MergeConsts mc;
   RobustConsts rc;
@@ -70,18 +72,23 @@ struct WorkItem {
   int tile;  // row-major tile index within the burst
 };
 
-// Workspace of the merge: per-(frame, tile) rejection strength and R_hat.
+// Workspace of the merge: per-(frame, tile) rejection strength, R_hat, and
+// the robustness's guide statistics.
 struct Work {
   float* s_tile;  // [n][TY][TX]
   float* rmin;    // [n][h][w]
+  float* gmu;     // [n][3][h][w] 3x3 box means of every frame's guide (raw units)
+  float* gref;    // [h][w] base frame: 1 / sum_c sigma_c^2 of eq. (5)-(6), negated where S.3 finds a loss
 };
 size_t work_bytes(const Geometry& g);
 Work work_carve(void* base, const Geometry& g);
 
 hipError_t launch_prior(const Geometry& g, const PriorConsts& pc, const float* motion, float* s_tile,
                         hipStream_t stream);
+// Guide statistics into w.gmu / w.gref, then R_hat into rmin (and R into
+// robust, nullable); reads w.s_tile.
 hipError_t launch_robust(const Geometry& g, const RobustConsts& rc, const uint16_t* frames,
-                         const float* motion, const float* s_tile, float* rmin, float* robust,
+                         const float* motion, const Work& w, float* rmin, float* robust,
                          hipStream_t stream);
 // Compiled tile shapes of the merge kernel (64 columns x rows, threads).
 struct MergeVariant {
@@ -101,6 +108,11 @@ hipError_t launch_merge_batch(int variant, const BurstArgs* bursts, const WorkIt
                               int* counter, int n_groups, hipStream_t stream);
 hipError_t launch_robust_batch(const BurstArgs* bursts, const WorkItem* items, int n_items,
                                int* counter, int n_groups, hipStream_t stream);
+// Guide statistics of every burst of a batch: workgroup i belongs to the last
+// burst b with first[b] <= i (first[b] = the workgroups of the bursts before b).
+hipError_t launch_guide_means_batch(const BurstArgs* bursts, const int* first, int n_bursts, int total,
+                                    hipStream_t stream);
+int guide_means_groups(const Geometry& g);
 hipError_t launch_prior_batch(const BurstArgs* bursts, const int* first, int n_bursts, int total,
                               hipStream_t stream);
 int merge_tile_rows(int variant);

@@ -94,15 +94,27 @@ hipError_t launch_fill(float* p, float v, size_t n, hipStream_t stream) {
   return hipGetLastError();
 }
 
+namespace {
+size_t a256(size_t b) { return (b + 255) / 256 * 256; }
+}  // namespace
+
 size_t work_bytes(const Geometry& g) {
-  return ((size_t)g.TY * g.TX * g.n * sizeof(float) + 255) / 256 * 256 +
-         (size_t)g.h * g.w * g.n * sizeof(float) + 256;
+  const size_t plane = (size_t)g.h * g.w * sizeof(float);
+  return a256((size_t)g.TY * g.TX * g.n * sizeof(float)) + a256(plane * g.n) + a256(plane * 3 * g.n) +
+         a256(plane);
 }
 
 Work work_carve(void* base, const Geometry& g) {
+  const size_t plane = (size_t)g.h * g.w * sizeof(float);
+  char* p = (char*)base;
   Work w;
-  w.s_tile = (float*)base;
-  w.rmin = (float*)((char*)base + ((size_t)g.TY * g.TX * g.n * sizeof(float) + 255) / 256 * 256);
+  w.s_tile = (float*)p;
+  p += a256((size_t)g.TY * g.TX * g.n * sizeof(float));
+  w.rmin = (float*)p;
+  p += a256(plane * g.n);
+  w.gmu = (float*)p;
+  p += a256(plane * 3 * g.n);
+  w.gref = (float*)p;
   return w;
 }
 
