@@ -129,7 +129,6 @@ RobustConsts make_robust(const hmfsr_desc* d, const hmfsr_tuning* t) {
   r.b_r = (float)((double)d->noise_b * range * range);
   r.t = t->t;
   r.hf = t->hf_ratio;
-  r.m_th = t->m_th;
   r.ntab = d->noise_table;
   r.nbins = d->noise_bins;
   r.inv_range = (float)(1.0 / range);
@@ -255,7 +254,7 @@ hmfsr_status run_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, const
   const PriorConsts pc = make_prior(tuning);
   const RobustConsts rc = make_robust(desc, tuning);
   const MergeConsts mc = make_merge(desc, tuning, g);
-  if (timed(HMFSR_STAGE_PRIOR, s, [&] { return launch_prior(g, pc, motion, w.s_tile, s); }) != hipSuccess)
+  if (timed(HMFSR_STAGE_PRIOR, s, [&] { return launch_prior(g, pc, motion, w, s); }) != hipSuccess)
     return HMFSR_E_HIP;
   if (timed(HMFSR_STAGE_ROBUST, s, [&] {
         return launch_robust(g, rc, frames, motion, w, w.rmin, nullptr, s);
@@ -342,7 +341,7 @@ hmfsr_status hmfsr_stream_add(const hmfsr_desc* desc, const hmfsr_tuning* tuning
   const PriorConsts pc = make_prior(tuning);
   const RobustConsts rc = make_robust(desc, tuning);
   const MergeConsts mc = make_merge(desc, tuning, g);
-  if (timed(HMFSR_STAGE_PRIOR, s, [&] { return launch_prior(g, pc, mo, w.s_tile, s); }) != hipSuccess ||
+  if (timed(HMFSR_STAGE_PRIOR, s, [&] { return launch_prior(g, pc, mo, w, s); }) != hipSuccess ||
       timed(HMFSR_STAGE_ROBUST, s, [&] {
         return launch_robust(g, rc, frames, mo, w, w.rmin, nullptr, s);
       }) != hipSuccess ||
@@ -399,7 +398,7 @@ hmfsr_status hmfsr_merge_backward(const hmfsr_desc* desc, const hmfsr_tuning* tu
   bc.tiles_x = (g.OW + 63) / 64;
   bc.tiles_y = (g.OH + kBwdRows - 1) / kBwdRows;
   bc.n_tiles = bc.tiles_x * bc.tiles_y;
-  if (timed(HMFSR_STAGE_PRIOR, s, [&] { return launch_prior(g, pc, motion, w.fwd.s_tile, s); }) != hipSuccess)
+  if (timed(HMFSR_STAGE_PRIOR, s, [&] { return launch_prior(g, pc, motion, w.fwd, s); }) != hipSuccess)
     return HMFSR_E_HIP;
   if (timed(HMFSR_STAGE_ROBUST, s, [&] {
         return launch_robust(g, rc, frames, motion, w.fwd, w.fwd.rmin, w.rmap, s);
@@ -445,7 +444,7 @@ hmfsr_status hmfsr_merge_maps(const hmfsr_desc* desc, const hmfsr_tuning* tuning
   const size_t plane = (size_t)g.h * g.w;
   if (omega && launch_omega_map(g, make_omega(desc, tuning), frames, omega, s) != hipSuccess)
     return HMFSR_E_HIP;
-  if (launch_prior(g, make_prior(tuning), motion, w.s_tile, s) != hipSuccess) return HMFSR_E_HIP;
+  if (launch_prior(g, make_prior(tuning), motion, w, s) != hipSuccess) return HMFSR_E_HIP;
   float* rmin = robust_min ? robust_min : w.rmin;
   if (launch_robust(g, make_robust(desc, tuning), frames, motion, w, rmin, robust, s) !=
       hipSuccess)

@@ -72,7 +72,7 @@ void tune_save() {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t counters = 0, args = 0, first = 0, mfirst = 0, ritems = 0, mitems = 0, work = 0, total = 0;
+  size_t counters = 0, args = 0, first = 0, bfirst = 0, ffirst = 0, ritems = 0, mitems = 0, work = 0, total = 0;
   std::vector<size_t> burst_work;  // offset of each burst's Work inside the workspace
 };
 
@@ -166,7 +166,7 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
   std::vector<int> var(n_bursts), mtx(n_bursts), mtiles(n_bursts), rtiles(n_bursts);
   std::vector<double> cost(n_bursts);
   Layout L;
-  size_t n_prior = 0, n_means = 0, n_ritems = 0, n_mitems = 0;
+  size_t n_prior = 0, n_base = 0, n_fmeans = 0, n_ritems = 0, n_mitems = 0;
   for (int i = 0; i < n_bursts; ++i) {
     geo[i] = make_geometry(&descs[i]);
     var[i] = merge_variant(geo[i]);
@@ -176,17 +176,19 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
     rtiles[i] = geo[i].n > 1 ? robust_tiles_x(geo[i]) * robust_tiles_y(geo[i]) : 0;
     cost[i] = (double)geo[i].n * geo[i].OH * geo[i].OW;
     n_prior += (size_t)geo[i].n * geo[i].TY * geo[i].TX;
-    n_means += (size_t)guide_means_groups(geo[i]);
+    n_base += (size_t)base_stats_groups(geo[i]);
+    n_fmeans += (size_t)frame_means_groups(geo[i]);
     n_ritems += rtiles[i];
     n_mitems += mtiles[i];
   }
-  if (n_prior > 0x7fffffff || n_means > 0x7fffffff || n_ritems > 0x7fffffff || n_mitems > 0x7fffffff)
+  if (n_prior > 0x7fffffff || n_base > 0x7fffffff || n_fmeans > 0x7fffffff || n_ritems > 0x7fffffff || n_mitems > 0x7fffffff)
     return HMFSR_E_INVALID;
   size_t off = 0;
   L.counters = off; off += 256;
   L.args = off; off += align256(sizeof(BurstArgs) * n_bursts);
   L.first = off; off += align256(sizeof(int) * n_bursts);
-  L.mfirst = off; off += align256(sizeof(int) * n_bursts);
+  L.bfirst = off; off += align256(sizeof(int) * n_bursts);
+  L.ffirst = off; off += align256(sizeof(int) * n_bursts);
   L.ritems = off; off += align256(sizeof(WorkItem) * n_ritems);
   L.mitems = off; off += align256(sizeof(WorkItem) * n_mitems);
   L.burst_work.resize(n_bursts);
@@ -222,6 +224,7 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
     a.motion = motion[i];
     a.out = out[i];
     a.s_tile = w.s_tile;
+    a.mov = w.mov;
     a.rmin = w.rmin;
     a.gmu = w.gmu;
     a.gref = w.gref;
@@ -278,14 +281,16 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
         for (int t = 0; t < mtiles[i]; ++t) mitems.push_back({i, t});
   }
   group_start[kNumMergeVariants] = (int)mitems.size();
-  std::vector<int> first(n_bursts), mfirst(n_bursts);
+  std::vector<int> first(n_bursts), bfirst(n_bursts), ffirst(n_bursts);
   {
-    size_t acc = 0, macc = 0;
+    size_t acc = 0, bacc = 0, facc = 0;
     for (int i = 0; i < n_bursts; ++i) {
       first[i] = (int)acc;
       acc += (size_t)geo[i].n * geo[i].TY * geo[i].TX;
-      mfirst[i] = (int)macc;
-      macc += (size_t)guide_means_groups(geo[i]);
+      bfirst[i] = (int)bacc;
+      bacc += (size_t)base_stats_groups(geo[i]);
+      ffirst[i] = (int)facc;
+      facc += (size_t)frame_means_groups(geo[i]);
     }
   }
 
@@ -297,7 +302,8 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
   if (hipMemcpy(base + L.args, args.data(), sizeof(BurstArgs) * n_bursts, hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemcpy(base + L.first, first.data(), sizeof(int) * n_bursts, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(base + L.mfirst, mfirst.data(), sizeof(int) * n_bursts, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(base + L.bfirst, bfirst.data(), sizeof(int) * n_bursts, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(base + L.ffirst, ffirst.data(), sizeof(int) * n_bursts, hipMemcpyHostToDevice) != hipSuccess ||
       (n_ritems && hipMemcpy(base + L.ritems, ritems.data(), sizeof(WorkItem) * n_ritems,
                              hipMemcpyHostToDevice) != hipSuccess) ||
       hipMemcpy(base + L.mitems, mitems.data(), sizeof(WorkItem) * n_mitems, hipMemcpyHostToDevice) !=
@@ -308,7 +314,8 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
 
   const BurstArgs* d_args = (const BurstArgs*)(base + L.args);
   const int* d_first = (const int*)(base + L.first);
-  const int* d_mfirst = (const int*)(base + L.mfirst);
+  const int* d_bfirst = (const int*)(base + L.bfirst);
+  const int* d_ffirst = (const int*)(base + L.ffirst);
   const WorkItem* d_ritems = (const WorkItem*)(base + L.ritems);
   const WorkItem* d_mitems = (const WorkItem*)(base + L.mitems);
   int* d_counters = (int*)(base + L.counters);  // [0] robustness, [1 + v] merge shape v
@@ -318,7 +325,8 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return HMFSR_E_HIP;
   hipError_t err = launch_fill_i32(d_counters, 0, 1 + kNumMergeVariants, cs);
   if (err == hipSuccess) err = launch_prior_batch(d_args, d_first, n_bursts, (int)n_prior, cs);
-  if (err == hipSuccess) err = launch_guide_means_batch(d_args, d_mfirst, n_bursts, (int)n_means, cs);
+  if (err == hipSuccess)
+    err = launch_guide_stats_batch(d_args, d_bfirst, (int)n_base, d_ffirst, (int)n_fmeans, n_bursts, cs);
   if (err == hipSuccess && n_ritems) {
     const int groups = (int)std::min<size_t>(n_ritems, (size_t)cus * robust_batch_blocks_per_cu());
     err = launch_robust_batch(d_args, d_ritems, (int)n_ritems, d_counters, groups, cs);

@@ -35,7 +35,6 @@ struct RobustConsts {
   float b_r;  // noise_b * range^2
   float t;
   double hf;    // S.3 variance-loss threshold; 0 turns the rejection off
-  double m_th;  // the motion prior's threshold, for the S.3 test's tile decision
   const float* ntab;  // Monte-Carlo noise table [nbins][4] (normalised units), or null
   int nbins;
   float inv_range;    // 1 / (white - black)
@@ -55,8 +54,9 @@ struct BurstArgs {
   const float* motion;
   float* out;
   float* s_tile;  // workspace [n][TY][TX]
+  unsigned char* mov;  // workspace [n][TY][TX]
   float* rmin;    // workspace [n][h][w]
-  float* gmu;     // workspace [n][3][h][w]
+  float* gmu;     // workspace [n][3][h][w + 2]
   float* gref;    // workspace [h][w]
   Geometry g;
   MergeConsts mc;
@@ -76,14 +76,17 @@ struct WorkItem {
 // the robustness's guide statistics.
 struct Work {
   float* s_tile;  // [n][TY][TX]
+  unsigned char* mov;  // [n][TY][TX] 1 where the motion prior chose s1 (eq. 8)
   float* rmin;    // [n][h][w]
-  float* gmu;     // [n][3][h][w] 3x3 box means of every frame's guide (raw units)
+  float* gmu;     // [n][3][h][w + 2] 3x3 box means of every frame's guide (raw units), a
+                  // replicated edge column on either side (column Q at Q + 1)
   float* gref;    // [h][w] base frame: 1 / sum_c sigma_c^2 of eq. (5)-(6), negated where S.3 finds a loss
 };
 size_t work_bytes(const Geometry& g);
 Work work_carve(void* base, const Geometry& g);
 
-hipError_t launch_prior(const Geometry& g, const PriorConsts& pc, const float* motion, float* s_tile,
+// Rejection strength into w.s_tile and the prior's choice into w.mov.
+hipError_t launch_prior(const Geometry& g, const PriorConsts& pc, const float* motion, const Work& w,
                         hipStream_t stream);
 // Guide statistics into w.gmu / w.gref, then R_hat into rmin (and R into
 // robust, nullable); reads w.s_tile.
@@ -108,11 +111,13 @@ hipError_t launch_merge_batch(int variant, const BurstArgs* bursts, const WorkIt
                               int* counter, int n_groups, hipStream_t stream);
 hipError_t launch_robust_batch(const BurstArgs* bursts, const WorkItem* items, int n_items,
                                int* counter, int n_groups, hipStream_t stream);
-// Guide statistics of every burst of a batch: workgroup i belongs to the last
-// burst b with first[b] <= i (first[b] = the workgroups of the bursts before b).
-hipError_t launch_guide_means_batch(const BurstArgs* bursts, const int* first, int n_bursts, int total,
-                                    hipStream_t stream);
-int guide_means_groups(const Geometry& g);
+// Guide statistics of every burst of a batch, the base frames' and the aligned
+// frames' in two flat launches: workgroup i belongs to the last burst b with
+// first[b] <= i (first[b] = the workgroups of the bursts before b).
+hipError_t launch_guide_stats_batch(const BurstArgs* bursts, const int* base_first, int base_total,
+                                    const int* frame_first, int frame_total, int n_bursts, hipStream_t stream);
+int base_stats_groups(const Geometry& g);
+int frame_means_groups(const Geometry& g);
 hipError_t launch_prior_batch(const BurstArgs* bursts, const int* first, int n_bursts, int total,
                               hipStream_t stream);
 int merge_tile_rows(int variant);

@@ -11,22 +11,25 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 
 // eq. (7)-(8): rejection strength s1 or s2 per tile.
 __device__ __forceinline__ void prior_one(const float* __restrict__ motion, const Geometry& g,
-                                          const PriorConsts& pc, float* __restrict__ s_tile, int n,
-                                          int ty, int tx) {
+                                          const PriorConsts& pc, float* __restrict__ s_tile,
+                                          unsigned char* __restrict__ mov, int n, int ty, int tx) {
   const size_t idx = ((size_t)n * g.TY + ty) * g.TX + tx;
   if (n == g.ref) {
     s_tile[idx] = 0.0f;
+    mov[idx] = 0;
     return;
   }
-  s_tile[idx] = prior_moving(motion, g, pc.m_th, n, ty, tx) ? pc.s1 : pc.s2;
+  const bool moving = prior_moving(motion, g, pc.m_th, n, ty, tx);
+  s_tile[idx] = moving ? pc.s1 : pc.s2;
+  mov[idx] = moving;
 }
 
 __global__ void k_prior(const float* __restrict__ motion, Geometry g, PriorConsts pc,
-                        float* __restrict__ s_tile) {
+                        float* __restrict__ s_tile, unsigned char* __restrict__ mov) {
   const int tx = blockIdx.x * blockDim.x + threadIdx.x;
   const int ty = blockIdx.y * blockDim.y + threadIdx.y;
   if (ty >= g.TY || tx >= g.TX) return;
-  prior_one(motion, g, pc, s_tile, blockIdx.z, ty, tx);
+  prior_one(motion, g, pc, s_tile, mov, blockIdx.z, ty, tx);
 }
 
 // Every (burst, frame, tile) of a batch; first[b] = first flat index of burst b.
@@ -43,7 +46,7 @@ __global__ void k_prior_batch(const BurstArgs* __restrict__ bursts, const int* _
   const int k = i - first[lo];
   const int per = b.g.TY * b.g.TX;
   const int n = k / per, t = k - n * per;
-  prior_one(b.motion, b.g, b.pc, b.s_tile, n, t / b.g.TX, t % b.g.TX);
+  prior_one(b.motion, b.g, b.pc, b.s_tile, b.mov, n, t / b.g.TX, t % b.g.TX);
 }
 
 // Omega per half-res pixel of every frame (inspection output).
@@ -100,8 +103,9 @@ size_t a256(size_t b) { return (b + 255) / 256 * 256; }
 
 size_t work_bytes(const Geometry& g) {
   const size_t plane = (size_t)g.h * g.w * sizeof(float);
-  return a256((size_t)g.TY * g.TX * g.n * sizeof(float)) + a256(plane * g.n) + a256(plane * 3 * g.n) +
-         a256(plane);
+  const size_t mu_plane = (size_t)g.h * (g.w + 2) * sizeof(float);
+  return a256((size_t)g.TY * g.TX * g.n * sizeof(float)) + a256((size_t)g.TY * g.TX * g.n) +
+         a256(plane * g.n) + a256(mu_plane * 3 * g.n) + a256(plane);
 }
 
 Work work_carve(void* base, const Geometry& g) {
@@ -110,19 +114,21 @@ Work work_carve(void* base, const Geometry& g) {
   Work w;
   w.s_tile = (float*)p;
   p += a256((size_t)g.TY * g.TX * g.n * sizeof(float));
+  w.mov = (unsigned char*)p;
+  p += a256((size_t)g.TY * g.TX * g.n);
   w.rmin = (float*)p;
   p += a256(plane * g.n);
   w.gmu = (float*)p;
-  p += a256(plane * 3 * g.n);
+  p += a256((size_t)g.h * (g.w + 2) * sizeof(float) * 3 * g.n);
   w.gref = (float*)p;
   return w;
 }
 
-hipError_t launch_prior(const Geometry& g, const PriorConsts& pc, const float* motion, float* s_tile,
+hipError_t launch_prior(const Geometry& g, const PriorConsts& pc, const float* motion, const Work& w,
                         hipStream_t stream) {
   const dim3 blk(16, 16);
   const dim3 grid((g.TX + 15) / 16, (g.TY + 15) / 16, g.n);
-  hipLaunchKernelGGL(k_prior, grid, blk, 0, stream, motion, g, pc, s_tile);
+  hipLaunchKernelGGL(k_prior, grid, blk, 0, stream, motion, g, pc, w.s_tile, w.mov);
   return hipGetLastError();
 }
 

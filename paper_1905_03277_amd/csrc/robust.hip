@@ -3,16 +3,21 @@
 // (eq. 7-8, precomputed per tile) and the 5x5 minimum (eq. 9).
 //
 // Two passes:
-//  * k_guide_means: the 3x3 box means of every frame's guide (R, mean G, B;
-//    edge-replicated) into a map [n][3][h][w]; for the base frame also the
-//    reciprocal of the noise-corrected variance sum of eq. (5)-(6) into
-//    [h][w], negated where the S.3 test below finds a variance loss.
-//  * k_robust: one workgroup per (32x16 tile of the base half-res grid,
-//    aligned frame). R is evaluated on the tile plus a 2-pixel border (the
-//    min-pool footprint; border pixels outside the grid repeat the edge pixel,
-//    which is what the edge-clamped 5x5 minimum reads) by sampling the frame's
-//    mean map bilinearly at u + v/2 (corners clamped to the map), then the
-//    5x5 minimum in LDS. Any displacement field costs the same.
+//  * guide statistics: k_frame_means writes the 3x3 box means of every
+//    aligned frame's guide (R, mean G, B; edge-replicated) into a map
+//    [n][3][h][w + 2] (the edge columns repeated once on either side, so that
+//    the two horizontal bilinear corners are adjacent whatever the clamping),
+//    one wave walking down a 62-column strip with the row sums in registers;
+//    k_base_stats writes the base frame's means and the reciprocal of its
+//    noise-corrected variance sum of eq. (5)-(6) into [h][w], negated where
+//    the S.3 test below finds a variance loss.
+//  * k_robust: one workgroup per 32x16 tile of the base half-res grid, the
+//    aligned frames in turn (the base statistics stay in registers). R is
+//    evaluated on the tile plus a 2-pixel border (the min-pool footprint;
+//    border pixels outside the grid repeat the edge pixel, which is what the
+//    edge-clamped 5x5 minimum reads) by sampling the frame's mean map
+//    bilinearly at u + v/2 (corners clamped to the map), then the 5x5 minimum
+//    in LDS.
 //
 // Colour statistics are kept in raw units (the black level enters only the
 // noise model's brightness): the ratio d^2 / sigma^2 of eq. (5) is scale-free.
@@ -35,7 +40,7 @@ constexpr int RR_W = RB_W + 4, RR_H = RB_H + 4;  // robustness region incl. the 
 constexpr int RR_N = RR_W * RR_H;
 constexpr int TT_X = RR_W / 4 + 2, TT_Y = RR_H / 4 + 2;  // alignment tiles spanned (T >= 8)
 constexpr int THREADS = 256;
-constexpr int GM_W = 64, GM_H = 16;              // guide-means tile (half-res px)
+constexpr int GM_W = 64, GM_H = 16;              // base-statistics tile (half-res px)
 constexpr int GW_W = GM_W + 4, GW_H = GM_H + 4;  // its guide window: two rings, edge-replicated
 constexpr int GW_N = GW_W * GW_H;
 
@@ -60,24 +65,129 @@ __host__ __device__ __forceinline__ int robust_tiles_y_(const Geometry& g) { ret
 __host__ __device__ __forceinline__ int means_tiles_x(const Geometry& g) { return (g.w + GM_W - 1) / GM_W; }
 __host__ __device__ __forceinline__ int means_tiles_y(const Geometry& g) { return (g.h + GM_H - 1) / GM_H; }
 
-// ---- pass 1: guide statistics ------------------------------------------------------
-struct MeansSmem {
+// Row stride of the mean maps: column Q of row P at P * mu_stride + Q + 1,
+// columns -1 and w repeating columns 0 and w - 1.
+__device__ __forceinline__ int mu_stride(const Geometry& g) { return g.w + 2; }
+
+// Raw buffer resource over one mean-map plane (word 3 as for gfx9 raw
+// buffers); a plane holds at most 16384 x 16386 floats, below 2^31 bytes.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* p, size_t floats) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, 0, (int)(floats * 4), 0x00020000);
+}
+
+// Two consecutive floats at byte offset off (one dwordx2 load).
+__device__ __forceinline__ float2 ld_pair(__amdgpu_buffer_rsrc_t r, int off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
+}
+
+// Last burst b with first[b] <= i.
+__device__ __forceinline__ int burst_of(const int* __restrict__ first, int n_bursts, int i) {
+  int lo = 0, hi = n_bursts - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---- pass 1a: the aligned frames' guide means --------------------------------------
+// One wave per 62 x 16 block of half-res pixels: lane l holds guide column
+// strip * 62 - 1 + l (clamped), so lanes 1 .. 62 have both neighbours in the
+// wave; the wave walks down the rows keeping the last two row sums.
+constexpr int FM_COLS = 62, FM_ROWS = 16, FM_WAVES = THREADS / 64;
+
+__host__ __device__ __forceinline__ int fm_strips(const Geometry& g) { return (g.w + FM_COLS - 1) / FM_COLS; }
+__host__ __device__ __forceinline__ int fm_bands(const Geometry& g) {
+  return (g.h + FM_ROWS * FM_WAVES - 1) / (FM_ROWS * FM_WAVES);
+}
+
+__device__ __forceinline__ void frame_means_block(const uint16_t* __restrict__ frames, const Geometry& g,
+                                                  float* __restrict__ gmu, int n, int strip, int band) {
+  const int lane = threadIdx.x & 63;
+  const int P0 = band * FM_ROWS;
+  if (P0 >= g.h) return;  // uniform per wave; no barrier follows
+  const int J = strip * FM_COLS - 1 + lane, Jc = clampi(J, 0, g.w - 1);
+  const bool out_ok = lane >= 1 && lane <= FM_COLS && J < g.w;
+  const uint16_t* f = frames + (size_t)n * g.H * g.W;
+  const int ws = mu_stride(g);
+  const size_t plane = (size_t)g.h * ws;
+  float* mu = gmu + (size_t)n * 3 * plane;
+  // every row's quad first, so that the loads are all in flight together
+  uint32_t top[FM_ROWS + 2], bot[FM_ROWS + 2];
+#pragma unroll
+  for (int i = 0; i < FM_ROWS + 2; ++i) {
+    const int I = clampi(P0 - 1 + i, 0, g.h - 1);
+    top[i] = *(const uint32_t*)(f + (size_t)(2 * I) * g.W + 2 * Jc);
+    bot[i] = *(const uint32_t*)(f + (size_t)(2 * I + 1) * g.W + 2 * Jc);
+  }
+  // 3x3 box mean, separable: Hs = (g(Q-1) + g(Q)) + g(Q+1), then
+  // (Hs(P-1) + Hs(P)) + Hs(P+1), times 1/9
+  float h0[3] = {0.f, 0.f, 0.f}, h1[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < FM_ROWS + 2; ++i) {
+    float v[3];
+    v[0] = (float)quad_at(top[i], bot[i], g.red_pos);
+    v[1] = (float)(quad_at(top[i], bot[i], g.green_pos[0]) + quad_at(top[i], bot[i], g.green_pos[1])) * 0.5f;
+    v[2] = (float)quad_at(top[i], bot[i], g.blue_pos);
+    float hs[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float l = __shfl_up(v[c], 1, 64), r = __shfl_down(v[c], 1, 64);
+      hs[c] = (l + v[c]) + r;
+    }
+    const int P = P0 + i - 2;  // the row whose mean is complete
+    if (i >= 2 && out_ok && P < g.h) {
+      float* row = mu + (size_t)P * ws + J + 1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float m = ((h0[c] + h1[c]) + hs[c]) * (1.f / 9.f);
+        row[(size_t)c * plane] = m;
+        if (J == 0) row[(size_t)c * plane - 1] = m;        // column -1
+        if (J == g.w - 1) row[(size_t)c * plane + 1] = m;  // column w
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      h0[c] = h1[c];
+      h1[c] = hs[c];
+    }
+  }
+}
+
+// Workgroup (strip, band of FM_WAVES blocks, aligned frame).
+__global__ __launch_bounds__(THREADS) void k_frame_means(const uint16_t* __restrict__ frames, Geometry g,
+                                                         float* __restrict__ gmu) {
+  const int n = (int)blockIdx.z < g.ref ? (int)blockIdx.z : (int)blockIdx.z + 1;
+  frame_means_block(frames, g, gmu, n, blockIdx.x, blockIdx.y * FM_WAVES + (threadIdx.x >> 6));
+}
+
+// Every (burst, aligned frame, strip, band) of a batch, one workgroup each.
+__global__ __launch_bounds__(THREADS) void k_frame_means_batch(const BurstArgs* __restrict__ bursts,
+                                                               const int* __restrict__ first, int n_bursts) {
+  const int i = blockIdx.x, bi = burst_of(first, n_bursts, i);
+  const BurstArgs& b = bursts[bi];
+  const int ns = fm_strips(b.g), per = ns * fm_bands(b.g);
+  const int k = i - first[bi], m = k / per, t = k - m * per;
+  const int n = m < b.g.ref ? m : m + 1;
+  frame_means_block(b.frames, b.g, b.gmu, n, t % ns, (t / ns) * FM_WAVES + (threadIdx.x >> 6));
+}
+
+// ---- pass 1b: the base frame's statistics ------------------------------------------
+struct BaseSmem {
   float G[3][GW_N];  // guide at rows I0-2 .. I0+GM_H+1, columns J0-2 .., clamped to the grid
-  float S[3][GW_N];  // row sums (aligned frames) or doubled 3x3 box sums (base frame, S.3)
-  int sItem;
+  float S[3][GW_N];  // doubled 3x3 box sums (S.3)
 };
 
-// One 64x16 tile (tile_x, tile_y) of frame n's mean map and, for the base
-// frame, of the reciprocal variance sum with its S.3 sign.
-__device__ __forceinline__ void guide_means_tile(const uint16_t* __restrict__ frames, const Geometry& g,
-                                                 const RobustConsts& rc, float* __restrict__ gmu,
-                                                 float* __restrict__ gref, int n, int tile_x, int tile_y,
-                                                 MeansSmem& sm) {
+// One 64x16 tile (tile_x, tile_y): the base frame's 3x3 guide means into
+// gmu[ref] and the reciprocal variance sum, with its S.3 sign, into gref.
+__device__ __forceinline__ void base_stats_tile(const uint16_t* __restrict__ frames, const Geometry& g,
+                                                const RobustConsts& rc, float* __restrict__ gmu,
+                                                float* __restrict__ gref, int tile_x, int tile_y, BaseSmem& sm) {
   const int tid = threadIdx.x;
   const int I0 = tile_y * GM_H, J0 = tile_x * GM_W;
   const int gy0 = I0 - 2, gx0 = J0 - 2;
-  const uint16_t* f = frames + (size_t)n * g.H * g.W;
-  const size_t plane = (size_t)g.h * g.w;
+  const uint16_t* f = frames + (size_t)g.ref * g.H * g.W;
   {
     const float ginv = 1.f / (float)GW_W;
     for (int k = tid; k < GW_N; k += THREADS) {
@@ -91,28 +201,6 @@ __device__ __forceinline__ void guide_means_tile(const uint16_t* __restrict__ fr
   }
   __syncthreads();
   const int oh = min(GM_H, g.h - I0), ow = min(GM_W, g.w - J0);
-  if (n != g.ref) {
-    // 3x3 box mean, separable: row sums Hs = (g(Q-1) + g(Q)) + g(Q+1) at
-    // rows I0-1 .., then (Hs(P-1) + Hs(P)) + Hs(P+1), times 1/9
-    for (int k = tid; k < (GM_H + 2) * GM_W; k += THREADS) {
-      const int r = k >> 6, j = k & (GM_W - 1);  // GM_W == 64
-      const int q = (r + 1) * GW_W + j + 1;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) sm.S[c][k] = (sm.G[c][q] + sm.G[c][q + 1]) + sm.G[c][q + 2];
-    }
-    __syncthreads();
-    for (int k = tid; k < GM_H * GM_W; k += THREADS) {
-      const int i = k >> 6, j = k & (GM_W - 1);
-      if (i >= oh || j >= ow) continue;
-      const size_t o = (size_t)(I0 + i) * g.w + J0 + j;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float* col = sm.S[c] + i * GM_W + j;
-        gmu[((size_t)n * 3 + c) * plane + o] = ((col[0] + col[GM_W]) + col[2 * GM_W]) * (1.f / 9.f);
-      }
-    }
-    return;
-  }
   if (rc.hf > 0.0) {
     // doubled 3x3 box sums at window rows and columns 1 .. GW - 2 (integers
     // below 2^24: exact in float whatever the order); the S.3 test reads them
@@ -133,10 +221,11 @@ __device__ __forceinline__ void guide_means_tile(const uint16_t* __restrict__ fr
     }
     __syncthreads();
   }
-  // base frame: 3x3 mean and population variance of the guide, noise-corrected
-  // per channel (eq. 6), the reciprocal of their sum (eq. 5)
+  // 3x3 mean and population variance of the guide, noise-corrected per
+  // channel (eq. 6), the reciprocal of their sum (eq. 5)
+  const size_t mplane = (size_t)g.h * mu_stride(g);
   for (int k = tid; k < GM_H * GM_W; k += THREADS) {
-    const int i = k >> 6, j = k & (GM_W - 1);
+    const int i = k >> 6, j = k & (GM_W - 1);  // GM_W == 64
     if (i >= oh || j >= ow) continue;
     const int P = I0 + i, Q = J0 + j;
     const int o = (i + 1) * GW_W + (j + 1);  // window position of (P - 1, Q - 1)
@@ -189,62 +278,67 @@ __device__ __forceinline__ void guide_means_tile(const uint16_t* __restrict__ fr
       }
       if (A < rc.hf * (81.0 * B)) inv = -inv;
     }
-    const size_t op = (size_t)P * g.w + Q;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) gmu[((size_t)n * 3 + c) * plane + op] = mu3[c];
-    gref[op] = inv;
+    for (int c = 0; c < 3; ++c) gmu[((size_t)g.ref * 3 + c) * mplane + (size_t)P * mu_stride(g) + Q + 1] = mu3[c];
+    gref[(size_t)P * g.w + Q] = inv;
   }
 }
 
-// Workgroup (tile, frame).
-__global__ __launch_bounds__(THREADS) void k_guide_means(const uint16_t* __restrict__ frames, Geometry g,
-                                                         RobustConsts rc, float* __restrict__ gmu,
-                                                         float* __restrict__ gref) {
-  __shared__ MeansSmem sm;
+__global__ __launch_bounds__(THREADS) void k_base_stats(const uint16_t* __restrict__ frames, Geometry g,
+                                                        RobustConsts rc, float* __restrict__ gmu,
+                                                        float* __restrict__ gref) {
+  __shared__ BaseSmem sm;
   const int tx_n = means_tiles_x(g), t = xcd_tile(blockIdx.x, tx_n * means_tiles_y(g));
-  guide_means_tile(frames, g, rc, gmu, gref, blockIdx.y, t % tx_n, t / tx_n, sm);
+  base_stats_tile(frames, g, rc, gmu, gref, t % tx_n, t / tx_n, sm);
 }
 
-// Every (burst, frame, tile) of a batch, one workgroup each.
-__global__ __launch_bounds__(THREADS) void k_guide_means_batch(const BurstArgs* __restrict__ bursts,
-                                                               const int* __restrict__ first, int n_bursts) {
-  __shared__ MeansSmem sm;
-  const int i = blockIdx.x;
-  int lo = 0, hi = n_bursts - 1;  // last burst with first[b] <= i
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (first[mid] <= i) lo = mid; else hi = mid - 1;
-  }
-  const BurstArgs& b = bursts[lo];
-  const int tx_n = means_tiles_x(b.g), per = tx_n * means_tiles_y(b.g);
-  const int k = i - first[lo], n = k / per, t = k - n * per;
-  guide_means_tile(b.frames, b.g, b.rc, b.gmu, b.gref, n, t % tx_n, t / tx_n, sm);
+// Every (burst, tile) of a batch, one workgroup each.
+__global__ __launch_bounds__(THREADS) void k_base_stats_batch(const BurstArgs* __restrict__ bursts,
+                                                              const int* __restrict__ first, int n_bursts) {
+  __shared__ BaseSmem sm;
+  const int i = blockIdx.x, bi = burst_of(first, n_bursts, i);
+  const BurstArgs& b = bursts[bi];
+  const int tx_n = means_tiles_x(b.g), t = i - first[bi];
+  base_stats_tile(b.frames, b.g, b.rc, b.gmu, b.gref, t % tx_n, t / tx_n, sm);
 }
 
 // ---- pass 2: robustness and its 5x5 minimum ---------------------------------------
+constexpr int TT = TT_X * TT_Y;
+constexpr int NF = 4;                               // aligned frames whose tile data are staged at once
+constexpr int PP = (RR_N + THREADS - 1) / THREADS;  // region pixels per thread
+constexpr int WCAP = 1152;  // mean-map window of one frame (per channel): every corner of the region
+
 struct RobustSmem {
+  float sW[3][WCAP];           // the frame's mean maps over the region's corners
   float sR[RR_N];
   float sTmp[RR_H * RB_W];
   int sTyR[RR_H], sTxR[RR_W];  // alignment tile of each region row / column
-  int2 sO[TT_X * TT_Y];        // floor(v / 2): integer part of the half-res displacement
-  float2 sF[TT_X * TT_Y];      // v / 2 - floor(v / 2): the bilinear fractions, exact
-  float sS[TT_X * TT_Y];
-  int sMov[TT_X * TT_Y];       // motion prior's choice (s1) per alignment tile
-  float2 sMv[(TT_X + 2) * (TT_Y + 2)];  // the frame's vectors of those tiles and a ring
+  int sRlo[TT_Y], sRhi[TT_Y], sClo[TT_X], sChi[TT_X];  // region rows / columns of each tile
+  int4 sOF[NF][TT];            // per alignment tile: floor(v/2) (x, y) and the fractions' bits
+  float sS[NF][TT];            // rejection strength of eq. (8)
+  unsigned char sMov[NF][TT];  // the motion prior chose s1
+  int sBox[NF][4];             // per frame: corner window x0, -x1, y0, -y1 (padded columns)
   int sItem;
 };
 
-// R_hat of one 32x16 half-res tile (tile_x, tile_y) of aligned frame n.
-__device__ __forceinline__ void robust_tile_frame(const float* __restrict__ motion,
-                                                  const float* __restrict__ s_tile, const Geometry& g,
-                                                  const RobustConsts& rc, const float* __restrict__ gmu,
-                                                  const float* __restrict__ gref, float* __restrict__ rmin,
-                                                  float* __restrict__ robust, int n, int tile_x, int tile_y,
-                                                  RobustSmem& sm) {
+// R_hat of one 32x16 half-res tile (tile_x, tile_y), every aligned frame.
+//
+// Per frame, the mean-map rows and columns that hold any bilinear corner of
+// the region are copied to LDS (row-contiguous loads) when they fit WCAP,
+// and the corners read from there; otherwise (a strongly divergent motion
+// field) each pixel reads its corners from the maps directly. The values,
+// and so the results, are the same either way.
+__device__ __forceinline__ void robust_tile(const float* __restrict__ motion, const float* __restrict__ s_tile,
+                                            const unsigned char* __restrict__ mov, const Geometry& g,
+                                            const RobustConsts& rc, const float* __restrict__ gmu,
+                                            const float* __restrict__ gref, float* __restrict__ rmin,
+                                            float* __restrict__ robust, int tile_x, int tile_y, RobustSmem& sm) {
   const int tid = threadIdx.x;
   const int I0 = tile_y * RB_H, J0 = tile_x * RB_W;
   const int ra0 = I0 - 2, ca0 = J0 - 2;  // region origin (may be outside the grid)
   const size_t plane = (size_t)g.h * g.w;
+  const int ws = mu_stride(g);
+  const size_t mplane = (size_t)g.h * ws;
 
   if (tid < RR_W) sm.sTxR[tid] = min(2 * clampi(ca0 + tid, 0, g.w - 1) / g.T, g.TX - 1);
   if (tid >= 64 && tid < 64 + RR_H) {
@@ -254,126 +348,189 @@ __device__ __forceinline__ void robust_tile_frame(const float* __restrict__ moti
   __syncthreads();
   const int txA = sm.sTxR[0], tyA = sm.sTyR[0];
   const int ntx = sm.sTxR[RR_W - 1] - txA + 1, nty = sm.sTyR[RR_H - 1] - tyA + 1, ntiles = ntx * nty;
-  const int mvw = ntx + 2, mvn = (nty + 2) * (ntx + 2);
-  if (rc.hf > 0.0) {
-    // the S.3 test takes the motion prior's decision (eq. 8) per tile: stage
-    // the tiles' vectors and their ring once, in one round of loads
-    for (int k = tid; k < mvn; k += THREADS) {
-      const int y = tyA - 1 + k / mvw, x = txA - 1 + k % mvw;
-      float2 v = make_float2(0.f, 0.f);
-      if (y >= 0 && y < g.TY && x >= 0 && x < g.TX) {
-        const float* p = motion + (((size_t)n * g.TY + y) * g.TX + x) * 2;  // 4-byte aligned
-        v = make_float2(p[0], p[1]);
-      }
-      sm.sMv[k] = v;
-    }
-    __syncthreads();
+  // first / last region column and row of every alignment tile
+  if (tid < RR_W) {
+    const int t = sm.sTxR[tid] - txA;
+    if (tid == 0 || sm.sTxR[tid - 1] != sm.sTxR[tid]) sm.sClo[t] = tid;
+    if (tid == RR_W - 1 || sm.sTxR[tid + 1] != sm.sTxR[tid]) sm.sChi[t] = tid;
   }
-  // per alignment tile: the bilinear base corner of u + v/2 is u + floor(v/2)
-  // (u integer) with the same fractions for every pixel of the tile
-  const float vlim = (float)(max(g.W, g.H) + 16);
-  for (int k = tid; k < ntiles; k += THREADS) {
-    const int ky = k / ntx, kx = k - ky * ntx;
-    const size_t t = ((size_t)n * g.TY + tyA + ky) * g.TX + txA + kx;
-    const float* p = motion + 2 * t;
-    // clamping keeps non-finite or huge vectors finite and changes no result
-    const float hx = fminf(fmaxf(p[0], -vlim), vlim) * 0.5f, hy = fminf(fmaxf(p[1], -vlim), vlim) * 0.5f;
-    const float fx = floorf(hx), fy = floorf(hy);
-    sm.sO[k] = make_int2((int)fx, (int)fy);
-    sm.sF[k] = make_float2(hx - fx, hy - fy);  // exact: v/2 has at most 24 significant bits
-    sm.sS[k] = s_tile[t];
-    if (rc.hf > 0.0) {
-      // eq. (7)-(8) as the motion prior takes them: spread over the existing
-      // 3x3 tiles in float64, M^2 > M_th^2 rounded operation by operation
-      double xmax = -INFINITY, xmin = INFINITY, ymax = -INFINITY, ymin = INFINITY;
-      for (int a = -1; a <= 1; ++a)
-        for (int b = -1; b <= 1; ++b) {
-          const int y = tyA + ky + a, x = txA + kx + b;
-          if (y < 0 || y >= g.TY || x < 0 || x >= g.TX) continue;
-          const float2 v = sm.sMv[(ky + 1 + a) * mvw + kx + 1 + b];
-          xmax = fmax(xmax, (double)v.x);
-          xmin = fmin(xmin, (double)v.x);
-          ymax = fmax(ymax, (double)v.y);
-          ymin = fmin(ymin, (double)v.y);
-        }
-      const double mx = xmax - xmin, my = ymax - ymin;
-      sm.sMov[k] = __dadd_rn(__dmul_rn(mx, mx), __dmul_rn(my, my)) > __dmul_rn(rc.m_th, rc.m_th);
-    }
+  if (tid >= 64 && tid < 64 + RR_H) {
+    const int r = tid - 64, t = sm.sTyR[r] - tyA;
+    if (r == 0 || sm.sTyR[r - 1] != sm.sTyR[r]) sm.sRlo[t] = r;
+    if (r == RR_H - 1 || sm.sTyR[r + 1] != sm.sTyR[r]) sm.sRhi[t] = r;
   }
-  __syncthreads();
-  const float* mun = gmu + (size_t)n * 3 * plane;
-  const float* muref = gmu + (size_t)g.ref * 3 * plane;
+
+  // this thread's region pixels: position, alignment tile, and the base
+  // frame's statistics, kept for every aligned frame
+  int kt[PP], Ic[PP], Jc[PP];
+  float mr[PP][3], dm[PP][3], gi[PP];
   {
     const float rinv = 1.f / (float)RR_W;
-    for (int k = tid; k < RR_N; k += THREADS) {
-      const int rr = split_row(k, rinv), cc = k - rr * RR_W;
-      const int kt = (sm.sTyR[rr] - tyA) * ntx + (sm.sTxR[cc] - txA);
-      const int I = clampi(ra0 + rr, 0, g.h - 1), J = clampi(ca0 + cc, 0, g.w - 1);
-      const int2 o = sm.sO[kt];
-      const float2 fr = sm.sF[kt];
-      const float fx = fr.x, fy = fr.y;
-      // the frame's mean map at u + v/2, corners clamped to the map
-      const int ya = clampi(I + o.y, 0, g.h - 1), yb = clampi(I + o.y + 1, 0, g.h - 1);
-      const int xa = clampi(J + o.x, 0, g.w - 1), xb = clampi(J + o.x + 1, 0, g.w - 1);
-      const size_t p00 = (size_t)ya * g.w + xa, p01 = (size_t)ya * g.w + xb;
-      const size_t p10 = (size_t)yb * g.w + xa, p11 = (size_t)yb * g.w + xb;
-      const size_t pr = (size_t)I * g.w + J;
-      const float ginv = gref[pr];
-      float num = 0.f;
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+      const int k = tid + q * THREADS;
+      const int kk = k < RR_N ? k : RR_N - 1;
+      const int rr = split_row(kk, rinv), cc = kk - rr * RR_W;
+      kt[q] = (sm.sTyR[rr] - tyA) * ntx + (sm.sTxR[cc] - txA);
+      Ic[q] = clampi(ra0 + rr, 0, g.h - 1);
+      Jc[q] = clampi(ca0 + cc, 0, g.w - 1);
+      gi[q] = gref[(size_t)Ic[q] * g.w + Jc[q]];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float* m = mun + (size_t)c * plane;
-        const float m00 = m[p00], m01 = m[p01], m10 = m[p10], m11 = m[p11];
-        const float top = fmaf(fx, m01 - m00, m00), bot = fmaf(fx, m11 - m10, m10);
-        const float mu_al = fmaf(fy, bot - top, top);
-        const float mu_ref = muref[(size_t)c * plane + pr];
-        float sig2, dmd2;
-        noise_md(rc, mu_ref, c, sig2, dmd2);
-        const float dms = mu_ref - mu_al;
-        const float dms2 = dms * dms;
-        // Wiener shrinkage of eq. (6): d = d_ms^3 / (d_ms^2 + d_md^2)
-        const float dd = dms * dms2 * __builtin_amdgcn_rcpf(dms2 + dmd2);
-        num = fmaf(dd, dd, num);
+        mr[q][c] = gmu[((size_t)g.ref * 3 + c) * mplane + (size_t)Ic[q] * ws + Jc[q] + 1];
+        float sig2_unused;
+        noise_md(rc, mr[q][c], c, sig2_unused, dm[q][c]);  // d_md^2 at the base brightness
       }
-      const float R = sm.sS[kt] * __expf(-num * fabsf(ginv)) - rc.t;  // eq. (5)
-      sm.sR[k] = rc.hf > 0.0 && ginv < 0.f && sm.sMov[kt] ? 0.f : fminf(fmaxf(R, 0.f), 1.f);
     }
   }
-  __syncthreads();
-  // eq. (9): 5x5 minimum, separable (the region repeats edge pixels)
+  const float vlim = (float)(max(g.W, g.H) + 16);
+  const int na = g.n - 1;
   const int ow = min(RB_W, g.w - J0), oh = min(RB_H, g.h - I0);
-  for (int k = tid; k < RR_H * RB_W; k += THREADS) {
-    const int r = k >> 5, j = k & 31;  // RB_W == 32
-    const float* row = sm.sR + r * RR_W + j;
-    sm.sTmp[k] = fminf(fminf(fminf(row[0], row[1]), fminf(row[2], row[3])), row[4]);
-  }
-  __syncthreads();
-  for (int k = tid; k < RB_H * RB_W; k += THREADS) {
-    const int i = k >> 5, j = k & 31;
-    if (i >= oh || j >= ow) continue;
-    const float* col = sm.sTmp + i * RB_W + j;
-    const float m = fminf(fminf(fminf(col[0], col[RB_W]), fminf(col[2 * RB_W], col[3 * RB_W])), col[4 * RB_W]);
-    const size_t o = (size_t)n * plane + (size_t)(I0 + i) * g.w + J0 + j;
-    rmin[o] = m;
-    if (robust) robust[o] = sm.sR[(i + 2) * RR_W + j + 2];
+
+  for (int m0 = 0; m0 < na; m0 += NF) {
+    const int nf = min(NF, na - m0);
+    // Readers of the previous chunk's data all passed a barrier since.
+    if (tid < NF * 4) (&sm.sBox[0][0])[tid] = 0x7fffffff;
+    __syncthreads();
+    // per alignment tile and frame: half the displacement (the bilinear base
+    // corner of u + v/2 is u + floor(v/2), u integer, with the same fractions
+    // for every pixel of the tile), the rejection strength, the prior's
+    // choice, and the tile's corner window (monotonic in the pixel position)
+    for (int k = tid; k < nf * ntiles; k += THREADS) {
+      const int fl = k / ntiles, kk = k - fl * ntiles;
+      const int m = m0 + fl, n = m < g.ref ? m : m + 1;
+      const int ky = kk / ntx, kx = kk - ky * ntx;
+      const size_t t = ((size_t)n * g.TY + tyA + ky) * g.TX + txA + kx;
+      const float* p = motion + 2 * t;
+      // clamping keeps non-finite or huge vectors finite and changes no result
+      const float hx = fminf(fmaxf(p[0], -vlim), vlim) * 0.5f, hy = fminf(fmaxf(p[1], -vlim), vlim) * 0.5f;
+      const float fhx = floorf(hx), fhy = floorf(hy);
+      const int ox = (int)fhx, oy = (int)fhy;
+      // the fractions are exact: v/2 has at most 24 significant bits
+      sm.sOF[fl][kk] = make_int4(ox, oy, __float_as_int(hx - fhx), __float_as_int(hy - fhy));
+      sm.sS[fl][kk] = s_tile[t];
+      sm.sMov[fl][kk] = mov[t];
+      const int x0 = clampi(clampi(ca0 + sm.sClo[kx], 0, g.w - 1) + ox, -1, g.w - 1) + 1;
+      const int x1 = clampi(clampi(ca0 + sm.sChi[kx], 0, g.w - 1) + ox, -1, g.w - 1) + 2;
+      const int y0 = clampi(clampi(ra0 + sm.sRlo[ky], 0, g.h - 1) + oy, 0, g.h - 1);
+      const int y1 = clampi(clampi(ra0 + sm.sRhi[ky], 0, g.h - 1) + oy + 1, 0, g.h - 1);
+      atomicMin(&sm.sBox[fl][0], x0);
+      atomicMin(&sm.sBox[fl][1], -x1);
+      atomicMin(&sm.sBox[fl][2], y0);
+      atomicMin(&sm.sBox[fl][3], -y1);
+    }
+    __syncthreads();
+    // copy chunk frame fl's corner window to LDS if it fits
+    auto stage = [&](int fl) -> bool {
+      const int m = m0 + fl, n = m < g.ref ? m : m + 1;
+      const int X0 = sm.sBox[fl][0], Y0 = sm.sBox[fl][2];
+      const int wx = -sm.sBox[fl][1] - X0 + 1, wy = -sm.sBox[fl][3] - Y0 + 1;
+      if (wx * wy > WCAP) return false;  // uniform
+      const float* src = gmu + (size_t)n * 3 * mplane + (size_t)Y0 * ws + X0;
+      const float inv = 1.f / (float)wx;
+      for (int k = tid; k < wx * wy; k += THREADS) {
+        const int r = split_row(k, inv);
+        const size_t o = (size_t)r * ws + (k - r * wx);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sm.sW[c][k] = src[(size_t)c * mplane + o];
+      }
+      return true;
+    };
+    bool staged = stage(0);
+    __syncthreads();
+    for (int fl = 0; fl < nf; ++fl) {
+      const int m = m0 + fl, n = m < g.ref ? m : m + 1;
+      const float* mun = gmu + (size_t)n * 3 * mplane;
+      const __amdgpu_buffer_rsrc_t rs[3] = {plane_rsrc(mun, mplane), plane_rsrc(mun + mplane, mplane),
+                                            plane_rsrc(mun + 2 * mplane, mplane)};
+      const int X0 = sm.sBox[fl][0], Y0 = sm.sBox[fl][2], wx = -sm.sBox[fl][1] - X0 + 1;
+#pragma unroll
+      for (int q = 0; q < PP; ++q) {
+        const int k = tid + q * THREADS;
+        if (k >= RR_N) continue;
+        const int4 of = sm.sOF[fl][kt[q]];
+        const float fx = __int_as_float(of.z), fy = __int_as_float(of.w);
+        // the frame's mean map at u + v/2, corners clamped to the map: rows
+        // clamped, and columns x0, x0 + 1 of the padded map with x0 clamped
+        // to [-1, w - 1], which hold the clamped corner columns
+        const int ya = clampi(Ic[q] + of.y, 0, g.h - 1), yb = clampi(Ic[q] + of.y + 1, 0, g.h - 1);
+        const int x0 = clampi(Jc[q] + of.x, -1, g.w - 1) + 1;
+        float mm[3][4];
+        if (staged) {
+          const int ia = (ya - Y0) * wx + x0 - X0, ib = (yb - Y0) * wx + x0 - X0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            mm[c][0] = sm.sW[c][ia];
+            mm[c][1] = sm.sW[c][ia + 1];
+            mm[c][2] = sm.sW[c][ib];
+            mm[c][3] = sm.sW[c][ib + 1];
+          }
+        } else {
+          const int oa = (ya * ws + x0) * 4, ob = (yb * ws + x0) * 4;  // bytes, below 2^31
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const float2 ra = ld_pair(rs[c], oa), rb = ld_pair(rs[c], ob);
+            mm[c][0] = ra.x;
+            mm[c][1] = ra.y;
+            mm[c][2] = rb.x;
+            mm[c][3] = rb.y;
+          }
+        }
+        float num = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float m00 = mm[c][0], m01 = mm[c][1], m10 = mm[c][2], m11 = mm[c][3];
+          const float top = fmaf(fx, m01 - m00, m00), bot = fmaf(fx, m11 - m10, m10);
+          const float mu_al = fmaf(fy, bot - top, top);
+          const float mu_ref = mr[q][c];
+          const float dmd2 = dm[q][c];
+          const float dms = mu_ref - mu_al;
+          const float dms2 = dms * dms;
+          // Wiener shrinkage of eq. (6): d = d_ms^3 / (d_ms^2 + d_md^2)
+          const float dd = dms * dms2 * __builtin_amdgcn_rcpf(dms2 + dmd2);
+          num = fmaf(dd, dd, num);
+        }
+        const int ktq = kt[q];
+        const float R = sm.sS[fl][ktq] * __expf(-num * fabsf(gi[q])) - rc.t;  // eq. (5)
+        sm.sR[k] = rc.hf > 0.0 && gi[q] < 0.f && sm.sMov[fl][ktq] ? 0.f : fminf(fmaxf(R, 0.f), 1.f);
+      }
+      __syncthreads();
+      // the window is free again: the next frame's copy overlaps the minimum
+      if (fl + 1 < nf) staged = stage(fl + 1);
+      // eq. (9): 5x5 minimum, separable (the region repeats edge pixels)
+      for (int k = tid; k < RR_H * RB_W; k += THREADS) {
+        const int r = k >> 5, j = k & 31;  // RB_W == 32
+        const float* row = sm.sR + r * RR_W + j;
+        sm.sTmp[k] = fminf(fminf(fminf(row[0], row[1]), fminf(row[2], row[3])), row[4]);
+      }
+      __syncthreads();
+      for (int k = tid; k < RB_H * RB_W; k += THREADS) {
+        const int i = k >> 5, j = k & 31;
+        if (i >= oh || j >= ow) continue;
+        const float* col = sm.sTmp + i * RB_W + j;
+        const float mn = fminf(fminf(fminf(col[0], col[RB_W]), fminf(col[2 * RB_W], col[3 * RB_W])), col[4 * RB_W]);
+        const size_t o = (size_t)n * plane + (size_t)(I0 + i) * g.w + J0 + j;
+        rmin[o] = mn;
+        if (robust) robust[o] = sm.sR[(i + 2) * RR_W + j + 2];
+      }
+      // the next frame writes sR (read above before the last barrier) and,
+      // after its first barrier, sTmp
+    }
   }
 }
 
-// Workgroup (tile, aligned frame): blockIdx.y enumerates the frames other
-// than the base.
 __global__ __launch_bounds__(THREADS) void k_robust(const float* __restrict__ motion,
-                                                    const float* __restrict__ s_tile, Geometry g,
+                                                    const float* __restrict__ s_tile,
+                                                    const unsigned char* __restrict__ mov, Geometry g,
                                                     RobustConsts rc, const float* __restrict__ gmu,
                                                     const float* __restrict__ gref, float* __restrict__ rmin,
                                                     float* __restrict__ robust) {
   __shared__ RobustSmem sm;
   const int tx_n = robust_tiles_x_(g), t = xcd_tile(blockIdx.x, tx_n * robust_tiles_y_(g));
-  const int n = (int)blockIdx.y < g.ref ? (int)blockIdx.y : (int)blockIdx.y + 1;
-  robust_tile_frame(motion, s_tile, g, rc, gmu, gref, rmin, robust, n, t % tx_n, t / tx_n, sm);
+  robust_tile(motion, s_tile, mov, g, rc, gmu, gref, rmin, robust, t % tx_n, t / tx_n, sm);
 }
 
-// Persistent form over (burst, tile) items of a batch, the tile's aligned
-// frames in turn.
+// Persistent form over (burst, tile) items of a batch.
 __global__ __launch_bounds__(THREADS) void k_robust_batch(const BurstArgs* __restrict__ bursts,
                                                           const WorkItem* __restrict__ items,
                                                           int n_items, int* __restrict__ counter) {
@@ -386,12 +543,8 @@ __global__ __launch_bounds__(THREADS) void k_robust_batch(const BurstArgs* __res
     if (it >= n_items) break;
     const WorkItem w = items[it];
     const BurstArgs& b = bursts[w.burst];
-    for (int n = 0; n < b.g.n; ++n) {
-      if (n == b.g.ref) continue;
-      __syncthreads();  // the previous frame's LDS is no longer read
-      robust_tile_frame(b.motion, b.s_tile, b.g, b.rc, b.gmu, b.gref, b.rmin, nullptr, n,
-                        w.tile % b.robust_tiles_x, w.tile / b.robust_tiles_x, sm);
-    }
+    robust_tile(b.motion, b.s_tile, b.mov, b.g, b.rc, b.gmu, b.gref, b.rmin, nullptr,
+                w.tile % b.robust_tiles_x, w.tile / b.robust_tiles_x, sm);
   }
 }
 
@@ -399,25 +552,36 @@ __global__ __launch_bounds__(THREADS) void k_robust_batch(const BurstArgs* __res
 
 int robust_tiles_x(const Geometry& g) { return robust_tiles_x_(g); }
 int robust_tiles_y(const Geometry& g) { return robust_tiles_y_(g); }
-int guide_means_groups(const Geometry& g) { return g.n > 1 ? g.n * means_tiles_x(g) * means_tiles_y(g) : 0; }
+int base_stats_groups(const Geometry& g) { return g.n > 1 ? means_tiles_x(g) * means_tiles_y(g) : 0; }
+int frame_means_groups(const Geometry& g) { return g.n > 1 ? (g.n - 1) * fm_strips(g) * fm_bands(g) : 0; }
 
 hipError_t launch_robust(const Geometry& g, const RobustConsts& rc, const uint16_t* frames,
                          const float* motion, const Work& w, float* rmin, float* robust,
                          hipStream_t stream) {
   if (g.n < 2) return hipSuccess;
-  hipLaunchKernelGGL(k_guide_means, dim3(means_tiles_x(g) * means_tiles_y(g), g.n), dim3(THREADS), 0, stream,
-                     frames, g, rc, w.gmu, w.gref);
+  hipLaunchKernelGGL(k_base_stats, dim3(means_tiles_x(g) * means_tiles_y(g)), dim3(THREADS), 0, stream, frames, g,
+                     rc, w.gmu, w.gref);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_robust, dim3(robust_tiles_x(g) * robust_tiles_y(g), g.n - 1), dim3(THREADS), 0, stream,
-                     motion, w.s_tile, g, rc, w.gmu, w.gref, rmin, robust);
+  hipLaunchKernelGGL(k_frame_means, dim3(fm_strips(g), fm_bands(g), g.n - 1), dim3(THREADS), 0, stream, frames, g,
+                     w.gmu);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  hipLaunchKernelGGL(k_robust, dim3(robust_tiles_x(g) * robust_tiles_y(g)), dim3(THREADS), 0, stream, motion,
+                     w.s_tile, w.mov, g, rc, w.gmu, w.gref, rmin, robust);
   return hipGetLastError();
 }
 
-hipError_t launch_guide_means_batch(const BurstArgs* bursts, const int* first, int n_bursts, int total,
-                                    hipStream_t stream) {
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_guide_means_batch, dim3(total), dim3(THREADS), 0, stream, bursts, first, n_bursts);
+hipError_t launch_guide_stats_batch(const BurstArgs* bursts, const int* base_first, int base_total,
+                                    const int* frame_first, int frame_total, int n_bursts, hipStream_t stream) {
+  if (base_total > 0) {
+    hipLaunchKernelGGL(k_base_stats_batch, dim3(base_total), dim3(THREADS), 0, stream, bursts, base_first,
+                       n_bursts);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  if (frame_total > 0)
+    hipLaunchKernelGGL(k_frame_means_batch, dim3(frame_total), dim3(THREADS), 0, stream, bursts, frame_first,
+                       n_bursts);
   return hipGetLastError();
 }
 

@@ -50,6 +50,27 @@ def test_config1_maps_match_oracle():
     np.testing.assert_allclose(maps["robust_min"].cpu().numpy(), ref["r_hat"], rtol=0, atol=5e-5)
 
 
+@pytest.mark.parametrize("spread", [0.0, 3.0, 60.0], ids=["uniform", "smooth", "divergent"])
+def test_robustness_maps_any_motion(spread):
+    """R and R_hat against the oracle for a displacement field whose tiles are
+    equal, close, or up to 60 px apart: the robustness pass reads the frames'
+    mean maps through a staged corner window when the field is coherent and
+    directly otherwise; both must give the oracle's values."""
+    b = synth.make_burst(4, 96, 160, seed=61, scale=1.5, tile_size=16)
+    f, m = b.numpy()
+    rng = np.random.default_rng(62)
+    m = m.copy()
+    m[1:] = np.float32(2.5) + rng.uniform(-spread, spread, size=m[1:].shape).astype(np.float32)
+    m[0] = 0
+    m = m.astype(np.float32)
+    case("robustness maps", spread=spread)
+    maps = torch_ops.merge_maps(torch.from_numpy(f.astype(np.int16)).to(DEV), torch.from_numpy(m).to(DEV),
+                                b.desc, b.tuning)
+    ref = om.prepare(f, m, b.desc, b.tuning)
+    np.testing.assert_allclose(maps["robust"].cpu().numpy(), ref["r"], rtol=0, atol=5e-5)
+    np.testing.assert_allclose(maps["robust_min"].cpu().numpy(), ref["r_hat"], rtol=0, atol=5e-5)
+
+
 SMALL = [
     # name, n, h, w, scale, tile, cfa, ref, sigma_t
     ("s1_rggb", 4, 64, 96, 1.0, 16, 0, 0, 1.5),
