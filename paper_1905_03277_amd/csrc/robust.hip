@@ -12,7 +12,8 @@
 //    noise-corrected variance sum of eq. (5)-(6) into [h][w], negated where
 //    the S.3 test below finds a variance loss.
 //  * k_robust: one workgroup per 32x16 tile of the base half-res grid, the
-//    aligned frames in turn (the base statistics stay in registers). R is
+//    aligned frames in turn (the base statistics stay in registers; on small
+//    grids the frames are split over several workgroups per tile). R is
 //    evaluated on the tile plus a 2-pixel border (the min-pool footprint;
 //    border pixels outside the grid repeat the edge pixel, which is what the
 //    edge-clamped 5x5 minimum reads) by sampling the frame's mean map
@@ -307,6 +308,7 @@ constexpr int TT = TT_X * TT_Y;
 constexpr int NF = 4;                               // aligned frames whose tile data are staged at once
 constexpr int PP = (RR_N + THREADS - 1) / THREADS;  // region pixels per thread
 constexpr int WCAP = 1152;  // mean-map window of one frame (per channel): every corner of the region
+constexpr long long kRobustGroups = 6144;  // target workgroup count of one robustness launch
 
 struct RobustSmem {
   float sW[3][WCAP];           // the frame's mean maps over the region's corners
@@ -321,7 +323,8 @@ struct RobustSmem {
   int sItem;
 };
 
-// R_hat of one 32x16 half-res tile (tile_x, tile_y), every aligned frame.
+// R_hat of one 32x16 half-res tile (tile_x, tile_y), aligned frames
+// m_first .. m_first + m_count - 1 (m indexes the frames other than the base).
 //
 // Per frame, the mean-map rows and columns that hold any bilinear corner of
 // the region are copied to LDS (row-contiguous loads) when they fit WCAP,
@@ -332,7 +335,8 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
                                             const unsigned char* __restrict__ mov, const Geometry& g,
                                             const RobustConsts& rc, const float* __restrict__ gmu,
                                             const float* __restrict__ gref, float* __restrict__ rmin,
-                                            float* __restrict__ robust, int tile_x, int tile_y, RobustSmem& sm) {
+                                            float* __restrict__ robust, int tile_x, int tile_y, int m_first,
+                                            int m_count, RobustSmem& sm) {
   const int tid = threadIdx.x;
   const int I0 = tile_y * RB_H, J0 = tile_x * RB_W;
   const int ra0 = I0 - 2, ca0 = J0 - 2;  // region origin (may be outside the grid)
@@ -384,10 +388,10 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
     }
   }
   const float vlim = (float)(max(g.W, g.H) + 16);
-  const int na = g.n - 1;
+  const int na = m_first + m_count;
   const int ow = min(RB_W, g.w - J0), oh = min(RB_H, g.h - I0);
 
-  for (int m0 = 0; m0 < na; m0 += NF) {
+  for (int m0 = m_first; m0 < na; m0 += NF) {
     const int nf = min(NF, na - m0);
     // Readers of the previous chunk's data all passed a barrier since.
     if (tid < NF * 4) (&sm.sBox[0][0])[tid] = 0x7fffffff;
@@ -519,15 +523,18 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
   }
 }
 
+// Workgroup (tile, group of m_per aligned frames).
 __global__ __launch_bounds__(THREADS) void k_robust(const float* __restrict__ motion,
                                                     const float* __restrict__ s_tile,
                                                     const unsigned char* __restrict__ mov, Geometry g,
                                                     RobustConsts rc, const float* __restrict__ gmu,
                                                     const float* __restrict__ gref, float* __restrict__ rmin,
-                                                    float* __restrict__ robust) {
+                                                    float* __restrict__ robust, int m_per) {
   __shared__ RobustSmem sm;
   const int tx_n = robust_tiles_x_(g), t = xcd_tile(blockIdx.x, tx_n * robust_tiles_y_(g));
-  robust_tile(motion, s_tile, mov, g, rc, gmu, gref, rmin, robust, t % tx_n, t / tx_n, sm);
+  const int m_first = blockIdx.y * m_per;
+  robust_tile(motion, s_tile, mov, g, rc, gmu, gref, rmin, robust, t % tx_n, t / tx_n, m_first,
+              min(m_per, g.n - 1 - m_first), sm);
 }
 
 // Persistent form over (burst, tile) items of a batch.
@@ -544,7 +551,7 @@ __global__ __launch_bounds__(THREADS) void k_robust_batch(const BurstArgs* __res
     const WorkItem w = items[it];
     const BurstArgs& b = bursts[w.burst];
     robust_tile(b.motion, b.s_tile, b.mov, b.g, b.rc, b.gmu, b.gref, b.rmin, nullptr,
-                w.tile % b.robust_tiles_x, w.tile / b.robust_tiles_x, sm);
+                w.tile % b.robust_tiles_x, w.tile / b.robust_tiles_x, 0, b.g.n - 1, sm);
   }
 }
 
@@ -566,8 +573,17 @@ hipError_t launch_robust(const Geometry& g, const RobustConsts& rc, const uint16
   hipLaunchKernelGGL(k_frame_means, dim3(fm_strips(g), fm_bands(g), g.n - 1), dim3(THREADS), 0, stream, frames, g,
                      w.gmu);
   if ((err = hipGetLastError()) != hipSuccess) return err;
-  hipLaunchKernelGGL(k_robust, dim3(robust_tiles_x(g) * robust_tiles_y(g)), dim3(THREADS), 0, stream, motion,
-                     w.s_tile, w.mov, g, rc, w.gmu, w.gref, rmin, robust);
+  // Frames per workgroup: all of them (the base statistics are loaded once
+  // per tile) unless that leaves fewer than ~kRobustGroups workgroups, about
+  // four rounds of the resident workgroups of a 256-CU device; then as few
+  // as that target needs.
+  const int tiles = robust_tiles_x(g) * robust_tiles_y(g), na = g.n - 1;
+  const long long work = (long long)tiles * na;
+  int m_per = (int)((work + kRobustGroups - 1) / kRobustGroups);
+  m_per = m_per < 1 ? 1 : (m_per > na ? na : m_per);
+  const int groups = (na + m_per - 1) / m_per;
+  hipLaunchKernelGGL(k_robust, dim3(tiles, groups), dim3(THREADS), 0, stream, motion, w.s_tile, w.mov, g, rc, w.gmu,
+                     w.gref, rmin, robust, m_per);
   return hipGetLastError();
 }
 
