@@ -93,14 +93,21 @@ __device__ __forceinline__ int burst_of(const int* __restrict__ first, int n_bur
 }
 
 // ---- pass 1a: the aligned frames' guide means --------------------------------------
-// One wave per 62 x 16 block of half-res pixels: lane l holds guide column
-// strip * 62 - 1 + l (clamped), so lanes 1 .. 62 have both neighbours in the
-// wave; the wave walks down the rows keeping the last two row sums.
-constexpr int FM_COLS = 62, FM_ROWS = 16, FM_WAVES = THREADS / 64;
+// One wave per 64 x 8 block of half-res pixels: lane l holds guide column
+// strip * 64 + l, its neighbours come from the adjacent lanes and, for lanes
+// 0 and 63, from one extra column load each; the wave walks down the rows
+// keeping the last two row sums.
+constexpr int FM_COLS = 64, FM_ROWS = 8, FM_WAVES = THREADS / 64;
 
 __host__ __device__ __forceinline__ int fm_strips(const Geometry& g) { return (g.w + FM_COLS - 1) / FM_COLS; }
 __host__ __device__ __forceinline__ int fm_bands(const Geometry& g) {
   return (g.h + FM_ROWS * FM_WAVES - 1) / (FM_ROWS * FM_WAVES);
+}
+
+__device__ __forceinline__ void guide_of(uint32_t top, uint32_t bot, const Geometry& g, float (&v)[3]) {
+  v[0] = (float)quad_at(top, bot, g.red_pos);
+  v[1] = (float)(quad_at(top, bot, g.green_pos[0]) + quad_at(top, bot, g.green_pos[1])) * 0.5f;
+  v[2] = (float)quad_at(top, bot, g.blue_pos);
 }
 
 __device__ __forceinline__ void frame_means_block(const uint16_t* __restrict__ frames, const Geometry& g,
@@ -108,37 +115,46 @@ __device__ __forceinline__ void frame_means_block(const uint16_t* __restrict__ f
   const int lane = threadIdx.x & 63;
   const int P0 = band * FM_ROWS;
   if (P0 >= g.h) return;  // uniform per wave; no barrier follows
-  const int J = strip * FM_COLS - 1 + lane, Jc = clampi(J, 0, g.w - 1);
-  const bool out_ok = lane >= 1 && lane <= FM_COLS && J < g.w;
+  const int J = strip * FM_COLS + lane, Jc = min(J, g.w - 1);
+  const bool edge = lane == 0 || lane == 63;
+  const int Jh = clampi(lane == 0 ? J - 1 : J + 1, 0, g.w - 1);  // the edge lanes' outer neighbour
   const uint16_t* f = frames + (size_t)n * g.H * g.W;
   const int ws = mu_stride(g);
   const size_t plane = (size_t)g.h * ws;
   float* mu = gmu + (size_t)n * 3 * plane;
-  // every row's quad first, so that the loads are all in flight together
-  uint32_t top[FM_ROWS + 2], bot[FM_ROWS + 2];
+  // every row's quads first, so that the loads are all in flight together
+  uint32_t top[FM_ROWS + 2], bot[FM_ROWS + 2], htop[FM_ROWS + 2], hbot[FM_ROWS + 2];
 #pragma unroll
   for (int i = 0; i < FM_ROWS + 2; ++i) {
     const int I = clampi(P0 - 1 + i, 0, g.h - 1);
     top[i] = *(const uint32_t*)(f + (size_t)(2 * I) * g.W + 2 * Jc);
     bot[i] = *(const uint32_t*)(f + (size_t)(2 * I + 1) * g.W + 2 * Jc);
   }
+  if (edge) {
+#pragma unroll
+    for (int i = 0; i < FM_ROWS + 2; ++i) {
+      const int I = clampi(P0 - 1 + i, 0, g.h - 1);
+      htop[i] = *(const uint32_t*)(f + (size_t)(2 * I) * g.W + 2 * Jh);
+      hbot[i] = *(const uint32_t*)(f + (size_t)(2 * I + 1) * g.W + 2 * Jh);
+    }
+  }
   // 3x3 box mean, separable: Hs = (g(Q-1) + g(Q)) + g(Q+1), then
   // (Hs(P-1) + Hs(P)) + Hs(P+1), times 1/9
   float h0[3] = {0.f, 0.f, 0.f}, h1[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int i = 0; i < FM_ROWS + 2; ++i) {
-    float v[3];
-    v[0] = (float)quad_at(top[i], bot[i], g.red_pos);
-    v[1] = (float)(quad_at(top[i], bot[i], g.green_pos[0]) + quad_at(top[i], bot[i], g.green_pos[1])) * 0.5f;
-    v[2] = (float)quad_at(top[i], bot[i], g.blue_pos);
+    float v[3], hv[3] = {0.f, 0.f, 0.f};
+    guide_of(top[i], bot[i], g, v);
+    if (edge) guide_of(htop[i], hbot[i], g, hv);
     float hs[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const float l = __shfl_up(v[c], 1, 64), r = __shfl_down(v[c], 1, 64);
+      const float up = __shfl_up(v[c], 1, 64), dn = __shfl_down(v[c], 1, 64);
+      const float l = lane == 0 ? hv[c] : up, r = lane == 63 ? hv[c] : dn;
       hs[c] = (l + v[c]) + r;
     }
     const int P = P0 + i - 2;  // the row whose mean is complete
-    if (i >= 2 && out_ok && P < g.h) {
+    if (i >= 2 && J < g.w && P < g.h) {
       float* row = mu + (size_t)P * ws + J + 1;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -156,11 +172,14 @@ __device__ __forceinline__ void frame_means_block(const uint16_t* __restrict__ f
   }
 }
 
-// Workgroup (strip, band of FM_WAVES blocks, aligned frame).
+// Workgroup (band of FM_WAVES blocks of one strip, aligned frame), mapped by
+// XCD so that neighbouring strips and bands, which share the edge columns and
+// rows, meet in one L2.
 __global__ __launch_bounds__(THREADS) void k_frame_means(const uint16_t* __restrict__ frames, Geometry g,
                                                          float* __restrict__ gmu) {
-  const int n = (int)blockIdx.z < g.ref ? (int)blockIdx.z : (int)blockIdx.z + 1;
-  frame_means_block(frames, g, gmu, n, blockIdx.x, blockIdx.y * FM_WAVES + (threadIdx.x >> 6));
+  const int n = (int)blockIdx.y < g.ref ? (int)blockIdx.y : (int)blockIdx.y + 1;
+  const int ns = fm_strips(g), t = xcd_tile(blockIdx.x, ns * fm_bands(g));
+  frame_means_block(frames, g, gmu, n, t % ns, (t / ns) * FM_WAVES + (threadIdx.x >> 6));
 }
 
 // Every (burst, aligned frame, strip, band) of a batch, one workgroup each.
@@ -570,8 +589,8 @@ hipError_t launch_robust(const Geometry& g, const RobustConsts& rc, const uint16
                      rc, w.gmu, w.gref);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_frame_means, dim3(fm_strips(g), fm_bands(g), g.n - 1), dim3(THREADS), 0, stream, frames, g,
-                     w.gmu);
+  hipLaunchKernelGGL(k_frame_means, dim3(fm_strips(g) * fm_bands(g), g.n - 1), dim3(THREADS), 0, stream, frames,
+                     g, w.gmu);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   // Frames per workgroup: all of them (the base statistics are loaded once
   // per tile) unless that leaves fewer than ~kRobustGroups workgroups, about
