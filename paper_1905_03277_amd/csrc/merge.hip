@@ -16,7 +16,8 @@
 //      channel against a per-channel reference exponent that is raised only
 //      when a frame would exceed it by more than 2^64 (online normalisation).
 // If a frame's footprint does not fit the LDS buffers (a strongly divergent
-// motion field), the tile is processed one alignment tile at a time.
+// motion field), every alignment tile of the output tile gets its own
+// windows, laid out side by side in as few groups as the buffers allow.
 #include <math.h>
 
 #include <type_traits>
@@ -30,6 +31,40 @@ namespace hmfsr {
 namespace {
 
 constexpr float SLACK = 64.f;   // log2 headroom above the reference exponent
+
+// Footprint windows of a set of output pixels in one frame. Omega window:
+// every bilinear corner, unclamped (edge values repeated); luma window: the
+// clamped corners' 3x3 neighbourhoods; raw window: the luma quads and every
+// nine-sample window, unclamped (zero outside the frame). raw, lum, om: the
+// window's offsets in the LDS buffers.
+struct Win {
+  int rc0, rr0, rw, rh;
+  int lc0, lr0, lw, lh;
+  int oc0, or0, ow, oh;
+  int raw, lum, om;
+};
+
+__device__ __forceinline__ Win make_win(const Bounds& bd, const Geometry& g) {
+  Win w;
+  w.oc0 = bd.hj0;
+  w.ow = bd.hj1 - bd.hj0 + 2;
+  w.or0 = bd.hi0;
+  w.oh = bd.hi1 - bd.hi0 + 2;
+  w.lc0 = max(clampi(bd.hj0, 0, g.w - 1) - 1, 0);
+  const int lc1 = min(clampi(bd.hj1 + 1, 0, g.w - 1) + 1, g.w - 1);
+  w.lr0 = max(clampi(bd.hi0, 0, g.h - 1) - 1, 0);
+  const int lr1 = min(clampi(bd.hi1 + 1, 0, g.h - 1) + 1, g.h - 1);
+  w.rc0 = min(2 * w.lc0, bd.jc0 - 1);
+  const int rc1 = max(2 * lc1 + 1, bd.jc1 + 1);
+  w.rr0 = min(2 * w.lr0, bd.ic0 - 1);
+  const int rr1 = max(2 * lr1 + 1, bd.ic1 + 1);
+  w.lw = lc1 - w.lc0 + 1;
+  w.lh = lr1 - w.lr0 + 1;
+  w.rw = rc1 - w.rc0 + 1;
+  w.rh = rr1 - w.rr0 + 1;
+  w.raw = w.lum = w.om = 0;
+  return w;
+}
 
 template <int MH>
 struct MergeSmem {
@@ -46,6 +81,9 @@ struct MergeSmem {
   float sRh[CP::RH];
   int sRed[8];
   int sRh0[4];
+  Win sWin[CP::VT];    // per alignment tile, when the whole tile's window does not fit
+  int sGrp[CP::VT + 1];  // groups of alignment tiles whose windows fit side by side
+  int sNGrp;
   int sItem;
 };
 
@@ -95,6 +133,8 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
   float* sRh = sm.sRh;
   int* sRed = sm.sRed;
   int* sRh0 = sm.sRh0;
+  Win* sWin = sm.sWin;
+  int* sGrp = sm.sGrp;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int C0 = tile_x * MW, R0 = tile_y * MH;
@@ -236,216 +276,281 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
     }
     __syncthreads();
 
-    // Segments: the whole tile, or one alignment tile at a time.
-    bool whole = true;
-    int seg = 0;
-    while (true) {
+    // Windows: the whole tile's footprint in one window when it fits the
+    // buffers; otherwise every alignment tile's own window, laid out side by
+    // side in groups that fit (one alignment tile always does: its pixels
+    // share one displacement).
+    Win W;
+    {
       Bounds bd;
-      if (whole) {
-        bd.jc0 = sRed[0]; bd.jc1 = -sRed[1]; bd.ic0 = sRed[2]; bd.ic1 = -sRed[3];
-        bd.hj0 = sRed[4]; bd.hj1 = -sRed[5]; bd.hi0 = sRed[6]; bd.hi1 = -sRed[7];
-      } else {
-        bd = sTB[seg];
+      bd.jc0 = sRed[0]; bd.jc1 = -sRed[1]; bd.ic0 = sRed[2]; bd.ic1 = -sRed[3];
+      bd.hj0 = sRed[4]; bd.hj1 = -sRed[5]; bd.hi0 = sRed[6]; bd.hi1 = -sRed[7];
+      W = make_win(bd, g);
+    }
+    // uniform: every thread read the same bounds
+    const bool whole = W.ow * W.oh <= CP::OM && W.lw * W.lh <= CP::LUMA && W.rw * W.rh <= CP::RAW;
+    int ngroups = 1;
+    if (!whole) {
+      for (int k = tid; k < ntiles; k += THREADS) sWin[k] = make_win(sTB[k], g);
+      __syncthreads();
+      if (tid == 0) {
+        int ng = 0, n_raw = 0, n_lum = 0, n_om = 0;
+        sGrp[0] = 0;
+        for (int k = 0; k < ntiles; ++k) {
+          Win& w = sWin[k];
+          const int a_raw = w.rw * w.rh, a_lum = w.lw * w.lh, a_om = w.ow * w.oh;
+          if (k > sGrp[ng] && (n_raw + a_raw > CP::RAW || n_lum + a_lum > CP::LUMA || n_om + a_om > CP::OM)) {
+            sGrp[++ng] = k;
+            n_raw = n_lum = n_om = 0;
+          }
+          w.raw = n_raw;
+          w.lum = n_lum;
+          w.om = n_om;
+          n_raw += a_raw;
+          n_lum += a_lum;
+          n_om += a_om;
+        }
+        sGrp[++ng] = ntiles;
+        sm.sNGrp = ng;
       }
-      const int sty = whole ? -1 : seg / ntx, stx = whole ? -1 : seg % ntx;
-      // Omega window: every bilinear corner, unclamped (edge values repeated);
-      // luma window: the clamped corners' 3x3 neighbourhoods; raw window: the
-      // luma quads and every nine-sample window, unclamped (zero outside).
-      const int oc0 = bd.hj0, ow = bd.hj1 - bd.hj0 + 2;
-      const int or0 = bd.hi0, oh = bd.hi1 - bd.hi0 + 2;
-      const int lc0 = max(clampi(bd.hj0, 0, g.w - 1) - 1, 0);
-      const int lc1 = min(clampi(bd.hj1 + 1, 0, g.w - 1) + 1, g.w - 1);
-      const int lr0 = max(clampi(bd.hi0, 0, g.h - 1) - 1, 0);
-      const int lr1 = min(clampi(bd.hi1 + 1, 0, g.h - 1) + 1, g.h - 1);
-      const int rc0 = min(2 * lc0, bd.jc0 - 1), rc1 = max(2 * lc1 + 1, bd.jc1 + 1);
-      const int rr0 = min(2 * lr0, bd.ic0 - 1), rr1 = max(2 * lr1 + 1, bd.ic1 + 1);
-      const int lw = lc1 - lc0 + 1, lh = lr1 - lr0 + 1;
-      const int rw = rc1 - rc0 + 1, rh = rr1 - rr0 + 1;
-      if (whole && (ow * oh > CP::OM || lw * lh > CP::LUMA || rw * rh > CP::RAW)) {
-        whole = false;  // uniform: every thread read the same bounds
-        seg = 0;
-        continue;
-      }
+      __syncthreads();
+      ngroups = sm.sNGrp;
+    }
+    for (int gi = 0; gi < ngroups; ++gi) {
+      if (gi) __syncthreads();  // the previous group's windows are no longer read
+      const int s0 = whole ? 0 : sGrp[gi], s1 = whole ? 0 : sGrp[gi + 1];
+      // window of flat buffer entry e of this group (kind: 0 raw, 1 luma, 2 Omega)
+      auto find = [&](int e, int kind) -> int {
+        int k = s0;
+        while (k + 1 < s1 && (kind == 0 ? sWin[k + 1].raw : kind == 1 ? sWin[k + 1].lum : sWin[k + 1].om) <= e) ++k;
+        return k;
+      };
+      auto entries = [&](int kind) -> int {
+        if (whole) return kind == 0 ? W.rw * W.rh : kind == 1 ? W.lw * W.lh : W.ow * W.oh;
+        const Win& w = sWin[s1 - 1];
+        return kind == 0 ? w.raw + w.rw * w.rh : kind == 1 ? w.lum + w.lw * w.lh : w.om + w.ow * w.oh;
+      };
       // stage raw footprint, quad sums, Omega
-      {
+      if (whole) {
+        const int rc0 = W.rc0, rr0 = W.rr0, rw = W.rw, rh = W.rh;
         const float inv = 1.f / (float)rw;
         for (int k = tid; k < rw * rh; k += THREADS) {
           const int r = split_row(k, inv), c = k - r * rw;
           const int gr = rr0 + r, gc = rc0 + c;
           sRaw[k] = (gr >= 0 && gr < g.H && gc >= 0 && gc < g.W) ? (float)f[(size_t)gr * g.W + gc] : 0.f;
         }
+      } else {
+        const int n_e = entries(0);
+        for (int e = tid; e < n_e; e += THREADS) {
+          const Win& w = sWin[find(e, 0)];
+          const int k = e - w.raw, r = k / w.rw, c = k - r * w.rw;
+          const int gr = w.rr0 + r, gc = w.rc0 + c;
+          sRaw[e] = (gr >= 0 && gr < g.H && gc >= 0 && gc < g.W) ? (float)f[(size_t)gr * g.W + gc] : 0.f;
+        }
       }
       __syncthreads();
-      {
+      if (whole) {
+        const int rc0 = W.rc0, rr0 = W.rr0, rw = W.rw, lc0 = W.lc0, lr0 = W.lr0, lw = W.lw, lh = W.lh;
         const float inv = 1.f / (float)lw;
         for (int k = tid; k < lw * lh; k += THREADS) {
           const int r = split_row(k, inv), c = k - r * lw;
           const int o = (2 * (lr0 + r) - rr0) * rw + 2 * (lc0 + c) - rc0;
           sLum[k] = (sRaw[o] + sRaw[o + 1]) + (sRaw[o + rw] + sRaw[o + rw + 1]);  // exact
         }
+      } else {
+        const int n_e = entries(1);
+        for (int e = tid; e < n_e; e += THREADS) {
+          const Win& w = sWin[find(e, 1)];
+          const int k = e - w.lum, r = k / w.lw, c = k - r * w.lw;
+          const int o = w.raw + (2 * (w.lr0 + r) - w.rr0) * w.rw + 2 * (w.lc0 + c) - w.rc0;
+          sLum[e] = (sRaw[o] + sRaw[o + 1]) + (sRaw[o + w.rw] + sRaw[o + w.rw + 1]);  // exact
+        }
       }
       __syncthreads();
       {
-        const float inv = 1.f / (float)ow;
-        for (int k = tid; k < ow * oh; k += THREADS) {
-          const int r = split_row(k, inv), c = k - r * ow;
-          const int I = clampi(or0 + r, 0, g.h - 1), J = clampi(oc0 + c, 0, g.w - 1);
+        // Omega at entry (r, c) of window w, stored at flat entry e
+        auto omega_at = [&](int e, const Win& w, int r, int c) {
+          const int I = clampi(w.or0 + r, 0, g.h - 1), J = clampi(w.oc0 + c, 0, g.w - 1);
           float l[3][3];
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
-            const int row = (clampi(I + a - 1, 0, g.h - 1) - lr0) * lw;
+            const int row = w.lum + (clampi(I + a - 1, 0, g.h - 1) - w.lr0) * w.lw;
 #pragma unroll
-            for (int bb = 0; bb < 3; ++bb) l[a][bb] = sLum[row + clampi(J + bb - 1, 0, g.w - 1) - lc0];
+            for (int bb = 0; bb < 3; ++bb) l[a][bb] = sLum[row + clampi(J + bb - 1, 0, g.w - 1) - w.lc0];
           }
           double oxx, oxy, oyy;
           omega_from_quads(l, mc.om, oxx, oxy, oyy);
-          sOm[0][k] = oxx;
-          sOm[1][k] = oxy;
-          sOm[2][k] = oyy;
+          sOm[0][e] = oxx;
+          sOm[1][e] = oxy;
+          sOm[2][e] = oyy;
+        };
+        if (whole) {
+          const float inv = 1.f / (float)W.ow;
+          for (int k = tid; k < W.ow * W.oh; k += THREADS) {
+            const int r = split_row(k, inv);
+            omega_at(k, W, r, k - r * W.ow);
+          }
+        } else {
+          const int n_e = entries(2);
+          for (int e = tid; e < n_e; e += THREADS) {
+            const Win& w = sWin[find(e, 2)];
+            const int k = e - w.om, r = k / w.ow;
+            omega_at(e, w, r, k - r * w.ow);
+          }
         }
       }
       __syncthreads();
 
-      // accumulate
-      if (col_ok) {
+      // accumulate: one pixel with its windows (uniform for the whole tile,
+      // else its alignment tile's)
+      auto pixel = [&](const int p, const int r, const int tyl, const Win& wg) __attribute__((always_inline)) {
+            float rho = 1.f;
+            if (!is_ref) {
+              const RowInfo ri = sRow[r];
+              const float top = sRh[ri.ya + rxa] + rfx * (sRh[ri.ya + rxb] - sRh[ri.ya + rxa]);
+              const float bot = sRh[ri.yb + rxa] + rfx * (sRh[ri.yb + rxb] - sRh[ri.yb + rxa]);
+              rho = top + ri.fy * (bot - top);
+              if (!(rho > 0.f)) return;
+            }
+            const float2 v = sV[tyl * ntx + txl];
+            const double px = X + (double)v.x, py = sY[r] + (double)v.y;
+            const double fjc = floor(px), fic = floor(py);
+            const double frx = px - fjc, fry = py - fic;  // exact
+            const int jc = (int)fjc, ic = (int)fic;
+            // Omega at p / 2 - 1/2 (bilinear; the window repeats edge values)
+            const double hx = px * 0.5 - 0.5, hy = py * 0.5 - 0.5;
+            const double fhj = floor(hx), fhi = floor(hy);
+            const double fx = hx - fhj, fy = hy - fhi;
+            const int ow = wg.ow;
+            const int ob = wg.om + ((int)fhi - wg.or0) * ow + ((int)fhj - wg.oc0);
+            double O[3];
+  #pragma unroll
+            for (int e = 0; e < 3; ++e) {
+              const double o00 = sOm[e][ob], o01 = sOm[e][ob + 1];
+              const double o10 = sOm[e][ob + ow], o11 = sOm[e][ob + ow + 1];
+              const double top = fma(fx, o01 - o00, o00);
+              const double bot = fma(fx, o11 - o10, o10);
+              O[e] = fma(fy, bot - top, top);
+            }
+            // eq. (2): log2 w = -1/2 log2(e) d^T Omega^-1 d
+            const double sc = NEG_HALF_LOG2E * recip64(O[0] * O[2] - O[1] * O[1]);
+            const double qa = O[2] * sc, qb2 = -2.0 * O[1] * sc, qc = O[0] * sc;
+            // sample offsets d = q + 1/2 - p; far away where the sample is outside the frame
+            double dx[3], dy[3];
+  #pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              dx[j] = ((double)j - 0.5) - frx;
+              dy[j] = ((double)j - 0.5) - fry;
+            }
+            if (!(jc >= 1 && jc <= g.W - 2 && ic >= 1 && ic <= g.H - 2)) {
+  #pragma unroll
+              for (int j = 0; j < 3; ++j) {
+                const int qj = jc + j - 1, qi = ic + j - 1;
+                if (qj < 0 || qj >= g.W) dx[j] = FAR_X;
+                if (qi < 0 || qi >= g.H) dy[j] = FAR_Y;
+              }
+            }
+            double E[3][3];
+            {
+              double ax[3], cy[3], by[3];
+  #pragma unroll
+              for (int j = 0; j < 3; ++j) {
+                ax[j] = qa * (dx[j] * dx[j]);
+                cy[j] = qc * (dy[j] * dy[j]);
+                by[j] = qb2 * dy[j];
+              }
+  #pragma unroll
+              for (int i = 0; i < 3; ++i)
+  #pragma unroll
+                for (int j = 0; j < 3; ++j) E[i][j] = fma(by[i], dx[j], ax[j] + cy[i]);
+            }
+            // Colour groups of the 3x3 window: centre (0), left/right (1), up/down (2), corners (3).
+            const int pr = ic & 1, pc = jc & 1;
+            const int c0 = colour_of(mc.col4, pr * 2 + pc);
+            const int c1 = colour_of(mc.col4, pr * 2 + (pc ^ 1));
+            const bool isG = c0 == 1;
+            const bool xIsR = (isG ? c1 : c0) == 0;  // group "X" (centre or left/right) is red
+            float d[3][3];
+            auto exponents = [&]() {
+              const float MX = xIsR ? M[p][0] : M[p][2], MY = xIsR ? M[p][2] : M[p][0], MG = M[p][1];
+              const double g0 = (double)(isG ? MG : MX), g1 = (double)(isG ? MX : MG);
+              const double g2 = (double)(isG ? MY : MG), g3 = (double)(isG ? MG : MY);
+              d[1][1] = (float)(E[1][1] - g0);
+              d[1][0] = (float)(E[1][0] - g1);
+              d[1][2] = (float)(E[1][2] - g1);
+              d[0][1] = (float)(E[0][1] - g2);
+              d[2][1] = (float)(E[2][1] - g2);
+              d[0][0] = (float)(E[0][0] - g3);
+              d[0][2] = (float)(E[0][2] - g3);
+              d[2][0] = (float)(E[2][0] - g3);
+              d[2][2] = (float)(E[2][2] - g3);
+            };
+            exponents();
+            const float dmax = fmaxf(fmaxf(fmaxf(d[0][0], d[0][1]), fmaxf(d[0][2], d[1][0])),
+                                     fmaxf(fmaxf(d[1][1], d[1][2]), fmaxf(fmaxf(d[2][0], d[2][1]), d[2][2])));
+            if (dmax > SLACK) {
+              // raise the reference of every channel this frame would overflow
+              const float m0 = (float)E[1][1];
+              const float m1 = (float)fmax(E[1][0], E[1][2]);
+              const float m2 = (float)fmax(E[0][1], E[2][1]);
+              const float m3 = (float)fmax(fmax(E[0][0], E[0][2]), fmax(E[2][0], E[2][2]));
+              const float fG = isG ? fmaxf(m0, m3) : fmaxf(m1, m2);
+              const float fX = isG ? m1 : m0, fY = isG ? m2 : m3;
+              const float fm[3] = {xIsR ? fX : fY, fG, xIsR ? fY : fX};
+  #pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                if (fm[c] > M[p][c] + SLACK) {
+                  const float s = __builtin_amdgcn_exp2f(M[p][c] - fm[c]);
+                  num[p][c] *= s;
+                  den[p][c] *= s;
+                  M[p][c] = fm[c];
+                }
+              }
+              exponents();
+            }
+            const int rw = wg.rw;
+            const int vb = wg.raw + (ic - 1 - wg.rr0) * rw + (jc - 1 - wg.rc0);
+            float w[3][3], val[3][3];
+  #pragma unroll
+            for (int i = 0; i < 3; ++i)
+  #pragma unroll
+              for (int j = 0; j < 3; ++j) {
+                w[i][j] = __builtin_amdgcn_exp2f(d[i][j]);
+                val[i][j] = sRaw[vb + i * rw + j];
+              }
+            const float S0n = w[1][1] * val[1][1], S0d = w[1][1];
+            const float S1n = fmaf(w[1][0], val[1][0], w[1][2] * val[1][2]), S1d = w[1][0] + w[1][2];
+            const float S2n = fmaf(w[0][1], val[0][1], w[2][1] * val[2][1]), S2d = w[0][1] + w[2][1];
+            const float S3n = fmaf(w[0][0], val[0][0], w[0][2] * val[0][2]) +
+                              fmaf(w[2][0], val[2][0], w[2][2] * val[2][2]);
+            const float S3d = (w[0][0] + w[0][2]) + (w[2][0] + w[2][2]);
+            const float Gn = isG ? S0n + S3n : S1n + S2n, Gd = isG ? S0d + S3d : S1d + S2d;
+            const float Xn = isG ? S1n : S0n, Xd = isG ? S1d : S0d;
+            const float Yn = isG ? S2n : S3n, Yd = isG ? S2d : S3d;
+            const Acc ra = rho;
+            num[p][0] = fma(ra, (Acc)(xIsR ? Xn : Yn), num[p][0]);
+            den[p][0] = fma(ra, (Acc)(xIsR ? Xd : Yd), den[p][0]);
+            num[p][1] = fma(ra, (Acc)Gn, num[p][1]);
+            den[p][1] = fma(ra, (Acc)Gd, den[p][1]);
+            num[p][2] = fma(ra, (Acc)(xIsR ? Yn : Xn), num[p][2]);
+            den[p][2] = fma(ra, (Acc)(xIsR ? Yd : Xd), den[p][2]);
+      };
+      if (col_ok && whole) {
+#pragma unroll
+        for (int p = 0; p < PX; ++p) {
+          const int r = wave * PX + p;
+          if (r < nrow) pixel(p, r, sTyRow[r] - tyA, W);
+        }
+      } else if (col_ok) {
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
           const int r = wave * PX + p;
           if (r >= nrow) continue;
-          const int tyl = sTyRow[r] - tyA;
-          if (!whole && (tyl != sty || txl != stx)) continue;
-          float rho = 1.f;
-          if (!is_ref) {
-            const RowInfo ri = sRow[r];
-            const float top = sRh[ri.ya + rxa] + rfx * (sRh[ri.ya + rxb] - sRh[ri.ya + rxa]);
-            const float bot = sRh[ri.yb + rxa] + rfx * (sRh[ri.yb + rxb] - sRh[ri.yb + rxa]);
-            rho = top + ri.fy * (bot - top);
-            if (!(rho > 0.f)) continue;
-          }
-          const float2 v = sV[tyl * ntx + txl];
-          const double px = X + (double)v.x, py = sY[r] + (double)v.y;
-          const double fjc = floor(px), fic = floor(py);
-          const double frx = px - fjc, fry = py - fic;  // exact
-          const int jc = (int)fjc, ic = (int)fic;
-          // Omega at p / 2 - 1/2 (bilinear; the window repeats edge values)
-          const double hx = px * 0.5 - 0.5, hy = py * 0.5 - 0.5;
-          const double fhj = floor(hx), fhi = floor(hy);
-          const double fx = hx - fhj, fy = hy - fhi;
-          const int ob = ((int)fhi - or0) * ow + ((int)fhj - oc0);
-          double O[3];
-#pragma unroll
-          for (int e = 0; e < 3; ++e) {
-            const double o00 = sOm[e][ob], o01 = sOm[e][ob + 1];
-            const double o10 = sOm[e][ob + ow], o11 = sOm[e][ob + ow + 1];
-            const double top = fma(fx, o01 - o00, o00);
-            const double bot = fma(fx, o11 - o10, o10);
-            O[e] = fma(fy, bot - top, top);
-          }
-          // eq. (2): log2 w = -1/2 log2(e) d^T Omega^-1 d
-          const double sc = NEG_HALF_LOG2E * recip64(O[0] * O[2] - O[1] * O[1]);
-          const double qa = O[2] * sc, qb2 = -2.0 * O[1] * sc, qc = O[0] * sc;
-          // sample offsets d = q + 1/2 - p; far away where the sample is outside the frame
-          double dx[3], dy[3];
-#pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            dx[j] = ((double)j - 0.5) - frx;
-            dy[j] = ((double)j - 0.5) - fry;
-          }
-          if (!(jc >= 1 && jc <= g.W - 2 && ic >= 1 && ic <= g.H - 2)) {
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-              const int qj = jc + j - 1, qi = ic + j - 1;
-              if (qj < 0 || qj >= g.W) dx[j] = FAR_X;
-              if (qi < 0 || qi >= g.H) dy[j] = FAR_Y;
-            }
-          }
-          double E[3][3];
-          {
-            double ax[3], cy[3], by[3];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-              ax[j] = qa * (dx[j] * dx[j]);
-              cy[j] = qc * (dy[j] * dy[j]);
-              by[j] = qb2 * dy[j];
-            }
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-              for (int j = 0; j < 3; ++j) E[i][j] = fma(by[i], dx[j], ax[j] + cy[i]);
-          }
-          // Colour groups of the 3x3 window: centre (0), left/right (1), up/down (2), corners (3).
-          const int pr = ic & 1, pc = jc & 1;
-          const int c0 = colour_of(mc.col4, pr * 2 + pc);
-          const int c1 = colour_of(mc.col4, pr * 2 + (pc ^ 1));
-          const bool isG = c0 == 1;
-          const bool xIsR = (isG ? c1 : c0) == 0;  // group "X" (centre or left/right) is red
-          float d[3][3];
-          auto exponents = [&]() {
-            const float MX = xIsR ? M[p][0] : M[p][2], MY = xIsR ? M[p][2] : M[p][0], MG = M[p][1];
-            const double g0 = (double)(isG ? MG : MX), g1 = (double)(isG ? MX : MG);
-            const double g2 = (double)(isG ? MY : MG), g3 = (double)(isG ? MG : MY);
-            d[1][1] = (float)(E[1][1] - g0);
-            d[1][0] = (float)(E[1][0] - g1);
-            d[1][2] = (float)(E[1][2] - g1);
-            d[0][1] = (float)(E[0][1] - g2);
-            d[2][1] = (float)(E[2][1] - g2);
-            d[0][0] = (float)(E[0][0] - g3);
-            d[0][2] = (float)(E[0][2] - g3);
-            d[2][0] = (float)(E[2][0] - g3);
-            d[2][2] = (float)(E[2][2] - g3);
-          };
-          exponents();
-          const float dmax = fmaxf(fmaxf(fmaxf(d[0][0], d[0][1]), fmaxf(d[0][2], d[1][0])),
-                                   fmaxf(fmaxf(d[1][1], d[1][2]), fmaxf(fmaxf(d[2][0], d[2][1]), d[2][2])));
-          if (dmax > SLACK) {
-            // raise the reference of every channel this frame would overflow
-            const float m0 = (float)E[1][1];
-            const float m1 = (float)fmax(E[1][0], E[1][2]);
-            const float m2 = (float)fmax(E[0][1], E[2][1]);
-            const float m3 = (float)fmax(fmax(E[0][0], E[0][2]), fmax(E[2][0], E[2][2]));
-            const float fG = isG ? fmaxf(m0, m3) : fmaxf(m1, m2);
-            const float fX = isG ? m1 : m0, fY = isG ? m2 : m3;
-            const float fm[3] = {xIsR ? fX : fY, fG, xIsR ? fY : fX};
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              if (fm[c] > M[p][c] + SLACK) {
-                const float s = __builtin_amdgcn_exp2f(M[p][c] - fm[c]);
-                num[p][c] *= s;
-                den[p][c] *= s;
-                M[p][c] = fm[c];
-              }
-            }
-            exponents();
-          }
-          const int vb = (ic - 1 - rr0) * rw + (jc - 1 - rc0);
-          float w[3][3], val[3][3];
-#pragma unroll
-          for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-              w[i][j] = __builtin_amdgcn_exp2f(d[i][j]);
-              val[i][j] = sRaw[vb + i * rw + j];
-            }
-          const float S0n = w[1][1] * val[1][1], S0d = w[1][1];
-          const float S1n = fmaf(w[1][0], val[1][0], w[1][2] * val[1][2]), S1d = w[1][0] + w[1][2];
-          const float S2n = fmaf(w[0][1], val[0][1], w[2][1] * val[2][1]), S2d = w[0][1] + w[2][1];
-          const float S3n = fmaf(w[0][0], val[0][0], w[0][2] * val[0][2]) +
-                            fmaf(w[2][0], val[2][0], w[2][2] * val[2][2]);
-          const float S3d = (w[0][0] + w[0][2]) + (w[2][0] + w[2][2]);
-          const float Gn = isG ? S0n + S3n : S1n + S2n, Gd = isG ? S0d + S3d : S1d + S2d;
-          const float Xn = isG ? S1n : S0n, Xd = isG ? S1d : S0d;
-          const float Yn = isG ? S2n : S3n, Yd = isG ? S2d : S3d;
-          const Acc ra = rho;
-          num[p][0] = fma(ra, (Acc)(xIsR ? Xn : Yn), num[p][0]);
-          den[p][0] = fma(ra, (Acc)(xIsR ? Xd : Yd), den[p][0]);
-          num[p][1] = fma(ra, (Acc)Gn, num[p][1]);
-          den[p][1] = fma(ra, (Acc)Gd, den[p][1]);
-          num[p][2] = fma(ra, (Acc)(xIsR ? Yn : Xn), num[p][2]);
-          den[p][2] = fma(ra, (Acc)(xIsR ? Yd : Xd), den[p][2]);
+          const int tyl = sTyRow[r] - tyA, k = tyl * ntx + txl;
+          if (k < s0 || k >= s1) continue;
+          pixel(p, r, tyl, sWin[k]);
         }
       }
-      if (whole || ++seg >= ntiles) break;
-      __syncthreads();  // the next alignment tile restages the buffers
     }
   }
 

@@ -187,7 +187,7 @@ def test_full_size_sampled_parity(config):
 @pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_every_tile_shape_matches(variant, monkeypatch):
     """Each compiled tile shape of the merge kernel gives the oracle's result,
-    including the per-alignment-tile fallback for a divergent motion field."""
+    including the per-alignment-tile windows of a divergent motion field."""
     monkeypatch.setenv("HMFSR_MERGE_VARIANT", str(variant))
     b = synth.make_burst(5, 96, 160, seed=900 + variant, scale=1.5, tile_size=16)
     f, m = b.numpy()
