@@ -597,46 +597,13 @@ __device__ int rh_tiles(int I, int n_out, int edge, int n_tiles_axis, int n_half
   }
   return cnt;
 }
-// Guide colour (R, mean of the greens, B) of half-res pixel (I, J), raw units.
-__device__ __forceinline__ void guide_px(const uint16_t* f, const Geometry& g, int I, int J, float (&c)[3]) {
-  const uint32_t top = *(const uint32_t*)(f + (size_t)(2 * I) * g.W + 2 * J);
-  const uint32_t bot = *(const uint32_t*)(f + (size_t)(2 * I + 1) * g.W + 2 * J);
-  const int q[4] = {(int)(top & 0xffff), (int)(top >> 16), (int)(bot & 0xffff), (int)(bot >> 16)};
-  c[0] = (float)q[g.red_pos];
-  c[1] = (float)(q[g.green_pos[0]] + q[g.green_pos[1]]) * 0.5f;
-  c[2] = (float)q[g.blue_pos];
-}
-
-// 3x3 box mean of the guide around (I, J), edge-clamped.
-__device__ __forceinline__ void box3(const uint16_t* f, const Geometry& g, int I, int J, float (&mu)[3]) {
-  float s[3] = {0.f, 0.f, 0.f};
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) {
-      float c[3];
-      guide_px(f, g, clampi(I + a - 1, 0, g.h - 1), clampi(J + b - 1, 0, g.w - 1), c);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) s[k] += c[k];
-    }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) mu[k] = s[k] * (1.f / 9.f);
-}
-
-// Its population variance about mu, summed in the same order as the forward.
-__device__ __forceinline__ void box3_var(const uint16_t* f, const Geometry& g, int I, int J,
-                                         const float (&mu)[3], float (&var)[3]) {
-  float s[3] = {0.f, 0.f, 0.f};
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) {
-      float c[3];
-      guide_px(f, g, clampi(I + a - 1, 0, g.h - 1), clampi(J + b - 1, 0, g.w - 1), c);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) s[k] = fmaf(c[k] - mu[k], c[k] - mu[k], s[k]);
-    }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) var[k] = s[k] * (1.f / 9.f);
-}
-
-__global__ __launch_bounds__(64, 4) void k_robust_bwd(const uint16_t* __restrict__ frames,
+// The guide statistics are read from the forward's maps: the 3x3 means of
+// every frame (rows of w + 2 with a replicated edge column each side) and the
+// base frame's 1 / sum sigma^2 (its sign carries the S.3 test, which the
+// clamped R here already reflects), so the adjoint differentiates exactly the
+// values the forward used.
+__global__ __launch_bounds__(64, 4) void k_robust_bwd(const float* __restrict__ gmu,
+                                                   const float* __restrict__ gref,
                                                    const float* __restrict__ motion,
                                                    const float* __restrict__ rmap,
                                                    const float* __restrict__ part_rh, Geometry g,
@@ -657,8 +624,10 @@ __global__ __launch_bounds__(64, 4) void k_robust_bwd(const uint16_t* __restrict
   __shared__ int sNc[RB + 4], sTc[RB + 4][3], sLc[RB + 4][3], sWc[RB + 4][3];
   const size_t plane = (size_t)g.h * g.w;
   const float* R = rmap + (size_t)n * plane;
-  const uint16_t* fref = frames + (size_t)g.ref * g.H * g.W;
-  const uint16_t* fn = frames + (size_t)n * g.H * g.W;
+  const int ws = g.w + 2;
+  const size_t mplane = (size_t)g.h * ws;
+  const float* mref = gmu + (size_t)g.ref * 3 * mplane;
+  const float* mfr = gmu + (size_t)n * 3 * mplane;
   const bool moving = prior_moving(motion, g, pc.m_th, n, ty, tx);
   const float s_used = moving ? pc.s1 : pc.s2;
   const float vlim = (float)(max(g.W, g.H) + 16);
@@ -737,15 +706,13 @@ __global__ __launch_bounds__(64, 4) void k_robust_bwd(const uint16_t* __restrict
           }
         const float Rv = sR[i - bi0 + 4][j - bj0 + 4];
         if (gR != 0.f && Rv > 0.f && Rv < 1.f) {  // unclamped R of eq. (5)
-          float mu_ref[3], var_ref[3];
-          box3(fref, g, i, j, mu_ref);
-          box3_var(fref, g, i, j, mu_ref, var_ref);
-          float den = 0.f;
+          const float inv = fabsf(gref[(size_t)i * g.w + j]);  // 1 / sum_c sigma_c^2, eq. (5)
+          float mu_ref[3], dmd2[3];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            float sig2, dmd2;
-            noise_md(rc, mu_ref[c], c, sig2, dmd2);
-            den += fmaxf(var_ref[c], sig2);
+            mu_ref[c] = mref[(size_t)c * mplane + (size_t)i * ws + j + 1];
+            float sig2;
+            noise_md(rc, mu_ref[c], c, sig2, dmd2[c]);
           }
           // mu_w: frame n's box mean sampled bilinearly at (j, i) + v / 2
           const double hx = (double)j + (double)vx * 0.5, hy = (double)i + (double)vy * 0.5;
@@ -754,22 +721,15 @@ __global__ __launch_bounds__(64, 4) void k_robust_bwd(const uint16_t* __restrict
           const int xa = clampi((int)fhx, 0, g.w - 1), xb = clampi((int)fhx + 1, 0, g.w - 1);
           const int ya = clampi((int)fhy, 0, g.h - 1), yb = clampi((int)fhy + 1, 0, g.h - 1);
           float top[3], bot[3], dtop[3], dbot[3];
-          {
-            float ma[3], mb[3];
-            box3(fn, g, ya, xa, ma);
-            box3(fn, g, ya, xb, mb);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              dtop[c] = mb[c] - ma[c];
-              top[c] = fmaf(fx, dtop[c], ma[c]);
-            }
-            box3(fn, g, yb, xa, ma);
-            box3(fn, g, yb, xb, mb);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              dbot[c] = mb[c] - ma[c];
-              bot[c] = fmaf(fx, dbot[c], ma[c]);
-            }
+          for (int c = 0; c < 3; ++c) {
+            const float* m = mfr + (size_t)c * mplane;
+            const float ma = m[(size_t)ya * ws + xa + 1], mb = m[(size_t)ya * ws + xb + 1];
+            const float mc = m[(size_t)yb * ws + xa + 1], md = m[(size_t)yb * ws + xb + 1];
+            dtop[c] = mb - ma;
+            top[c] = fmaf(fx, dtop[c], ma);
+            dbot[c] = md - mc;
+            bot[c] = fmaf(fx, dbot[c], mc);
           }
           float num = 0.f, dd[3], ddp[3], dmx[3], dmy[3];
 #pragma unroll
@@ -777,23 +737,21 @@ __global__ __launch_bounds__(64, 4) void k_robust_bwd(const uint16_t* __restrict
             const float mu_w = fmaf(fy, bot[c] - top[c], top[c]);
             dmx[c] = fmaf(fy, dbot[c] - dtop[c], dtop[c]);
             dmy[c] = bot[c] - top[c];
-            float sig2, dmd2;
-            noise_md(rc, mu_ref[c], c, sig2, dmd2);
             const float dms = mu_ref[c] - mu_w, dms2 = dms * dms;
-            const float q = 1.f / (dms2 + dmd2);
+            const float q = 1.f / (dms2 + dmd2[c]);
             dd[c] = dms * dms2 * q;  // eq. (6) shrinkage
-            ddp[c] = dms2 * (dms2 + 3.f * dmd2) * q * q;
+            ddp[c] = dms2 * (dms2 + 3.f * dmd2[c]) * q * q;
             num = fmaf(dd[c], dd[c], num);
           }
-          const float ex = __expf(-num / den);
+          const float ex = __expf(-num * inv);
           gt -= (double)gR;
           gs += (double)(gR * ex);
           const float g_r = -gR * s_used * ex;
           float gx = 0.f, gy = 0.f;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            // r = sum d^2 / den; d_ms = mu_ref - mu_w; mu_w sampled at u + v / 2
-            const float g_mu = -g_r * (2.f * dd[c] / den) * ddp[c];
+            // r = inv * sum d^2; d_ms = mu_ref - mu_w; mu_w sampled at u + v / 2
+            const float g_mu = -g_r * (2.f * dd[c] * inv) * ddp[c];
             gx = fmaf(g_mu, dmx[c], gx);
             gy = fmaf(g_mu, dmy[c], gy);
           }
@@ -971,8 +929,9 @@ hipError_t launch_robust_bwd(const Geometry& g, const RobustConsts& rc, const Pr
                              const BwdConsts& bc, const uint16_t* frames, const float* motion,
                              const BwdWork& w, hipStream_t stream) {
   const dim3 grid(g.TX, g.TY, g.n);
-  hipLaunchKernelGGL(k_robust_bwd, grid, dim3(64), 0, stream, frames, motion, w.rmap, w.part_rh, g, rc, pc,
-                     bc, w.part_rob);
+  (void)frames;
+  hipLaunchKernelGGL(k_robust_bwd, grid, dim3(64), 0, stream, w.fwd.gmu, w.fwd.gref, motion, w.rmap, w.part_rh, g,
+                     rc, pc, bc, w.part_rob);
   return hipGetLastError();
 }
 

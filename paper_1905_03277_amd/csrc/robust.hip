@@ -7,7 +7,7 @@
 //    aligned frame's guide (R, mean G, B; edge-replicated) into a map
 //    [n][3][h][w + 2] (the edge columns repeated once on either side, so that
 //    the two horizontal bilinear corners are adjacent whatever the clamping),
-//    one wave walking down a 62-column strip with the row sums in registers;
+//    one wave walking down a 64-column strip with the row sums in registers;
 //    k_base_stats writes the base frame's means and the reciprocal of its
 //    noise-corrected variance sum of eq. (5)-(6) into [h][w], negated where
 //    the S.3 test below finds a variance loss.
