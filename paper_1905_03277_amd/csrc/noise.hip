@@ -125,13 +125,18 @@ __global__ __launch_bounds__(kThreads) void k_frame_sum(const uint32_t* __restri
   }
 }
 
+// One wave adds the partial sums (integers: exact in any order).
 __global__ __launch_bounds__(64) void k_sum_parts(const unsigned long long* __restrict__ parts, int n,
                                                   unsigned long long* __restrict__ sum) {
-  if (threadIdx.x == 0) {
-    unsigned long long t = 0;
-    for (int i = 0; i < n; ++i) t += parts[i];
-    *sum = t;
+  unsigned long long t = 0;
+  for (int i = threadIdx.x; i < n; i += 64) t += parts[i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned lo = __shfl_xor((unsigned)(t & 0xffffffffull), off, 64);
+    const unsigned hi = __shfl_xor((unsigned)(t >> 32), off, 64);
+    t += ((unsigned long long)hi << 32) | lo;
   }
+  if (threadIdx.x == 0) *sum = t;
 }
 
 }  // namespace
