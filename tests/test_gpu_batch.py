@@ -63,6 +63,30 @@ def test_batch_equals_per_burst_bitwise_and_replays():
     assert not np.array_equal(want2[2], want[2])
 
 
+def test_batch_divergent_fields_bitwise_and_oracle():
+    """Displacement fields whose tiles are up to 40 px apart: the merge then
+    packs per-alignment-tile windows and the robustness reads its corners
+    directly; the persistent batch must still equal the per-burst launches
+    bit for bit, and the oracle within the forward tolerance."""
+    bursts = make_bursts()[:4]
+    rng = np.random.default_rng(71)
+    for b in bursts:
+        m = b.motion.numpy().copy()
+        m[1:] += rng.uniform(-40.0, 40.0, size=m[1:].shape).astype(np.float32)
+        m[b.desc.ref_frame] = 0
+        b.motion = torch.from_numpy(m)
+    args = as_args(bursts)
+    print("[case] batch of divergent fields", len(args), flush=True)
+    want = per_burst(args)
+    outs = torch_ops.merge_batch(args)
+    torch.cuda.synchronize()
+    for i, (o, w) in enumerate(zip(outs, want)):
+        np.testing.assert_array_equal(o.cpu().numpy(), w, err_msg=f"burst {i}")
+    b = bursts[0]
+    f, m = b.numpy()
+    assert_parity(outs[0].cpu().numpy(), om.merge(f, m, b.desc, b.tuning), "divergent batch burst 0")
+
+
 def test_batch_matches_oracle():
     bursts = make_bursts()
     args = as_args(bursts)
