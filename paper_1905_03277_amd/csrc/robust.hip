@@ -76,6 +76,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* p, siz
   return __builtin_amdgcn_make_buffer_rsrc((void*)p, 0, (int)(floats * 4), 0x00020000);
 }
 
+// One float at byte offset off.
+__device__ __forceinline__ float ld_one(__amdgpu_buffer_rsrc_t r, int off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
 // Two consecutive floats at byte offset off (one dwordx2 load).
 __device__ __forceinline__ float2 ld_pair(__amdgpu_buffer_rsrc_t r, int off) {
   const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
@@ -327,6 +332,7 @@ constexpr int TT = TT_X * TT_Y;
 constexpr int NF = 4;                               // aligned frames whose tile data are staged at once
 constexpr int PP = (RR_N + THREADS - 1) / THREADS;  // region pixels per thread
 constexpr int WCAP = 1152;  // mean-map window of one frame (per channel): every corner of the region
+constexpr int WPT = (WCAP + THREADS - 1) / THREADS;  // window entries per thread
 constexpr long long kRobustGroups = 6144;  // target workgroup count of one robustness launch
 
 struct RobustSmem {
@@ -449,13 +455,31 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
       const int X0 = sm.sBox[fl][0], Y0 = sm.sBox[fl][2];
       const int wx = -sm.sBox[fl][1] - X0 + 1, wy = -sm.sBox[fl][3] - Y0 + 1;
       if (wx * wy > WCAP) return false;  // uniform
-      const float* src = gmu + (size_t)n * 3 * mplane + (size_t)Y0 * ws + X0;
+      const float* fm = gmu + (size_t)n * 3 * mplane;
+      const __amdgpu_buffer_rsrc_t q0 = plane_rsrc(fm, mplane), q1 = plane_rsrc(fm + mplane, mplane),
+                                   q2 = plane_rsrc(fm + 2 * mplane, mplane);
+      const int base = Y0 * ws + X0;  // the window's first entry in the plane (below 2^29)
       const float inv = 1.f / (float)wx;
-      for (int k = tid; k < wx * wy; k += THREADS) {
-        const int r = split_row(k, inv);
-        const size_t o = (size_t)r * ws + (k - r * wx);
+      const int nw = wx * wy;
+      // every load of the copy in flight before the first store
+      float v[WPT][3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) sm.sW[c][k] = src[(size_t)c * mplane + o];
+      for (int i = 0; i < WPT; ++i) {
+        const int k = tid + i * THREADS;
+        if (k >= nw) continue;
+        const int r = split_row(k, inv);
+        const int off = (base + r * ws + (k - r * wx)) * 4;
+        v[i][0] = ld_one(q0, off);
+        v[i][1] = ld_one(q1, off);
+        v[i][2] = ld_one(q2, off);
+      }
+#pragma unroll
+      for (int i = 0; i < WPT; ++i) {
+        const int k = tid + i * THREADS;
+        if (k >= nw) continue;
+        sm.sW[0][k] = v[i][0];
+        sm.sW[1][k] = v[i][1];
+        sm.sW[2][k] = v[i][2];
       }
       return true;
     };
@@ -532,9 +556,9 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
         if (i >= oh || j >= ow) continue;
         const float* col = sm.sTmp + i * RB_W + j;
         const float mn = fminf(fminf(fminf(col[0], col[RB_W]), fminf(col[2 * RB_W], col[3 * RB_W])), col[4 * RB_W]);
-        const size_t o = (size_t)n * plane + (size_t)(I0 + i) * g.w + J0 + j;
-        rmin[o] = mn;
-        if (robust) robust[o] = sm.sR[(i + 2) * RR_W + j + 2];
+        const int o = (I0 + i) * g.w + J0 + j;  // below 2^28
+        rmin[(size_t)n * plane + o] = mn;
+        if (robust) robust[(size_t)n * plane + o] = sm.sR[(i + 2) * RR_W + j + 2];
       }
       // the next frame writes sR (read above before the last barrier) and,
       // after its first barrier, sTmp
@@ -543,7 +567,7 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
 }
 
 // Workgroup (tile, group of m_per aligned frames).
-__global__ __launch_bounds__(THREADS) void k_robust(const float* __restrict__ motion,
+__global__ __launch_bounds__(THREADS, 6) void k_robust(const float* __restrict__ motion,
                                                     const float* __restrict__ s_tile,
                                                     const unsigned char* __restrict__ mov, Geometry g,
                                                     RobustConsts rc, const float* __restrict__ gmu,
