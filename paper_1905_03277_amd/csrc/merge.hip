@@ -79,7 +79,7 @@ struct MergeSmem {
   float sLum[CP::LUMA];
   double sOm[3][CP::OM];
   float sRh[CP::RH];
-  int sRed[8];
+  int sRed[16];  // footprint reduction, two slots used by alternate frames
   int sRh0[4];
   Win sWin[CP::VT];    // per alignment tile, when the whole tile's window does not fit
   int sGrp[CP::VT + 1];  // groups of alignment tiles whose windows fit side by side
@@ -227,22 +227,17 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
     }
   }
 
+  if (tid < 8) sRed[8 * ((MODE == TILE_STREAM ? st.first : 0) & 1) + tid] = 0x7fffffff;
   for (int fi = MODE == TILE_STREAM ? st.first : 0; fi < g.n; ++fi) {
     const int n = fi == 0 ? g.ref : (fi <= g.ref ? fi - 1 : fi);
     const bool is_ref = n == g.ref;
     const uint16_t* f = frames + (size_t)n * g.H * g.W;
+    // the footprint reduction alternates between two slots: this frame's was
+    // reset during the previous frame, the next frame's is reset now (its
+    // last readers passed the barrier below)
+    int* red = sRed + 8 * (fi & 1);
     __syncthreads();
-    for (int k = tid; k < ntiles; k += THREADS) {
-      float2 v = make_float2(0.f, 0.f);
-      if (!is_ref) {
-        const int ky = k / ntx;
-        const float* p = motion + (((size_t)n * g.TY + tyA + ky) * g.TX + txA + (k - ky * ntx)) * 2;
-        // clamping keeps non-finite or huge vectors finite and changes no result
-        v = make_float2(fminf(fmaxf(p[0], -vlim), vlim), fminf(fmaxf(p[1], -vlim), vlim));
-      }
-      sV[k] = v;
-    }
-    if (tid < 8) sRed[tid] = 0x7fffffff;
+    if (tid < 8) sRed[8 * ((fi + 1) & 1) + tid] = 0x7fffffff;
     if (!is_ref) {
       const float* rm = rmin + (size_t)n * g.h * g.w;
       const float inv = 1.f / (float)rhw;
@@ -251,12 +246,18 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
         sRh[k] = rm[(size_t)(rhr0 + r) * g.w + rhc0 + k - r * rhw];
       }
     }
-    __syncthreads();
-    // footprint of each alignment tile: positions are monotonic in X and Y,
-    // so the tile's extreme pixels give its extreme window centres.
+    // per alignment tile: its displacement and its footprint (positions are
+    // monotonic in X and Y, so the tile's extreme pixels give its extreme
+    // window centres)
     for (int k = tid; k < ntiles; k += THREADS) {
       const int ky = k / ntx, kx = k - ky * ntx;
-      const float2 v = sV[k];
+      float2 v = make_float2(0.f, 0.f);
+      if (!is_ref) {
+        const float* p = motion + (((size_t)n * g.TY + tyA + ky) * g.TX + txA + kx) * 2;
+        // clamping keeps non-finite or huge vectors finite and changes no result
+        v = make_float2(fminf(fmaxf(p[0], -vlim), vlim), fminf(fmaxf(p[1], -vlim), vlim));
+      }
+      sV[k] = v;
       const double pxa = sX[sClo[kx]] + (double)v.x, pxb = sX[sChi[kx]] + (double)v.x;
       const double pya = sY[sRlo[ky]] + (double)v.y, pyb = sY[sRhi[ky]] + (double)v.y;
       Bounds b;
@@ -269,10 +270,10 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
       b.hi0 = (int)floor(pya * 0.5 - 0.5);
       b.hi1 = (int)floor(pyb * 0.5 - 0.5);
       sTB[k] = b;
-      atomicMin(&sRed[0], b.jc0); atomicMin(&sRed[1], -b.jc1);
-      atomicMin(&sRed[2], b.ic0); atomicMin(&sRed[3], -b.ic1);
-      atomicMin(&sRed[4], b.hj0); atomicMin(&sRed[5], -b.hj1);
-      atomicMin(&sRed[6], b.hi0); atomicMin(&sRed[7], -b.hi1);
+      atomicMin(&red[0], b.jc0); atomicMin(&red[1], -b.jc1);
+      atomicMin(&red[2], b.ic0); atomicMin(&red[3], -b.ic1);
+      atomicMin(&red[4], b.hj0); atomicMin(&red[5], -b.hj1);
+      atomicMin(&red[6], b.hi0); atomicMin(&red[7], -b.hi1);
     }
     __syncthreads();
 
@@ -283,8 +284,8 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
     Win W;
     {
       Bounds bd;
-      bd.jc0 = sRed[0]; bd.jc1 = -sRed[1]; bd.ic0 = sRed[2]; bd.ic1 = -sRed[3];
-      bd.hj0 = sRed[4]; bd.hj1 = -sRed[5]; bd.hi0 = sRed[6]; bd.hi1 = -sRed[7];
+      bd.jc0 = red[0]; bd.jc1 = -red[1]; bd.ic0 = red[2]; bd.ic1 = -red[3];
+      bd.hj0 = red[4]; bd.hj1 = -red[5]; bd.hi0 = red[6]; bd.hi1 = -red[7];
       W = make_win(bd, g);
     }
     // uniform: every thread read the same bounds
