@@ -152,6 +152,9 @@ typedef struct {
  *          saved the normaliser is accumulated in float64 and the 64 x 16
  *          tile shape is used, so `out` can differ from a call without it in
  *          the last bits.
+ * The internal workspace holds per-frame maps of the base half-resolution
+ * grid (the guide's 3x3 means and R_hat): about 16 bytes per half-resolution
+ * pixel and frame.
  * Returns HMFSR_OK, or an error code with nothing enqueued.
  */
 hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
@@ -178,7 +181,9 @@ hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
  *            base frame's vectors are ignored by the merge and get 0.
  * Kernel weights are recomputed, not stored. Sums are taken in a fixed order:
  * repeated calls give identical bits. The internal workspace grows to about
- * 40 bytes per output pixel plus 48 more when saved is NULL.
+ * 20 bytes per half-resolution pixel and frame (the forward's maps and R)
+ * plus 3 bytes per output pixel and frame (per-tile partials), and 48 bytes
+ * per output pixel more when saved is NULL.
  */
 hmfsr_status hmfsr_merge_backward(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
                                   const uint16_t* frames, const float* motion,
