@@ -143,6 +143,29 @@ __device__ __forceinline__ void stage_block(int32_t* tpl, int ldt, int rows, int
   }
 }
 
+// Sum of squared differences of one block row of W pixels, every LDS read of
+// the row issued before the arithmetic. Values are integers: with float64
+// sums below 2^53 (or 64-bit integers) the order does not matter.
+template <int W, bool EXACT_F64>
+__device__ __forceinline__ void row_ssd(const int32_t* tr, const int32_t* rr, double& acc, unsigned long long& ssd) {
+  int tv[W], rv[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    tv[c] = tr[c];
+    rv[c] = rr[c];
+  }
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    if (EXACT_F64) {
+      const double d = (double)(rv[c] - tv[c]);
+      acc = fma(d, d, acc);
+    } else {
+      const long long d = (long long)(rv[c] - tv[c]);
+      ssd += (unsigned long long)(d * d);
+    }
+  }
+}
+
 // Candidate key packed for lane exchanges: cost, then (squared offset from
 // the guess) * 2^16 + scan index; the lexicographic minimum wins.
 struct PKey {
@@ -215,7 +238,21 @@ __global__ __launch_bounds__(256) void k_align_match(const int32_t* __restrict__
       for (int k = l; k < K; k += LPG) {
         const int dyi = k / D, dxi = k - (k / D) * D;
         unsigned long long ssd = 0;
-        if (EXACT_F64) {
+        if (nbx == 4 || nbx == 8 || nbx == 16 || nbx == 32) {  // full-width rows, unrolled
+          double acc = 0.0;
+          for (int r = 0; r < nby; ++r) {
+            const int32_t* tr = tpl + r * B;
+            const int32_t* rr = reg + (r + dyi) * E + dxi;
+            if (nbx == 8) {
+              row_ssd<8, EXACT_F64>(tr, rr, acc, ssd);
+            } else if (nbx == 4) {
+              row_ssd<4, EXACT_F64>(tr, rr, acc, ssd);
+            } else {
+              for (int c0 = 0; c0 < nbx; c0 += 8) row_ssd<8, EXACT_F64>(tr + c0, rr + c0, acc, ssd);
+            }
+          }
+          if (EXACT_F64) ssd = (unsigned long long)acc;
+        } else if (EXACT_F64) {
           double acc = 0.0;
           for (int r = 0; r < nby; ++r) {
             const int32_t* tr = tpl + r * B;
