@@ -414,20 +414,24 @@ __device__ __forceinline__ void tile_sums(const int32_t* SB, const int32_t* SM, 
       m1[k] = (double)m[SWW + k];
     }
     int bu = b[0], bc = b[SWW];
-    for (int r = 0; r < WH; ++r) {
-      const int32_t* m2p = m + (r + 2) * SWW;
-      const double m2[3] = {(double)m2p[0], (double)m2p[1], (double)m2p[2]};
+    double m2[3];
+    // window row r: the frame rows r .. r + 2 in ra, rb, rc (rc loaded here),
+    // the base column's rows r, r + 1 in bu, bc (r + 2 loaded here)
+    auto step = [&](int r, const double (&ra)[3], const double (&rb)[3], double (&rc)[3]) {
+      const int32_t* mp = m + (r + 2) * SWW;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) rc[k] = (double)mp[k];
       const int32_t* brow = b + (r + 1) * SWW;
       const int bd = b[(r + 2) * SWW];
       const double dx = (double)(brow[1] - brow[-1]), dy = (double)(bd - bu);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        acc[k] = fma(dx, m0[k], acc[k]);
-        acc[3 + k] = fma(dx, m1[k], acc[3 + k]);
-        acc[6 + k] = fma(dx, m2[k], acc[6 + k]);
-        acc[9 + k] = fma(dy, m0[k], acc[9 + k]);
-        acc[12 + k] = fma(dy, m1[k], acc[12 + k]);
-        acc[15 + k] = fma(dy, m2[k], acc[15 + k]);
+        acc[k] = fma(dx, ra[k], acc[k]);
+        acc[3 + k] = fma(dx, rb[k], acc[3 + k]);
+        acc[6 + k] = fma(dx, rc[k], acc[6 + k]);
+        acc[9 + k] = fma(dy, ra[k], acc[9 + k]);
+        acc[12 + k] = fma(dy, rb[k], acc[12 + k]);
+        acc[15 + k] = fma(dy, rc[k], acc[15 + k]);
       }
       if (BASE) {
         const double tv = (double)bc;
@@ -437,13 +441,30 @@ __device__ __forceinline__ void tile_sums(const int32_t* SB, const int32_t* SM, 
         acc[21] = fma(dx, dy, acc[21]);
         acc[22] = fma(dy, dy, acc[22]);
       }
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        m0[k] = m1[k];
-        m1[k] = m2[k];
-      }
       bu = bc;
       bc = bd;
+    };
+    if constexpr (LPG == 16) {
+      // three rows per pass: the three row registers rotate by name, not by
+      // copies (the wider groups keep the plain loop, whose registers allow a
+      // fourth wave per SIMD)
+      int r = 0;
+      for (; r + 3 <= WH; r += 3) {
+        step(r, m0, m1, m2);
+        step(r + 1, m1, m2, m0);
+        step(r + 2, m2, m0, m1);
+      }
+      if (r < WH) step(r++, m0, m1, m2);
+      if (r < WH) step(r, m1, m2, m0);
+    } else {
+      for (int r = 0; r < WH; ++r) {
+        step(r, m0, m1, m2);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          m0[k] = m1[k];
+          m1[k] = m2[k];
+        }
+      }
     }
   }
 }
