@@ -333,12 +333,29 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
       };
       // stage raw footprint, quad sums, Omega
       if (whole) {
-        const int rc0 = W.rc0, rr0 = W.rr0, rw = W.rw, rh = W.rh;
+        // loads in batches of RB in flight before their stores: each reads
+        // the clamped position and the zero outside the frame is chosen after
+        constexpr int RB = 4;
+        const int rc0 = W.rc0, rr0 = W.rr0, rw = W.rw, nr = W.rw * W.rh;
         const float inv = 1.f / (float)rw;
-        for (int k = tid; k < rw * rh; k += THREADS) {
-          const int r = split_row(k, inv), c = k - r * rw;
-          const int gr = rr0 + r, gc = rc0 + c;
-          sRaw[k] = (gr >= 0 && gr < g.H && gc >= 0 && gc < g.W) ? (float)f[(size_t)gr * g.W + gc] : 0.f;
+        for (int k0 = tid; k0 < nr; k0 += RB * THREADS) {
+          uint32_t rv[RB];
+          bool rin[RB];
+#pragma unroll
+          for (int i = 0; i < RB; ++i) {
+            // entries past the window read its last one (no branch, so the
+            // loads stay in flight together) and are not stored
+            const int k = min(k0 + i * THREADS, nr - 1);
+            const int r = split_row(k, inv), c = k - r * rw;
+            const int gr = rr0 + r, gc = rc0 + c;
+            rin[i] = gr >= 0 && gr < g.H && gc >= 0 && gc < g.W;
+            rv[i] = f[(unsigned)(clampi(gr, 0, g.H - 1) * g.W + clampi(gc, 0, g.W - 1))];  // below 2^30
+          }
+#pragma unroll
+          for (int i = 0; i < RB; ++i) {
+            const int k = k0 + i * THREADS;
+            if (k < nr) sRaw[k] = rin[i] ? (float)rv[i] : 0.f;
+          }
         }
       } else {
         const int n_e = entries(0);
