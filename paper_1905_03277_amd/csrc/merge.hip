@@ -359,11 +359,24 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
         }
       } else {
         const int n_e = entries(0);
-        for (int e = tid; e < n_e; e += THREADS) {
-          const Win& w = sWin[find(e, 0)];
-          const int k = e - w.raw, r = k / w.rw, c = k - r * w.rw;
-          const int gr = w.rr0 + r, gc = w.rc0 + c;
-          sRaw[e] = (gr >= 0 && gr < g.H && gc >= 0 && gc < g.W) ? (float)f[(size_t)gr * g.W + gc] : 0.f;
+        constexpr int RB = 4;  // as above: batches of branch-free loads
+        for (int e0 = tid; e0 < n_e; e0 += RB * THREADS) {
+          uint32_t rv[RB];
+          bool rin[RB];
+#pragma unroll
+          for (int i = 0; i < RB; ++i) {
+            const int e = min(e0 + i * THREADS, n_e - 1);
+            const Win& w = sWin[find(e, 0)];
+            const int k = e - w.raw, r = k / w.rw, c = k - r * w.rw;
+            const int gr = w.rr0 + r, gc = w.rc0 + c;
+            rin[i] = gr >= 0 && gr < g.H && gc >= 0 && gc < g.W;
+            rv[i] = f[(unsigned)(clampi(gr, 0, g.H - 1) * g.W + clampi(gc, 0, g.W - 1))];
+          }
+#pragma unroll
+          for (int i = 0; i < RB; ++i) {
+            const int e = e0 + i * THREADS;
+            if (e < n_e) sRaw[e] = rin[i] ? (float)rv[i] : 0.f;
+          }
         }
       }
       __syncthreads();
