@@ -239,12 +239,22 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
     __syncthreads();
     if (tid < 8) sRed[8 * ((fi + 1) & 1) + tid] = 0x7fffffff;
     if (!is_ref) {
+      // every load of the window in flight before its stores (entries past
+      // the window re-read its last one and are not stored)
+      constexpr int RHT = (CP::RH + THREADS - 1) / THREADS;
       const float* rm = rmin + (size_t)n * g.h * g.w;
       const float inv = 1.f / (float)rhw;
-      for (int k = tid; k < rhw * rhh; k += THREADS) {
+      const int nrh = rhw * rhh;
+      float rhv[RHT];
+#pragma unroll
+      for (int i = 0; i < RHT; ++i) {
+        const int k = min(tid + i * THREADS, nrh - 1);
         const int r = split_row(k, inv);
-        sRh[k] = rm[(size_t)(rhr0 + r) * g.w + rhc0 + k - r * rhw];
+        rhv[i] = rm[(unsigned)((rhr0 + r) * g.w + rhc0 + k - r * rhw)];  // below 2^28
       }
+#pragma unroll
+      for (int i = 0; i < RHT; ++i)
+        if (tid + i * THREADS < nrh) sRh[tid + i * THREADS] = rhv[i];
     }
     // per alignment tile: its displacement and its footprint (positions are
     // monotonic in X and Y, so the tile's extreme pixels give its extreme
