@@ -237,12 +237,22 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
     }
     if (tid < 8) sm.sRed[tid] = 0x7fffffff;
     if (!is_ref) {
+      // every load of the window in flight before its stores (entries past
+      // the window re-read its last one and are not stored)
+      constexpr int RHT = (BCP::RH + BTHREADS - 1) / BTHREADS;
       const float* rm = rmin + (size_t)n * g.h * g.w;
       const float inv = 1.f / (float)rhw;
-      for (int k = tid; k < rhw * rhh; k += BTHREADS) {
+      const int nrh = rhw * rhh;
+      float rhv[RHT];
+#pragma unroll
+      for (int i = 0; i < RHT; ++i) {
+        const int k = min(tid + i * BTHREADS, nrh - 1);
         const int r = split_row(k, inv);
-        sm.sRh[k] = rm[(size_t)(rhr0 + r) * g.w + rhc0 + k - r * rhw];
+        rhv[i] = rm[(unsigned)((rhr0 + r) * g.w + rhc0 + k - r * rhw)];  // below 2^28
       }
+#pragma unroll
+      for (int i = 0; i < RHT; ++i)
+        if (tid + i * BTHREADS < nrh) sm.sRh[tid + i * BTHREADS] = rhv[i];
     }
 #pragma unroll
     for (int p = 0; p < BPX; ++p) {
@@ -299,11 +309,27 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
         continue;
       }
       {
+        // loads in batches of four in flight before their stores: each reads
+        // the clamped position and the zero outside the frame is chosen after
+        constexpr int RB = 4;
         const float inv = 1.f / (float)rw;
-        for (int k = tid; k < rw * rh; k += BTHREADS) {
-          const int r = split_row(k, inv), c = k - r * rw;
-          const int gr = rr0 + r, gc = rc0 + c;
-          sm.sRaw[k] = (gr >= 0 && gr < g.H && gc >= 0 && gc < g.W) ? (float)f[(size_t)gr * g.W + gc] : 0.f;
+        const int nr = rw * rh;
+        for (int k0 = tid; k0 < nr; k0 += RB * BTHREADS) {
+          uint32_t rv[RB];
+          bool rin[RB];
+#pragma unroll
+          for (int i = 0; i < RB; ++i) {
+            const int k = min(k0 + i * BTHREADS, nr - 1);
+            const int r = split_row(k, inv), c = k - r * rw;
+            const int gr = rr0 + r, gc = rc0 + c;
+            rin[i] = gr >= 0 && gr < g.H && gc >= 0 && gc < g.W;
+            rv[i] = f[(unsigned)(clampi(gr, 0, g.H - 1) * g.W + clampi(gc, 0, g.W - 1))];  // below 2^30
+          }
+#pragma unroll
+          for (int i = 0; i < RB; ++i) {
+            const int k = k0 + i * BTHREADS;
+            if (k < nr) sm.sRaw[k] = rin[i] ? (float)rv[i] : 0.f;
+          }
         }
       }
       __syncthreads();
