@@ -51,16 +51,6 @@ __device__ __forceinline__ uint32_t quad_at(uint32_t top, uint32_t bot, int pos)
   return ((pos & 2) ? bot : top) >> ((pos & 1) * 16) & 0xffffu;
 }
 
-// Guide pixel (I, J) of a frame in raw units: R, mean of the two greens, B.
-__device__ __forceinline__ void load_guide(const uint16_t* f, const Geometry& g, int I, int J,
-                                           float& r, float& gr, float& b) {
-  const uint32_t top = *(const uint32_t*)(f + (size_t)(2 * I) * g.W + 2 * J);
-  const uint32_t bot = *(const uint32_t*)(f + (size_t)(2 * I + 1) * g.W + 2 * J);
-  r = (float)quad_at(top, bot, g.red_pos);
-  gr = (float)(quad_at(top, bot, g.green_pos[0]) + quad_at(top, bot, g.green_pos[1])) * 0.5f;
-  b = (float)quad_at(top, bot, g.blue_pos);
-}
-
 __host__ __device__ __forceinline__ int robust_tiles_x_(const Geometry& g) { return (g.w + RB_W - 1) / RB_W; }
 __host__ __device__ __forceinline__ int robust_tiles_y_(const Geometry& g) { return (g.h + RB_H - 1) / RB_H; }
 __host__ __device__ __forceinline__ int means_tiles_x(const Geometry& g) { return (g.w + GM_W - 1) / GM_W; }
@@ -109,6 +99,8 @@ __host__ __device__ __forceinline__ int fm_bands(const Geometry& g) {
   return (g.h + FM_ROWS * FM_WAVES - 1) / (FM_ROWS * FM_WAVES);
 }
 
+// Guide pixel of one quad (its two 32-bit rows) in raw units: R, mean of the
+// two greens, B.
 __device__ __forceinline__ void guide_of(uint32_t top, uint32_t bot, const Geometry& g, float (&v)[3]) {
   v[0] = (float)quad_at(top, bot, g.red_pos);
   v[1] = (float)(quad_at(top, bot, g.green_pos[0]) + quad_at(top, bot, g.green_pos[1])) * 0.5f;
@@ -214,14 +206,27 @@ __device__ __forceinline__ void base_stats_tile(const uint16_t* __restrict__ fra
   const int gy0 = I0 - 2, gx0 = J0 - 2;
   const uint16_t* f = frames + (size_t)g.ref * g.H * g.W;
   {
+    // every quad of the window loaded before the first store
+    constexpr int GPT = (GW_N + THREADS - 1) / THREADS;
     const float ginv = 1.f / (float)GW_W;
-    for (int k = tid; k < GW_N; k += THREADS) {
+    uint32_t top[GPT], bot[GPT];
+#pragma unroll
+    for (int i = 0; i < GPT; ++i) {
+      const int k = min(tid + i * THREADS, GW_N - 1);
       const int r = split_row(k, ginv), c = k - r * GW_W;
-      float vr, vg, vb;
-      load_guide(f, g, clampi(gy0 + r, 0, g.h - 1), clampi(gx0 + c, 0, g.w - 1), vr, vg, vb);
-      sm.G[0][k] = vr;
-      sm.G[1][k] = vg;
-      sm.G[2][k] = vb;
+      const int I = clampi(gy0 + r, 0, g.h - 1), J = clampi(gx0 + c, 0, g.w - 1);
+      top[i] = *(const uint32_t*)(f + (size_t)(2 * I) * g.W + 2 * J);
+      bot[i] = *(const uint32_t*)(f + (size_t)(2 * I + 1) * g.W + 2 * J);
+    }
+#pragma unroll
+    for (int i = 0; i < GPT; ++i) {
+      const int k = tid + i * THREADS;
+      if (k >= GW_N) continue;
+      float v[3];
+      guide_of(top[i], bot[i], g, v);
+      sm.G[0][k] = v[0];
+      sm.G[1][k] = v[1];
+      sm.G[2][k] = v[2];
     }
   }
   __syncthreads();
