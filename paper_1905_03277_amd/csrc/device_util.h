@@ -7,6 +7,10 @@ namespace hmfsr {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// a * b for |a|, |b| < 2^23 (window offsets and widths, LDS indices): the
+// full-rate 24-bit multiply instead of the quarter-rate 32-bit one.
+__device__ __forceinline__ int mul24(int a, int b) { return __mul24(a, b); }
+
 // Minimum over the 64 lanes of a wave.
 __device__ __forceinline__ int wave_min(int v) {
 #pragma unroll

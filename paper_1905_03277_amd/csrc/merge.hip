@@ -250,7 +250,7 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
       for (int i = 0; i < RHT; ++i) {
         const int k = min(tid + i * THREADS, nrh - 1);
         const int r = split_row(k, inv);
-        rhv[i] = rm[(unsigned)((rhr0 + r) * g.w + rhc0 + k - r * rhw)];  // below 2^28
+        rhv[i] = rm[(unsigned)((rhr0 + r) * g.w + rhc0 + k - mul24(r, rhw))];  // below 2^28
       }
 #pragma unroll
       for (int i = 0; i < RHT; ++i)
@@ -356,7 +356,7 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
             // entries past the window read its last one (no branch, so the
             // loads stay in flight together) and are not stored
             const int k = min(k0 + i * THREADS, nr - 1);
-            const int r = split_row(k, inv), c = k - r * rw;
+            const int r = split_row(k, inv), c = k - mul24(r, rw);
             const int gr = rr0 + r, gc = rc0 + c;
             rin[i] = gr >= 0 && gr < g.H && gc >= 0 && gc < g.W;
             rv[i] = f[(unsigned)(clampi(gr, 0, g.H - 1) * g.W + clampi(gc, 0, g.W - 1))];  // below 2^30
@@ -377,7 +377,7 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
           for (int i = 0; i < RB; ++i) {
             const int e = min(e0 + i * THREADS, n_e - 1);
             const Win& w = sWin[find(e, 0)];
-            const int k = e - w.raw, r = k / w.rw, c = k - r * w.rw;
+            const int k = e - w.raw, r = k / w.rw, c = k - mul24(r, w.rw);
             const int gr = w.rr0 + r, gc = w.rc0 + c;
             rin[i] = gr >= 0 && gr < g.H && gc >= 0 && gc < g.W;
             rv[i] = f[(unsigned)(clampi(gr, 0, g.H - 1) * g.W + clampi(gc, 0, g.W - 1))];
@@ -394,16 +394,16 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
         const int rc0 = W.rc0, rr0 = W.rr0, rw = W.rw, lc0 = W.lc0, lr0 = W.lr0, lw = W.lw, lh = W.lh;
         const float inv = 1.f / (float)lw;
         for (int k = tid; k < lw * lh; k += THREADS) {
-          const int r = split_row(k, inv), c = k - r * lw;
-          const int o = (2 * (lr0 + r) - rr0) * rw + 2 * (lc0 + c) - rc0;
+          const int r = split_row(k, inv), c = k - mul24(r, lw);
+          const int o = mul24(2 * (lr0 + r) - rr0, rw) + 2 * (lc0 + c) - rc0;
           sLum[k] = (sRaw[o] + sRaw[o + 1]) + (sRaw[o + rw] + sRaw[o + rw + 1]);  // exact
         }
       } else {
         const int n_e = entries(1);
         for (int e = tid; e < n_e; e += THREADS) {
           const Win& w = sWin[find(e, 1)];
-          const int k = e - w.lum, r = k / w.lw, c = k - r * w.lw;
-          const int o = w.raw + (2 * (w.lr0 + r) - w.rr0) * w.rw + 2 * (w.lc0 + c) - w.rc0;
+          const int k = e - w.lum, r = k / w.lw, c = k - mul24(r, w.lw);
+          const int o = w.raw + mul24(2 * (w.lr0 + r) - w.rr0, w.rw) + 2 * (w.lc0 + c) - w.rc0;
           sLum[e] = (sRaw[o] + sRaw[o + 1]) + (sRaw[o + w.rw] + sRaw[o + w.rw + 1]);  // exact
         }
       }
@@ -415,7 +415,7 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
           float l[3][3];
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
-            const int row = w.lum + (clampi(I + a - 1, 0, g.h - 1) - w.lr0) * w.lw;
+            const int row = w.lum + mul24(clampi(I + a - 1, 0, g.h - 1) - w.lr0, w.lw);
 #pragma unroll
             for (int bb = 0; bb < 3; ++bb) l[a][bb] = sLum[row + clampi(J + bb - 1, 0, g.w - 1) - w.lc0];
           }
@@ -429,14 +429,14 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
           const float inv = 1.f / (float)W.ow;
           for (int k = tid; k < W.ow * W.oh; k += THREADS) {
             const int r = split_row(k, inv);
-            omega_at(k, W, r, k - r * W.ow);
+            omega_at(k, W, r, k - mul24(r, W.ow));
           }
         } else {
           const int n_e = entries(2);
           for (int e = tid; e < n_e; e += THREADS) {
             const Win& w = sWin[find(e, 2)];
             const int k = e - w.om, r = k / w.ow;
-            omega_at(e, w, r, k - r * w.ow);
+            omega_at(e, w, r, k - mul24(r, w.ow));
           }
         }
       }
@@ -453,7 +453,7 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
               rho = top + ri.fy * (bot - top);
               if (!(rho > 0.f)) return;
             }
-            const float2 v = sV[tyl * ntx + txl];
+            const float2 v = sV[mul24(tyl, ntx) + txl];
             const double px = X + (double)v.x, py = sY[r] + (double)v.y;
             const double fjc = floor(px), fic = floor(py);
             const double frx = px - fjc, fry = py - fic;  // exact
@@ -463,7 +463,7 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
             const double fhj = floor(hx), fhi = floor(hy);
             const double fx = hx - fhj, fy = hy - fhi;
             const int ow = wg.ow;
-            const int ob = wg.om + ((int)fhi - wg.or0) * ow + ((int)fhj - wg.oc0);
+            const int ob = wg.om + mul24((int)fhi - wg.or0, ow) + ((int)fhj - wg.oc0);
             double O[3];
   #pragma unroll
             for (int e = 0; e < 3; ++e) {
@@ -550,7 +550,7 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
               exponents();
             }
             const int rw = wg.rw;
-            const int vb = wg.raw + (ic - 1 - wg.rr0) * rw + (jc - 1 - wg.rc0);
+            const int vb = wg.raw + mul24(ic - 1 - wg.rr0, rw) + (jc - 1 - wg.rc0);
             float w[3][3], val[3][3];
   #pragma unroll
             for (int i = 0; i < 3; ++i)
@@ -587,7 +587,7 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
         for (int p = 0; p < PX; ++p) {
           const int r = wave * PX + p;
           if (r >= nrow) continue;
-          const int tyl = sTyRow[r] - tyA, k = tyl * ntx + txl;
+          const int tyl = sTyRow[r] - tyA, k = mul24(tyl, ntx) + txl;
           if (k < s0 || k >= s1) continue;
           pixel(p, r, tyl, sWin[k]);
         }
