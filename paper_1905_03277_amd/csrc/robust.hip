@@ -473,7 +473,7 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
         const int k = tid + i * THREADS;
         if (k >= nw) continue;
         const int r = split_row(k, inv);
-        const int off = (base + r * ws + (k - r * wx)) * 4;
+        const int off = (base + mul24(r, ws) + (k - mul24(r, wx))) * 4;
         v[i][0] = ld_one(q0, off);
         v[i][1] = ld_one(q1, off);
         v[i][2] = ld_one(q2, off);
@@ -509,7 +509,7 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
         const int x0 = clampi(Jc[q] + of.x, -1, g.w - 1) + 1;
         float mm[3][4];
         if (staged) {
-          const int ia = (ya - Y0) * wx + x0 - X0, ib = (yb - Y0) * wx + x0 - X0;
+          const int ia = mul24(ya - Y0, wx) + x0 - X0, ib = mul24(yb - Y0, wx) + x0 - X0;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             mm[c][0] = sm.sW[c][ia];
