@@ -103,8 +103,10 @@ struct StreamState {
   int first;
 };
 
-// One 64 x MH output tile (tile_x, tile_y) of one burst.
-template <int MH, int THREADS, int MODE>
+// One 64 x MH output tile (tile_x, tile_y) of one burst. RB: raw-footprint
+// loads per thread in flight at once (one batch for most windows when the
+// window holds more than 4 x THREADS samples, see wide_raw_window).
+template <int MH, int THREADS, int MODE, int RB>
 __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
                                            const float* __restrict__ motion,
                                            const float* __restrict__ rmin, const Geometry& g,
@@ -115,6 +117,7 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
   constexpr int WAVES = THREADS / 64;
   constexpr int PX = MH / WAVES;
   static_assert(PX * WAVES == MH, "tile rows must split evenly over the waves");
+  static_assert(Caps<MH>::VT <= THREADS, "one alignment tile per thread at most");
   using CP = Caps<MH>;
   double* sX = sm.sX;
   double* sY = sm.sY;
@@ -238,6 +241,14 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
     int* red = sRed + 8 * (fi & 1);
     __syncthreads();
     if (tid < 8) sRed[8 * ((fi + 1) & 1) + tid] = 0x7fffffff;
+    // this thread's alignment tile (at most one: ntiles <= VT <= THREADS):
+    // its displacement loads in flight together with the R_hat window's
+    const int ky = tid < ntiles ? tid / ntx : 0, kx = tid - ky * ntx;
+    float2 v = make_float2(0.f, 0.f);
+    if (tid < ntiles && !is_ref) {
+      const float* p = motion + (((size_t)n * g.TY + tyA + ky) * g.TX + txA + kx) * 2;
+      v = make_float2(p[0], p[1]);
+    }
     if (!is_ref) {
       // every load of the window in flight before its stores (entries past
       // the window re-read its last one and are not stored)
@@ -259,14 +270,10 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
     // per alignment tile: its displacement and its footprint (positions are
     // monotonic in X and Y, so the tile's extreme pixels give its extreme
     // window centres)
-    for (int k = tid; k < ntiles; k += THREADS) {
-      const int ky = k / ntx, kx = k - ky * ntx;
-      float2 v = make_float2(0.f, 0.f);
-      if (!is_ref) {
-        const float* p = motion + (((size_t)n * g.TY + tyA + ky) * g.TX + txA + kx) * 2;
-        // clamping keeps non-finite or huge vectors finite and changes no result
-        v = make_float2(fminf(fmaxf(p[0], -vlim), vlim), fminf(fmaxf(p[1], -vlim), vlim));
-      }
+    if (tid < ntiles) {
+      const int k = tid;
+      // clamping keeps non-finite or huge vectors finite and changes no result
+      v = make_float2(fminf(fmaxf(v.x, -vlim), vlim), fminf(fmaxf(v.y, -vlim), vlim));
       sV[k] = v;
       const double pxa = sX[sClo[kx]] + (double)v.x, pxb = sX[sChi[kx]] + (double)v.x;
       const double pya = sY[sRlo[ky]] + (double)v.y, pyb = sY[sRhi[ky]] + (double)v.y;
@@ -345,7 +352,6 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
       if (whole) {
         // loads in batches of RB in flight before their stores: each reads
         // the clamped position and the zero outside the frame is chosen after
-        constexpr int RB = 4;
         const int rc0 = W.rc0, rr0 = W.rr0, rw = W.rw, nr = W.rw * W.rh;
         const float inv = 1.f / (float)rw;
         for (int k0 = tid; k0 < nr; k0 += RB * THREADS) {
@@ -369,12 +375,12 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
         }
       } else {
         const int n_e = entries(0);
-        constexpr int RB = 4;  // as above: batches of branch-free loads
-        for (int e0 = tid; e0 < n_e; e0 += RB * THREADS) {
-          uint32_t rv[RB];
-          bool rin[RB];
+        constexpr int MB = 4;  // batches of branch-free loads, as above
+        for (int e0 = tid; e0 < n_e; e0 += MB * THREADS) {
+          uint32_t rv[MB];
+          bool rin[MB];
 #pragma unroll
-          for (int i = 0; i < RB; ++i) {
+          for (int i = 0; i < MB; ++i) {
             const int e = min(e0 + i * THREADS, n_e - 1);
             const Win& w = sWin[find(e, 0)];
             const int k = e - w.raw, r = k / w.rw, c = k - mul24(r, w.rw);
@@ -383,7 +389,7 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
             rv[i] = f[(unsigned)(clampi(gr, 0, g.H - 1) * g.W + clampi(gc, 0, g.W - 1))];
           }
 #pragma unroll
-          for (int i = 0; i < RB; ++i) {
+          for (int i = 0; i < MB; ++i) {
             const int e = e0 + i * THREADS;
             if (e < n_e) sRaw[e] = rin[i] ? (float)rv[i] : 0.f;
           }
@@ -636,18 +642,19 @@ constexpr int waves_per_simd() {
   return (MH / (THREADS / 64) <= 4) ? 4 : 2;
 }
 
-template <int MH, int THREADS>
+template <int MH, int THREADS, int RB>
 __global__ __launch_bounds__(THREADS, (waves_per_simd<MH, THREADS>())) void k_merge(
     const uint16_t* __restrict__ frames, const float* __restrict__ motion,
     const float* __restrict__ rmin, Geometry g, MergeConsts mc, float* __restrict__ out) {
   __shared__ MergeSmem<MH> sm;
   const int tiles_x = (g.OW + MW - 1) / MW, n = tiles_x * ((g.OH + MH - 1) / MH);
   const int t = xcd_tile(blockIdx.x, n);
-  merge_tile<MH, THREADS, TILE_PLAIN>(frames, motion, rmin, g, mc, out, nullptr, StreamState{nullptr, nullptr, 0},
+  merge_tile<MH, THREADS, TILE_PLAIN, RB>(frames, motion, rmin, g, mc, out, nullptr, StreamState{nullptr, nullptr, 0},
                                       t % tiles_x, t / tiles_x, sm);
 }
 
 // Forward that also keeps the normaliser for the adjoint (float64 accumulation).
+template <int RB>
 __global__ __launch_bounds__(256, 2) void k_merge_save(
     const uint16_t* __restrict__ frames, const float* __restrict__ motion,
     const float* __restrict__ rmin, Geometry g, MergeConsts mc, float* __restrict__ out,
@@ -655,18 +662,19 @@ __global__ __launch_bounds__(256, 2) void k_merge_save(
   __shared__ MergeSmem<16> sm;
   const int tiles_x = (g.OW + MW - 1) / MW, n = tiles_x * ((g.OH + 15) / 16);
   const int t = xcd_tile(blockIdx.x, n);
-  merge_tile<16, 256, TILE_SAVE>(frames, motion, rmin, g, mc, out, saved, StreamState{nullptr, nullptr, 0},
+  merge_tile<16, 256, TILE_SAVE, RB>(frames, motion, rmin, g, mc, out, saved, StreamState{nullptr, nullptr, 0},
                                  t % tiles_x, t / tiles_x, sm);
 }
 
 // Streaming form: frames from loop index st.first on are added to the state.
+template <int RB>
 __global__ __launch_bounds__(256, 4) void k_merge_stream(
     const uint16_t* __restrict__ frames, const float* __restrict__ motion,
     const float* __restrict__ rmin, Geometry g, MergeConsts mc, StreamState st) {
   __shared__ MergeSmem<16> sm;
   const int tiles_x = (g.OW + MW - 1) / MW, n = tiles_x * ((g.OH + 15) / 16);
   const int t = xcd_tile(blockIdx.x, n);
-  merge_tile<16, 256, TILE_STREAM>(frames, motion, rmin, g, mc, nullptr, nullptr, st, t % tiles_x, t / tiles_x,
+  merge_tile<16, 256, TILE_STREAM, RB>(frames, motion, rmin, g, mc, nullptr, nullptr, st, t % tiles_x, t / tiles_x,
                                    sm);
 }
 
@@ -701,17 +709,29 @@ __global__ __launch_bounds__(THREADS, (waves_per_simd<MH, THREADS>())) void k_me
     const Geometry g = b->g;
     const MergeConsts mc = b->mc;
     const int tx = w.tile % b->merge_tiles_x, ty = w.tile / b->merge_tiles_x;
-    merge_tile<MH, THREADS, TILE_PLAIN>(b->frames, b->motion, b->rmin, g, mc, b->out, nullptr,
+    // bursts of every scale share the launch: batches of four
+    merge_tile<MH, THREADS, TILE_PLAIN, 4>(b->frames, b->motion, b->rmin, g, mc, b->out, nullptr,
                                         StreamState{nullptr, nullptr, 0}, tx, ty, sm);
   }
+}
+
+// Whether a 64 x MH tile's raw footprint (64/s + 8 by MH/s + 8 samples with
+// its rings) exceeds four loads per thread: then the loads go in batches of
+// eight, else of four (entries past the window still issue a load).
+bool wide_raw_window(int MH, int THREADS, double scale) {
+  return (64.0 / scale + 8.0) * (MH / scale + 8.0) > 4.0 * THREADS;
 }
 
 template <int MH, int THREADS>
 hipError_t launch_variant(const Geometry& g, const MergeConsts& mc, const uint16_t* frames,
                           const float* motion, const float* rmin, float* out, hipStream_t stream) {
   const dim3 grid(((g.OW + MW - 1) / MW) * ((g.OH + MH - 1) / MH));
-  hipLaunchKernelGGL((k_merge<MH, THREADS>), grid, dim3(THREADS), 0, stream, frames, motion, rmin, g,
-                     mc, out);
+  if (wide_raw_window(MH, THREADS, g.scale))
+    hipLaunchKernelGGL((k_merge<MH, THREADS, 8>), grid, dim3(THREADS), 0, stream, frames, motion, rmin, g,
+                       mc, out);
+  else
+    hipLaunchKernelGGL((k_merge<MH, THREADS, 4>), grid, dim3(THREADS), 0, stream, frames, motion, rmin, g,
+                       mc, out);
   return hipGetLastError();
 }
 
@@ -735,7 +755,10 @@ hipError_t launch_merge(int variant, const Geometry& g, const MergeConsts& mc, c
                         hipStream_t stream) {
   if (saved) {  // one tile shape keeps the normaliser
     const dim3 grid(((g.OW + MW - 1) / MW) * ((g.OH + 15) / 16));
-    hipLaunchKernelGGL(k_merge_save, grid, dim3(256), 0, stream, frames, motion, rmin, g, mc, out, saved);
+    if (wide_raw_window(16, 256, g.scale))
+      hipLaunchKernelGGL(k_merge_save<8>, grid, dim3(256), 0, stream, frames, motion, rmin, g, mc, out, saved);
+    else
+      hipLaunchKernelGGL(k_merge_save<4>, grid, dim3(256), 0, stream, frames, motion, rmin, g, mc, out, saved);
     return hipGetLastError();
   }
   switch (variant) {
@@ -762,8 +785,12 @@ hipError_t launch_merge_stream(const Geometry& g, const MergeConsts& mc, const u
                                const float* motion, const float* rmin, const float* state_in, float* state_out,
                                int first, hipStream_t stream) {
   const dim3 grid(((g.OW + MW - 1) / MW) * ((g.OH + 15) / 16));
-  hipLaunchKernelGGL(k_merge_stream, grid, dim3(256), 0, stream, frames, motion, rmin, g, mc,
-                     StreamState{state_in, state_out, first});
+  if (wide_raw_window(16, 256, g.scale))
+    hipLaunchKernelGGL(k_merge_stream<8>, grid, dim3(256), 0, stream, frames, motion, rmin, g, mc,
+                       StreamState{state_in, state_out, first});
+  else
+    hipLaunchKernelGGL(k_merge_stream<4>, grid, dim3(256), 0, stream, frames, motion, rmin, g, mc,
+                       StreamState{state_in, state_out, first});
   return hipGetLastError();
 }
 
