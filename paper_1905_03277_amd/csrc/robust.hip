@@ -454,12 +454,16 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
       atomicMin(&sm.sBox[fl][3], -y1);
     }
     __syncthreads();
-    // copy chunk frame fl's corner window to LDS if it fits
-    auto stage = [&](int fl) -> bool {
+    // copy chunk frame fl's corner window to LDS if it fits, running
+    // `between` while its loads are in flight
+    auto stage = [&](int fl, auto&& between) -> bool {
       const int m = m0 + fl, n = m < g.ref ? m : m + 1;
       const int X0 = sm.sBox[fl][0], Y0 = sm.sBox[fl][2];
       const int wx = -sm.sBox[fl][1] - X0 + 1, wy = -sm.sBox[fl][3] - Y0 + 1;
-      if (wx * wy > WCAP) return false;  // uniform
+      if (wx * wy > WCAP) {  // uniform
+        between();
+        return false;
+      }
       const float* fm = gmu + (size_t)n * 3 * mplane;
       const __amdgpu_buffer_rsrc_t q0 = plane_rsrc(fm, mplane), q1 = plane_rsrc(fm + mplane, mplane),
                                    q2 = plane_rsrc(fm + 2 * mplane, mplane);
@@ -478,6 +482,7 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
         v[i][1] = ld_one(q1, off);
         v[i][2] = ld_one(q2, off);
       }
+      between();
 #pragma unroll
       for (int i = 0; i < WPT; ++i) {
         const int k = tid + i * THREADS;
@@ -488,7 +493,7 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
       }
       return true;
     };
-    bool staged = stage(0);
+    bool staged = stage(0, [] {});
     __syncthreads();
     for (int fl = 0; fl < nf; ++fl) {
       const int m = m0 + fl, n = m < g.ref ? m : m + 1;
@@ -547,14 +552,18 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
         sm.sR[k] = rc.hf > 0.0 && gi[q] < 0.f && sm.sMov[fl][ktq] ? 0.f : fminf(fmaxf(R, 0.f), 1.f);
       }
       __syncthreads();
-      // the window is free again: the next frame's copy overlaps the minimum
-      if (fl + 1 < nf) staged = stage(fl + 1);
-      // eq. (9): 5x5 minimum, separable (the region repeats edge pixels)
-      for (int k = tid; k < RR_H * RB_W; k += THREADS) {
-        const int r = k >> 5, j = k & 31;  // RB_W == 32
-        const float* row = sm.sR + r * RR_W + j;
-        sm.sTmp[k] = fminf(fminf(fminf(row[0], row[1]), fminf(row[2], row[3])), row[4]);
-      }
+      // eq. (9): 5x5 minimum, separable (the region repeats edge pixels);
+      // its first pass runs while the next frame's window loads (the window
+      // is free again)
+      auto rows_min = [&] {
+        for (int k = tid; k < RR_H * RB_W; k += THREADS) {
+          const int r = k >> 5, j = k & 31;  // RB_W == 32
+          const float* row = sm.sR + r * RR_W + j;
+          sm.sTmp[k] = fminf(fminf(fminf(row[0], row[1]), fminf(row[2], row[3])), row[4]);
+        }
+      };
+      if (fl + 1 < nf) staged = stage(fl + 1, rows_min);
+      else rows_min();
       __syncthreads();
       for (int k = tid; k < RB_H * RB_W; k += THREADS) {
         const int i = k >> 5, j = k & 31;
