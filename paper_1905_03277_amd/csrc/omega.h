@@ -33,15 +33,18 @@ __device__ __forceinline__ double recip64(double d) {
   return fma(r, e, r);
 }
 
-// sqrt(x) for x >= 0 to ~1e-15 relative: hardware reciprocal square root
-// refined by two Newton steps (the correctly rounded library square root
-// costs twice as many instructions, and nothing here needs the last bit).
-__device__ __forceinline__ double sqrt64(double x) {
+// 1 / sqrt(x) for x > 0 to ~1e-15 relative: the hardware reciprocal square
+// root refined by two Newton steps.
+__device__ __forceinline__ double rsqrt64(double x) {
   double y = __builtin_amdgcn_rsq(x);
   y = y * fma(-0.5 * x, y * y, 1.5);
-  y = y * fma(-0.5 * x, y * y, 1.5);
-  return x > 0.0 ? x * y : 0.0;
+  return y * fma(-0.5 * x, y * y, 1.5);
 }
+
+// sqrt(x) for x >= 0 to ~1e-15 relative (the correctly rounded library
+// square root costs twice as many instructions, and nothing here needs the
+// last bit).
+__device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? x * rsqrt64(x) : 0.0; }
 
 // What the adjoint needs of one pixel's kernel covariance besides Omega.
 struct OmegaParts {
@@ -70,25 +73,26 @@ __device__ __forceinline__ void omega_core(const Q (&l)[3][3], const OmegaConsts
       tyy += gy * gy;
     }
   }
-  // Closed-form eigen-analysis: lambda1,2 = tr/2 +- rad; lambda1 - lambda2 = 2 rad.
+  // Closed-form eigen-analysis: lambda1,2 = tr/2 +- rad; lambda1 - lambda2 =
+  // 2 rad. With phi the angle of the dominant eigenvector (the gradient
+  // direction), cos 2phi = half / rad and sin 2phi = txy / rad, so its
+  // products are (1 +- cos 2phi) / 2 and sin 2phi / 2. An isotropic tensor
+  // (rad = 0, a tie of integers) takes the x axis.
   const double half = 0.5 * (txx - tyy);
-  const double rad = sqrt64(half * half + txy * txy);
+  const double r2 = half * half + txy * txy;
   const double tr = txx + tyy;
-  double ex, ey;  // dominant eigenvector (gradient direction), unnormalised
-  if (txy == 0.0 && txx == tyy) {
-    ex = 1.0;
-    ey = 0.0;
-  } else if (half >= 0.0) {
-    ex = half + rad;
-    ey = txy;
-  } else {
-    ex = txy;
-    ey = rad - half;
+  double rad = 0.0, gx2 = 1.0, gy2 = 0.0, gxy = 0.0, A = 1.0;
+  if (r2 > 0.0) {
+    const double y = rsqrt64(r2);  // 1 / rad
+    rad = r2 * y;
+    const double c2 = half * y;
+    gx2 = fma(0.5, c2, 0.5);
+    gy2 = fma(-0.5, c2, 0.5);
+    gxy = 0.5 * (txy * y);
+    // A = 1 + sqrt((lambda1 - lambda2) / (lambda1 + lambda2)) = 1 + 1 / sqrt(tr / (2 rad)),
+    // with tr >= 2 rad > 0
+    A = 1.0 + rsqrt64(0.5 * tr * y);
   }
-  const double inv_n2 = recip64(ex * ex + ey * ey);
-  const double gx2 = ex * ex * inv_n2, gy2 = ey * ey * inv_n2, gxy = ex * ey * inv_n2;
-
-  const double A = tr > 0.0 ? 1.0 + sqrt64(2.0 * rad * recip64(tr)) : 1.0;
   const double sqrt_l1 = sqrt64(0.5 * tr + rad);
   const double D_raw = 1.0 - sqrt_l1 * c.inv_16_range_dtr + c.d_th;
   const double D = D_raw < 0.0 ? 0.0 : (D_raw > 1.0 ? 1.0 : D_raw);
