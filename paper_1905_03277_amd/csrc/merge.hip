@@ -480,7 +480,7 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
               O[e] = fma(fy, bot - top, top);
             }
             // eq. (2): log2 w = -1/2 log2(e) d^T Omega^-1 d
-            const double sc = NEG_HALF_LOG2E * recip64(O[0] * O[2] - O[1] * O[1]);
+            const double sc = NEG_HALF_LOG2E * recip64_1(O[0] * O[2] - O[1] * O[1]);
             const double qa = O[2] * sc, qb2 = -2.0 * O[1] * sc, qc = O[0] * sc;
             // sample offsets d = q + 1/2 - p; far away where the sample is outside the frame
             double dx[3], dy[3];
@@ -497,20 +497,15 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
                 if (qi < 0 || qi >= g.H) dy[j] = FAR_Y;
               }
             }
-            double E[3][3];
-            {
-              double ax[3], cy[3], by[3];
+            // exponent of sample (i, j): ax[j] + cy[i] + by[i] dx[j]
+            double ax[3], cy[3], by[3];
   #pragma unroll
-              for (int j = 0; j < 3; ++j) {
-                ax[j] = qa * (dx[j] * dx[j]);
-                cy[j] = qc * (dy[j] * dy[j]);
-                by[j] = qb2 * dy[j];
-              }
-  #pragma unroll
-              for (int i = 0; i < 3; ++i)
-  #pragma unroll
-                for (int j = 0; j < 3; ++j) E[i][j] = fma(by[i], dx[j], ax[j] + cy[i]);
+            for (int j = 0; j < 3; ++j) {
+              ax[j] = qa * (dx[j] * dx[j]);
+              cy[j] = qc * (dy[j] * dy[j]);
+              by[j] = qb2 * dy[j];
             }
+            auto E = [&](int i, int j) { return fma(by[i], dx[j], ax[j] + cy[i]); };
             // Colour groups of the 3x3 window: centre (0), left/right (1), up/down (2), corners (3).
             const int pr = ic & 1, pc = jc & 1;
             const int c0 = colour_of(mc.col4, pr * 2 + pc);
@@ -522,25 +517,28 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
               const float MX = xIsR ? M[p][0] : M[p][2], MY = xIsR ? M[p][2] : M[p][0], MG = M[p][1];
               const double g0 = (double)(isG ? MG : MX), g1 = (double)(isG ? MX : MG);
               const double g2 = (double)(isG ? MY : MG), g3 = (double)(isG ? MG : MY);
-              d[1][1] = (float)(E[1][1] - g0);
-              d[1][0] = (float)(E[1][0] - g1);
-              d[1][2] = (float)(E[1][2] - g1);
-              d[0][1] = (float)(E[0][1] - g2);
-              d[2][1] = (float)(E[2][1] - g2);
-              d[0][0] = (float)(E[0][0] - g3);
-              d[0][2] = (float)(E[0][2] - g3);
-              d[2][0] = (float)(E[2][0] - g3);
-              d[2][2] = (float)(E[2][2] - g3);
+              // the group's reference joins the row term
+              const double r1c = cy[1] - g0, r1s = cy[1] - g1;
+              const double r0m = cy[0] - g2, r0c = cy[0] - g3, r2m = cy[2] - g2, r2c = cy[2] - g3;
+              d[1][1] = (float)fma(by[1], dx[1], ax[1] + r1c);
+              d[1][0] = (float)fma(by[1], dx[0], ax[0] + r1s);
+              d[1][2] = (float)fma(by[1], dx[2], ax[2] + r1s);
+              d[0][1] = (float)fma(by[0], dx[1], ax[1] + r0m);
+              d[2][1] = (float)fma(by[2], dx[1], ax[1] + r2m);
+              d[0][0] = (float)fma(by[0], dx[0], ax[0] + r0c);
+              d[0][2] = (float)fma(by[0], dx[2], ax[2] + r0c);
+              d[2][0] = (float)fma(by[2], dx[0], ax[0] + r2c);
+              d[2][2] = (float)fma(by[2], dx[2], ax[2] + r2c);
             };
             exponents();
             const float dmax = fmaxf(fmaxf(fmaxf(d[0][0], d[0][1]), fmaxf(d[0][2], d[1][0])),
                                      fmaxf(fmaxf(d[1][1], d[1][2]), fmaxf(fmaxf(d[2][0], d[2][1]), d[2][2])));
             if (dmax > SLACK) {
               // raise the reference of every channel this frame would overflow
-              const float m0 = (float)E[1][1];
-              const float m1 = (float)fmax(E[1][0], E[1][2]);
-              const float m2 = (float)fmax(E[0][1], E[2][1]);
-              const float m3 = (float)fmax(fmax(E[0][0], E[0][2]), fmax(E[2][0], E[2][2]));
+              const float m0 = (float)E(1, 1);
+              const float m1 = (float)fmax(E(1, 0), E(1, 2));
+              const float m2 = (float)fmax(E(0, 1), E(2, 1));
+              const float m3 = (float)fmax(fmax(E(0, 0), E(0, 2)), fmax(E(2, 0), E(2, 2)));
               const float fG = isG ? fmaxf(m0, m3) : fmaxf(m1, m2);
               const float fX = isG ? m1 : m0, fY = isG ? m2 : m3;
               const float fm[3] = {xIsR ? fX : fY, fG, xIsR ? fY : fX};

@@ -362,12 +362,12 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
           sm.sOm[2][k] = oyy;
           // sigma_1,2 = k1s, k2s (k1 = sigma_1^2): per unit dL/dk1, dL/dk2 the
           // derivatives of sigma_1,2 in every scalar, each times 2 sigma.
-          const double D = pt.D, A = pt.A, invA = recip64(A);
+          const double D = pt.D, A = pt.A, invA = pt.invA;
           const double s1 = 2.0 * pt.k1s, s2 = 2.0 * pt.k2s;
           const double f1 = pt.d_free ? s1 * (bc.kn - bc.kst * A) : 0.0;
           const double f2 = pt.d_free ? s2 * (bc.kn - invA / bc.ksh) : 0.0;
           const double sl = pt.sqrt_l1 * bc.sl;
-          sm.sDir[k] = make_double2(pt.gx2 - pt.gy2, 2.0 * pt.gxy);
+          sm.sDir[k] = make_double2(pt.c2, pt.s2);
           sm.sP[0][k] = make_float4((float)(s1 * pt.k1s), (float)(s2 * pt.k2s), (float)(s1 * D), (float)(s2 * D));
           sm.sP[1][k] = make_float4((float)(s1 * (1.0 - D) * A), (float)(s2 * (1.0 - D) * invA), (float)f1,
                                     (float)f2);
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
             dOx[e] = fma(fy, (o11 - o10) - (o01 - o00), o01 - o00);
             dOy[e] = bot - top;
           }
-          const double idet = recip64(O[0] * O[2] - O[1] * O[1]);
+          const double idet = recip64_1(O[0] * O[2] - O[1] * O[1]);
           const double sc = NEG_HALF_LOG2E * idet;
           const double qa = O[2] * sc, qb2 = -2.0 * O[1] * sc, qc = O[0] * sc;
           double dx[3], dy[3];

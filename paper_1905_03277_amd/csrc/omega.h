@@ -24,17 +24,24 @@ struct OmegaConsts {
   double inv_16_range_dtr;  // 1 / (16 * range * d_tr)
 };
 
-// 1 / d to float64 accuracy: hardware reciprocal refined by two Newton steps.
-__device__ __forceinline__ double recip64(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  double e = fma(-d, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-d, r, 1.0);
-  return fma(r, e, r);
+// The hardware reciprocal and reciprocal square root are good to ~5e-8
+// relative; one Newton step takes them to ~4e-15, two to the last bit or two.
+
+// 1 / d to ~2e-15 relative (one Newton step), for values that feed only
+// continuous arithmetic.
+__device__ __forceinline__ double recip64_1(double d) {
+  const double r = __builtin_amdgcn_rcp(d);
+  return fma(r, fma(-d, r, 1.0), r);
 }
 
-// 1 / sqrt(x) for x > 0 to ~1e-15 relative: the hardware reciprocal square
-// root refined by two Newton steps.
+// 1 / sqrt(x) for x > 0 to ~4e-15 relative (one Newton step).
+__device__ __forceinline__ double rsqrt64_1(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return y * fma(-0.5 * x, y * y, 1.5);
+}
+
+// 1 / sqrt(x) for x > 0 to ~2 ulp: the hardware reciprocal square root
+// refined by two Newton steps.
 __device__ __forceinline__ double rsqrt64(double x) {
   double y = __builtin_amdgcn_rsq(x);
   y = y * fma(-0.5 * x, y * y, 1.5);
@@ -48,8 +55,8 @@ __device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? x * rsqrt6
 
 // What the adjoint needs of one pixel's kernel covariance besides Omega.
 struct OmegaParts {
-  double gx2, gy2, gxy;  // products of the unit gradient direction
-  double A, D;           // anisotropy and denoising weight (S.1), D clamped
+  double c2, s2;         // cos 2phi, sin 2phi of the gradient direction phi
+  double A, invA, D;     // anisotropy, its inverse, denoising weight (S.1), D clamped
   double k1s, k2s;       // square roots of the edge / gradient variances
   double sqrt_l1;        // sqrt(lambda1) of the integer tensor
   bool d_free;           // D strictly inside (0, 1), i.e. not clamped
@@ -81,33 +88,35 @@ __device__ __forceinline__ void omega_core(const Q (&l)[3][3], const OmegaConsts
   const double half = 0.5 * (txx - tyy);
   const double r2 = half * half + txy * txy;
   const double tr = txx + tyy;
-  double rad = 0.0, gx2 = 1.0, gy2 = 0.0, gxy = 0.0, A = 1.0;
+  double rad = 0.0, c2 = 1.0, s2 = 0.0, A = 1.0;
   if (r2 > 0.0) {
     const double y = rsqrt64(r2);  // 1 / rad
     rad = r2 * y;
-    const double c2 = half * y;
-    gx2 = fma(0.5, c2, 0.5);
-    gy2 = fma(-0.5, c2, 0.5);
-    gxy = 0.5 * (txy * y);
+    c2 = half * y;
+    s2 = txy * y;
     // A = 1 + sqrt((lambda1 - lambda2) / (lambda1 + lambda2)) = 1 + 1 / sqrt(tr / (2 rad)),
     // with tr >= 2 rad > 0
-    A = 1.0 + rsqrt64(0.5 * tr * y);
+    A = 1.0 + rsqrt64_1(0.5 * tr * y);
   }
+  const double invA = recip64_1(A);
   const double sqrt_l1 = sqrt64(0.5 * tr + rad);
   const double D_raw = 1.0 - sqrt_l1 * c.inv_16_range_dtr + c.d_th;
   const double D = D_raw < 0.0 ? 0.0 : (D_raw > 1.0 ? 1.0 : D_raw);
   const double k1s = (1.0 - D) * (c.kd_st * A) + D * c.kd_dn;
-  const double k2s = (1.0 - D) * (c.kd_sh * recip64(A)) + D * c.kd_dn;
+  const double k2s = (1.0 - D) * (c.kd_sh * invA) + D * c.kd_dn;
   const double k1 = k1s * k1s, k2 = k2s * k2s;
-  // eq. (4): variance k1 along the edge (perpendicular to the gradient), k2 across it.
-  oxx = k1 * gy2 + k2 * gx2;
-  oxy = (k2 - k1) * gxy;
-  oyy = k1 * gx2 + k2 * gy2;
+  // eq. (4): variance k1 along the edge (perpendicular to the gradient), k2
+  // across it. With the gradient products (1 + c2) / 2, (1 - c2) / 2 and
+  // s2 / 2: Omega = (k1 + k2) / 2 I + (k1 - k2) / 2 [[-c2, -s2], [-s2, c2]].
+  const double hs = 0.5 * (k1 + k2), hd = 0.5 * (k1 - k2);
+  oxx = fma(-c2, hd, hs);
+  oxy = -(s2 * hd);
+  oyy = fma(c2, hd, hs);
   if (PARTS) {
-    parts->gx2 = gx2;
-    parts->gy2 = gy2;
-    parts->gxy = gxy;
+    parts->c2 = c2;
+    parts->s2 = s2;
     parts->A = A;
+    parts->invA = invA;
     parts->D = D;
     parts->k1s = k1s;
     parts->k2s = k2s;
