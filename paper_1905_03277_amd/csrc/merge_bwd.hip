@@ -47,6 +47,7 @@ constexpr int BWAVES = BTHREADS / 64;
 constexpr int BPX = BMH / BWAVES;  // pixel rows per thread
 using BCP = Caps<BMH>;
 static_assert(BCP::VT == kBwdVT && BCP::RH == kBwdRH, "partial layouts follow the tile caps");
+static_assert(BCP::VT <= BTHREADS, "one alignment tile per thread at most");
 
 struct BwdSmem {
   double sX[MW], sY[BMH];
@@ -226,14 +227,13 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
     const bool is_ref = n == g.ref;
     const uint16_t* f = frames + (size_t)n * g.H * g.W;
     __syncthreads();
-    for (int k = tid; k < ntiles; k += BTHREADS) {
-      float2 v = make_float2(0.f, 0.f);
-      if (!is_ref) {
-        const int ky = k / ntx;
-        const float* p = motion + (((size_t)n * g.TY + tyA + ky) * g.TX + txA + (k - ky * ntx)) * 2;
-        v = make_float2(fminf(fmaxf(p[0], -vlim), vlim), fminf(fmaxf(p[1], -vlim), vlim));
-      }
-      sm.sV[k] = v;
+    // this thread's alignment tile (at most one: ntiles <= VT <= BTHREADS):
+    // its displacement loads in flight together with the R_hat window's
+    float2 v = make_float2(0.f, 0.f);
+    if (tid < ntiles && !is_ref) {
+      const int ky = tid / ntx;
+      const float* p = motion + (((size_t)n * g.TY + tyA + ky) * g.TX + txA + (tid - ky * ntx)) * 2;
+      v = make_float2(p[0], p[1]);
     }
     if (tid < 8) sm.sRed[tid] = 0x7fffffff;
     if (!is_ref) {
@@ -254,6 +254,8 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
       for (int i = 0; i < RHT; ++i)
         if (tid + i * BTHREADS < nrh) sm.sRh[tid + i * BTHREADS] = rhv[i];
     }
+    // clamping keeps non-finite or huge vectors finite and changes no result
+    if (tid < ntiles) sm.sV[tid] = make_float2(fminf(fmaxf(v.x, -vlim), vlim), fminf(fmaxf(v.y, -vlim), vlim));
 #pragma unroll
     for (int p = 0; p < BPX; ++p) {
       sm.sGr[wave * BPX + p][lane] = 0.f;
