@@ -20,9 +20,12 @@ constexpr double FAR_X = 1e100, FAR_Y = 1e120;
 template <int MH>
 struct Caps {
   // sized for scale 1 with up to ~8 px of displacement spread inside the tile
-  static constexpr int RAW = (MW + 16) * (MH + 16);
-  static constexpr int LUMA = (MW / 2 + 8) * (MH / 2 + 8);
-  static constexpr int OM = (MW / 2 + 6) * (MH / 2 + 6);
+  // (the forward's tiles take 6 more rows and columns than the adjoint's
+  // 64 x 8 tile, whose LDS must leave room for three workgroups per CU)
+  static constexpr int PAD = MH >= 16 ? 6 : 0;
+  static constexpr int RAW = (MW + 16 + PAD) * (MH + 16 + PAD);
+  static constexpr int LUMA = (MW / 2 + 8 + PAD / 2) * (MH / 2 + 8 + PAD / 2);
+  static constexpr int OM = (MW / 2 + 6 + PAD / 2) * (MH / 2 + 6 + PAD / 2);
   static constexpr int RH_W = MW / 2 + 2, RH_H = MH / 2 + 2;
   static constexpr int RH = RH_W * RH_H;
   static constexpr int TX = MW / 8 + 2, TY = MH / 8 + 2;  // alignment tiles (T >= 8)
