@@ -34,9 +34,11 @@ constexpr float SLACK = 64.f;   // log2 headroom above the reference exponent
 
 // Footprint windows of a set of output pixels in one frame. Omega window:
 // every bilinear corner, unclamped (edge values repeated); luma window: the
-// clamped corners' 3x3 neighbourhoods; raw window: the luma quads and every
-// nine-sample window, unclamped (zero outside the frame). raw, lum, om: the
-// window's offsets in the LDS buffers.
+// clamped corners' 3x3 neighbourhoods, whose outer ring may lie one quad
+// outside the grid and then repeats the edge quad (so Omega reads it without
+// clamping); raw window: the quads inside the grid and every nine-sample
+// window, unclamped (zero outside the frame). raw, lum, om: the window's
+// offsets in the LDS buffers.
 struct Win {
   int rc0, rr0, rw, rh;
   int lc0, lr0, lw, lh;
@@ -50,14 +52,14 @@ __device__ __forceinline__ Win make_win(const Bounds& bd, const Geometry& g) {
   w.ow = bd.hj1 - bd.hj0 + 2;
   w.or0 = bd.hi0;
   w.oh = bd.hi1 - bd.hi0 + 2;
-  w.lc0 = max(clampi(bd.hj0, 0, g.w - 1) - 1, 0);
-  const int lc1 = min(clampi(bd.hj1 + 1, 0, g.w - 1) + 1, g.w - 1);
-  w.lr0 = max(clampi(bd.hi0, 0, g.h - 1) - 1, 0);
-  const int lr1 = min(clampi(bd.hi1 + 1, 0, g.h - 1) + 1, g.h - 1);
-  w.rc0 = min(2 * w.lc0, bd.jc0 - 1);
-  const int rc1 = max(2 * lc1 + 1, bd.jc1 + 1);
-  w.rr0 = min(2 * w.lr0, bd.ic0 - 1);
-  const int rr1 = max(2 * lr1 + 1, bd.ic1 + 1);
+  w.lc0 = clampi(bd.hj0, 0, g.w - 1) - 1;
+  const int lc1 = clampi(bd.hj1 + 1, 0, g.w - 1) + 1;
+  w.lr0 = clampi(bd.hi0, 0, g.h - 1) - 1;
+  const int lr1 = clampi(bd.hi1 + 1, 0, g.h - 1) + 1;
+  w.rc0 = min(2 * max(w.lc0, 0), bd.jc0 - 1);
+  const int rc1 = max(2 * min(lc1, g.w - 1) + 1, bd.jc1 + 1);
+  w.rr0 = min(2 * max(w.lr0, 0), bd.ic0 - 1);
+  const int rr1 = max(2 * min(lr1, g.h - 1) + 1, bd.ic1 + 1);
   w.lw = lc1 - w.lc0 + 1;
   w.lh = lr1 - w.lr0 + 1;
   w.rw = rc1 - w.rc0 + 1;
@@ -401,7 +403,7 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
         const float inv = 1.f / (float)lw;
         for (int k = tid; k < lw * lh; k += THREADS) {
           const int r = split_row(k, inv), c = k - mul24(r, lw);
-          const int o = mul24(2 * (lr0 + r) - rr0, rw) + 2 * (lc0 + c) - rc0;
+          const int o = mul24(2 * clampi(lr0 + r, 0, g.h - 1) - rr0, rw) + 2 * clampi(lc0 + c, 0, g.w - 1) - rc0;
           sLum[k] = (sRaw[o] + sRaw[o + 1]) + (sRaw[o + rw] + sRaw[o + rw + 1]);  // exact
         }
       } else {
@@ -409,7 +411,8 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
         for (int e = tid; e < n_e; e += THREADS) {
           const Win& w = sWin[find(e, 1)];
           const int k = e - w.lum, r = k / w.lw, c = k - mul24(r, w.lw);
-          const int o = w.raw + mul24(2 * (w.lr0 + r) - w.rr0, w.rw) + 2 * (w.lc0 + c) - w.rc0;
+          const int o = w.raw + mul24(2 * clampi(w.lr0 + r, 0, g.h - 1) - w.rr0, w.rw) +
+                        2 * clampi(w.lc0 + c, 0, g.w - 1) - w.rc0;
           sLum[e] = (sRaw[o] + sRaw[o + 1]) + (sRaw[o + w.rw] + sRaw[o + w.rw + 1]);  // exact
         }
       }
@@ -418,13 +421,13 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
         // Omega at entry (r, c) of window w, stored at flat entry e
         auto omega_at = [&](int e, const Win& w, int r, int c) {
           const int I = clampi(w.or0 + r, 0, g.h - 1), J = clampi(w.oc0 + c, 0, g.w - 1);
+          // the window's outer ring repeats the edge quads: no clamps here
+          const int base = w.lum + mul24(I - 1 - w.lr0, w.lw) + (J - 1 - w.lc0);
           float l[3][3];
 #pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const int row = w.lum + mul24(clampi(I + a - 1, 0, g.h - 1) - w.lr0, w.lw);
+          for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int bb = 0; bb < 3; ++bb) l[a][bb] = sLum[row + clampi(J + bb - 1, 0, g.w - 1) - w.lc0];
-          }
+            for (int bb = 0; bb < 3; ++bb) l[a][bb] = sLum[base + a * w.lw + bb];
           double oxx, oxy, oyy;
           omega_from_quads(l, mc.om, oxx, oxy, oyy);
           sOm[0][e] = oxx;
