@@ -297,12 +297,16 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
       const int sty = whole ? -1 : seg / ntx, stx = whole ? -1 : seg % ntx;
       const int oc0 = bd.hj0, ow = bd.hj1 - bd.hj0 + 2;
       const int or0 = bd.hi0, oh = bd.hi1 - bd.hi0 + 2;
-      const int lc0 = max(clampi(bd.hj0, 0, g.w - 1) - 1, 0);
-      const int lc1 = min(clampi(bd.hj1 + 1, 0, g.w - 1) + 1, g.w - 1);
-      const int lr0 = max(clampi(bd.hi0, 0, g.h - 1) - 1, 0);
-      const int lr1 = min(clampi(bd.hi1 + 1, 0, g.h - 1) + 1, g.h - 1);
-      const int rc0 = min(2 * lc0, bd.jc0 - 1), rc1 = max(2 * lc1 + 1, bd.jc1 + 1);
-      const int rr0 = min(2 * lr0, bd.ic0 - 1), rr1 = max(2 * lr1 + 1, bd.ic1 + 1);
+      // luma window: the clamped corners' 3x3 neighbourhoods, the outer ring
+      // repeating the edge quads where it leaves the grid (Omega then reads
+      // it without clamps); raw window: the quads inside the grid and every
+      // nine-sample window
+      const int lc0 = clampi(bd.hj0, 0, g.w - 1) - 1;
+      const int lc1 = clampi(bd.hj1 + 1, 0, g.w - 1) + 1;
+      const int lr0 = clampi(bd.hi0, 0, g.h - 1) - 1;
+      const int lr1 = clampi(bd.hi1 + 1, 0, g.h - 1) + 1;
+      const int rc0 = min(2 * max(lc0, 0), bd.jc0 - 1), rc1 = max(2 * min(lc1, g.w - 1) + 1, bd.jc1 + 1);
+      const int rr0 = min(2 * max(lr0, 0), bd.ic0 - 1), rr1 = max(2 * min(lr1, g.h - 1) + 1, bd.ic1 + 1);
       const int lw = lc1 - lc0 + 1, lh = lr1 - lr0 + 1;
       const int rw = rc1 - rc0 + 1, rh = rr1 - rr0 + 1;
       if (whole && (ow * oh > BCP::OM || lw * lh > BCP::LUMA || rw * rh > BCP::RAW)) {
@@ -339,7 +343,7 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
         const float inv = 1.f / (float)lw;
         for (int k = tid; k < lw * lh; k += BTHREADS) {
           const int r = split_row(k, inv), c = k - r * lw;
-          const int o = (2 * (lr0 + r) - rr0) * rw + 2 * (lc0 + c) - rc0;
+          const int o = (2 * clampi(lr0 + r, 0, g.h - 1) - rr0) * rw + 2 * clampi(lc0 + c, 0, g.w - 1) - rc0;
           sm.sLum[k] = (sm.sRaw[o] + sm.sRaw[o + 1]) + (sm.sRaw[o + rw] + sm.sRaw[o + rw + 1]);
         }
       }
@@ -349,13 +353,12 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
         for (int k = tid; k < ow * oh; k += BTHREADS) {
           const int r = split_row(k, inv), c = k - r * ow;
           const int I = clampi(or0 + r, 0, g.h - 1), J = clampi(oc0 + c, 0, g.w - 1);
+          const int base = (I - 1 - lr0) * lw + (J - 1 - lc0);  // the window's ring repeats the edges
           float l[3][3];
 #pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const int row = (clampi(I + a - 1, 0, g.h - 1) - lr0) * lw;
+          for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int bb = 0; bb < 3; ++bb) l[a][bb] = sm.sLum[row + clampi(J + bb - 1, 0, g.w - 1) - lc0];
-          }
+            for (int bb = 0; bb < 3; ++bb) l[a][bb] = sm.sLum[base + a * lw + bb];
           double oxx, oxy, oyy;
           OmegaParts pt;
           omega_parts_from_quads(l, mc.om, oxx, oxy, oyy, pt);
