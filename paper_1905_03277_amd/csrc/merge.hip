@@ -75,7 +75,7 @@ struct MergeSmem {
   int sTyRow[MH], sTxCol[MW];
   int sRlo[CP::TY], sRhi[CP::TY], sClo[CP::TX], sChi[CP::TX];
   RowInfo sRow[MH];
-  float2 sV[CP::VT];
+  float2 sV[2][CP::VT];  // displacement per alignment tile, per frame slot (loop index & 1)
   Bounds sTB[CP::VT];
   float sRaw[CP::RAW];
   float sLum[CP::LUMA];
@@ -130,7 +130,6 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
   int* sClo = sm.sClo;
   int* sChi = sm.sChi;
   RowInfo* sRow = sm.sRow;
-  float2* sV = sm.sV;
   Bounds* sTB = sm.sTB;
   float* sRaw = sm.sRaw;
   float* sLum = sm.sLum;
@@ -178,6 +177,7 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
     rh_range(C0, C0 + ncol - 1, g.scale, g.w, sRh0[0], sRh0[1]);
     rh_range(R0, R0 + nrow - 1, g.scale, g.h, sRh0[2], sRh0[3]);
   }
+  if (tid < 16) sRed[tid] = 0x7fffffff;  // both footprint slots
   __syncthreads();
   const int rhc0 = sRh0[0], rhw = sRh0[1] - sRh0[0] + 1;
   const int rhr0 = sRh0[2], rhh = sRh0[3] - sRh0[2] + 1;
@@ -232,42 +232,46 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
     }
   }
 
-  if (tid < 8) sRed[8 * ((MODE == TILE_STREAM ? st.first : 0) & 1) + tid] = 0x7fffffff;
+  // The R_hat window: every load in flight before its stores (entries past
+  // the window re-read its last one and are not stored).
+  constexpr int RHT = (CP::RH + THREADS - 1) / THREADS;
+  auto rh_load = [&](int n, float (&rhv)[RHT]) {
+    const float* rm = rmin + (size_t)n * g.h * g.w;
+    const float inv = 1.f / (float)rhw;
+    const int nrh = rhw * rhh;
+#pragma unroll
+    for (int i = 0; i < RHT; ++i) {
+      const int k = min(tid + i * THREADS, nrh - 1);
+      const int r = split_row(k, inv);
+      rhv[i] = rm[(unsigned)((rhr0 + r) * g.w + rhc0 + k - mul24(r, rhw))];  // below 2^28
+    }
+  };
+  auto rh_store = [&](const float (&rhv)[RHT]) {
+#pragma unroll
+    for (int i = 0; i < RHT; ++i)
+      if (tid + i * THREADS < rhw * rhh) sRh[tid + i * THREADS] = rhv[i];
+  };
+
+  // No barrier opens a frame: what the previous frame's pixels read is either
+  // per frame slot (sV, sRed) or written only after the footprint barrier
+  // below, so waves that finish their pixels start the next frame's loads.
   for (int fi = MODE == TILE_STREAM ? st.first : 0; fi < g.n; ++fi) {
     const int n = fi == 0 ? g.ref : (fi <= g.ref ? fi - 1 : fi);
     const bool is_ref = n == g.ref;
     const uint16_t* f = frames + (size_t)n * g.H * g.W;
     // the footprint reduction alternates between two slots: this frame's was
     // reset during the previous frame, the next frame's is reset now (its
-    // last readers passed the barrier below)
+    // last reader, the previous frame's window, passed that frame's staging
+    // barrier before any thread got here)
     int* red = sRed + 8 * (fi & 1);
-    __syncthreads();
+    float2* sV = sm.sV[fi & 1];
     if (tid < 8) sRed[8 * ((fi + 1) & 1) + tid] = 0x7fffffff;
-    // this thread's alignment tile (at most one: ntiles <= VT <= THREADS):
-    // its displacement loads in flight together with the R_hat window's
+    // this thread's alignment tile (at most one: ntiles <= VT <= THREADS)
     const int ky = tid < ntiles ? tid / ntx : 0, kx = tid - ky * ntx;
     float2 v = make_float2(0.f, 0.f);
     if (tid < ntiles && !is_ref) {
       const float* p = motion + (((size_t)n * g.TY + tyA + ky) * g.TX + txA + kx) * 2;
       v = make_float2(p[0], p[1]);
-    }
-    if (!is_ref) {
-      // every load of the window in flight before its stores (entries past
-      // the window re-read its last one and are not stored)
-      constexpr int RHT = (CP::RH + THREADS - 1) / THREADS;
-      const float* rm = rmin + (size_t)n * g.h * g.w;
-      const float inv = 1.f / (float)rhw;
-      const int nrh = rhw * rhh;
-      float rhv[RHT];
-#pragma unroll
-      for (int i = 0; i < RHT; ++i) {
-        const int k = min(tid + i * THREADS, nrh - 1);
-        const int r = split_row(k, inv);
-        rhv[i] = rm[(unsigned)((rhr0 + r) * g.w + rhc0 + k - mul24(r, rhw))];  // below 2^28
-      }
-#pragma unroll
-      for (int i = 0; i < RHT; ++i)
-        if (tid + i * THREADS < nrh) sRh[tid + i * THREADS] = rhv[i];
     }
     // per alignment tile: its displacement and its footprint (positions are
     // monotonic in X and Y, so the tile's extreme pixels give its extreme
@@ -311,6 +315,11 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
     const bool whole = W.ow * W.oh <= CP::OM && W.lw * W.lh <= CP::LUMA && W.rw * W.rh <= CP::RAW;
     int ngroups = 1;
     if (!whole) {
+      if (!is_ref) {
+        float rhv[RHT];
+        rh_load(n, rhv);
+        rh_store(rhv);
+      }
       for (int k = tid; k < ntiles; k += THREADS) sWin[k] = make_win(sTB[k], g);
       __syncthreads();
       if (tid == 0) {
@@ -356,6 +365,8 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
         // the clamped position and the zero outside the frame is chosen after
         const int rc0 = W.rc0, rr0 = W.rr0, rw = W.rw, nr = W.rw * W.rh;
         const float inv = 1.f / (float)rw;
+        float rhv[RHT];  // the R_hat window's loads join the first batch
+        if (!is_ref) rh_load(n, rhv);
         for (int k0 = tid; k0 < nr; k0 += RB * THREADS) {
           uint32_t rv[RB];
           bool rin[RB];
@@ -375,6 +386,7 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
             if (k < nr) sRaw[k] = rin[i] ? (float)rv[i] : 0.f;
           }
         }
+        if (!is_ref) rh_store(rhv);
       } else {
         const int n_e = entries(0);
         constexpr int MB = 4;  // batches of branch-free loads, as above
