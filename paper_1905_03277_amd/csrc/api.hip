@@ -169,7 +169,7 @@ hmfsr_status grow(void*& buf, size_t& have, size_t bytes, hipStream_t stream, vo
   if (have < bytes) {
     if (buf) {
       if (hipStreamSynchronize(stream) != hipSuccess) return HMFSR_E_HIP;
-      hipFree(buf);
+      (void)hipFree(buf);
       buf = nullptr;
       have = 0;
     }
@@ -610,27 +610,27 @@ void hmfsr_release(void) {
         !st.plan.exec && !st.capture_stream)
       continue;
     if (hipSetDevice(d) != hipSuccess) continue;
-    if (st.plan.exec) hipGraphExecDestroy(st.plan.exec);
-    if (st.plan.graph) hipGraphDestroy(st.plan.graph);
+    if (st.plan.exec) (void)hipGraphExecDestroy(st.plan.exec);
+    if (st.plan.graph) (void)hipGraphDestroy(st.plan.graph);
     st.plan = BatchPlan();
-    if (st.workspace) hipFree(st.workspace);
-    if (st.batch_ws) hipFree(st.batch_ws);
-    if (st.bwd_ws) hipFree(st.bwd_ws);
-    if (st.stream_ws) hipFree(st.stream_ws);
+    if (st.workspace) (void)hipFree(st.workspace);
+    if (st.batch_ws) (void)hipFree(st.batch_ws);
+    if (st.bwd_ws) (void)hipFree(st.bwd_ws);
+    if (st.stream_ws) (void)hipFree(st.stream_ws);
     st.stream_ws = nullptr;
     st.stream_ws_bytes = 0;
-    if (st.align_ws) hipFree(st.align_ws);
+    if (st.align_ws) (void)hipFree(st.align_ws);
     st.align_ws = nullptr;
     st.align_ws_bytes = 0;
-    if (st.sum_ws) hipFree(st.sum_ws);
+    if (st.sum_ws) (void)hipFree(st.sum_ws);
     st.sum_ws = nullptr;
     st.sum_ws_bytes = 0;
-    if (st.capture_stream) hipStreamDestroy(st.capture_stream);
+    if (st.capture_stream) (void)hipStreamDestroy(st.capture_stream);
     st.workspace = st.batch_ws = st.bwd_ws = nullptr;
     st.workspace_bytes = st.batch_ws_bytes = st.bwd_ws_bytes = 0;
     st.capture_stream = nullptr;
   }
-  if (have_cur) hipSetDevice(cur);
+  if (have_cur) (void)hipSetDevice(cur);
 }
 
 }  // extern "C"

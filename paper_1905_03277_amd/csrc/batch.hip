@@ -130,8 +130,8 @@ hmfsr_status hmfsr_autotune(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
       best = v;
     }
   }
-  hipEventDestroy(a);
-  hipEventDestroy(b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
   if (st != HMFSR_OK) return st;
   // leave `out` holding the merge of the chosen shape
   if (launch_merge(best, g, mc, frames, motion, w.rmin, out, nullptr, s) != hipSuccess) return HMFSR_E_HIP;
@@ -201,10 +201,10 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
   // workspace (grown only; the old graph points into the old one)
   if (ds.batch_ws_bytes < L.total) {
     if (hipStreamSynchronize(s) != hipSuccess) return HMFSR_E_HIP;
-    if (ds.plan.exec) hipGraphExecDestroy(ds.plan.exec);
-    if (ds.plan.graph) hipGraphDestroy(ds.plan.graph);
+    if (ds.plan.exec) (void)hipGraphExecDestroy(ds.plan.exec);
+    if (ds.plan.graph) (void)hipGraphDestroy(ds.plan.graph);
     ds.plan = BatchPlan();
-    if (ds.batch_ws) hipFree(ds.batch_ws);
+    if (ds.batch_ws) (void)hipFree(ds.batch_ws);
     ds.batch_ws = nullptr;
     ds.batch_ws_bytes = 0;
     if (hipMalloc(&ds.batch_ws, L.total) != hipSuccess) {
@@ -296,8 +296,8 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
 
   // rebuild: wait for any replay that reads the lists, upload, capture
   if (hipStreamSynchronize(s) != hipSuccess) return HMFSR_E_HIP;
-  if (P.exec) hipGraphExecDestroy(P.exec);
-  if (P.graph) hipGraphDestroy(P.graph);
+  if (P.exec) (void)hipGraphExecDestroy(P.exec);
+  if (P.graph) (void)hipGraphDestroy(P.graph);
   P = BatchPlan();
   if (hipMemcpy(base + L.args, args.data(), sizeof(BurstArgs) * n_bursts, hipMemcpyHostToDevice) !=
           hipSuccess ||
@@ -339,13 +339,13 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
   }
   const hipError_t end = hipStreamEndCapture(cs, &graph);
   if (err != hipSuccess || end != hipSuccess || !graph) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     (void)hipGetLastError();
     return HMFSR_E_HIP;
   }
   hipGraphExec_t exec = nullptr;
   if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     return HMFSR_E_HIP;
   }
   P.graph = graph;
