@@ -5,7 +5,7 @@
 
 namespace hmfsr {
 
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+__host__ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // a * b for |a|, |b| < 2^23 (window offsets and widths, LDS indices): the
 // full-rate 24-bit multiply instead of the quarter-rate 32-bit one.

@@ -32,42 +32,6 @@ namespace {
 
 constexpr float SLACK = 64.f;   // log2 headroom above the reference exponent
 
-// Footprint windows of a set of output pixels in one frame. Omega window:
-// every bilinear corner, unclamped (edge values repeated); luma window: the
-// clamped corners' 3x3 neighbourhoods, whose outer ring may lie one quad
-// outside the grid and then repeats the edge quad (so Omega reads it without
-// clamping); raw window: the quads inside the grid and every nine-sample
-// window, unclamped (zero outside the frame). raw, lum, om: the window's
-// offsets in the LDS buffers.
-struct Win {
-  int rc0, rr0, rw, rh;
-  int lc0, lr0, lw, lh;
-  int oc0, or0, ow, oh;
-  int raw, lum, om;
-};
-
-__device__ __forceinline__ Win make_win(const Bounds& bd, const Geometry& g) {
-  Win w;
-  w.oc0 = bd.hj0;
-  w.ow = bd.hj1 - bd.hj0 + 2;
-  w.or0 = bd.hi0;
-  w.oh = bd.hi1 - bd.hi0 + 2;
-  w.lc0 = clampi(bd.hj0, 0, g.w - 1) - 1;
-  const int lc1 = clampi(bd.hj1 + 1, 0, g.w - 1) + 1;
-  w.lr0 = clampi(bd.hi0, 0, g.h - 1) - 1;
-  const int lr1 = clampi(bd.hi1 + 1, 0, g.h - 1) + 1;
-  w.rc0 = min(2 * max(w.lc0, 0), bd.jc0 - 1);
-  const int rc1 = max(2 * min(lc1, g.w - 1) + 1, bd.jc1 + 1);
-  w.rr0 = min(2 * max(w.lr0, 0), bd.ic0 - 1);
-  const int rr1 = max(2 * min(lr1, g.h - 1) + 1, bd.ic1 + 1);
-  w.lw = lc1 - w.lc0 + 1;
-  w.lh = lr1 - w.lr0 + 1;
-  w.rw = rc1 - w.rc0 + 1;
-  w.rh = rr1 - w.rr0 + 1;
-  w.raw = w.lum = w.om = 0;
-  return w;
-}
-
 template <int MH>
 struct MergeSmem {
   using CP = Caps<MH>;
@@ -281,17 +245,8 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
       // clamping keeps non-finite or huge vectors finite and changes no result
       v = make_float2(fminf(fmaxf(v.x, -vlim), vlim), fminf(fmaxf(v.y, -vlim), vlim));
       sV[k] = v;
-      const double pxa = sX[sClo[kx]] + (double)v.x, pxb = sX[sChi[kx]] + (double)v.x;
-      const double pya = sY[sRlo[ky]] + (double)v.y, pyb = sY[sRhi[ky]] + (double)v.y;
-      Bounds b;
-      b.jc0 = (int)floor(pxa);
-      b.jc1 = (int)floor(pxb);
-      b.ic0 = (int)floor(pya);
-      b.ic1 = (int)floor(pyb);
-      b.hj0 = (int)floor(pxa * 0.5 - 0.5);
-      b.hj1 = (int)floor(pxb * 0.5 - 0.5);
-      b.hi0 = (int)floor(pya * 0.5 - 0.5);
-      b.hi1 = (int)floor(pyb * 0.5 - 0.5);
+      const Bounds b = footprint(sX[sClo[kx]] + (double)v.x, sX[sChi[kx]] + (double)v.x,
+                                 sY[sRlo[ky]] + (double)v.y, sY[sRhi[ky]] + (double)v.y, g);
       sTB[k] = b;
       atomicMin(&red[0], b.jc0); atomicMin(&red[1], -b.jc1);
       atomicMin(&red[2], b.ic0); atomicMin(&red[3], -b.ic1);
@@ -303,7 +258,9 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
     // Windows: the whole tile's footprint in one window when it fits the
     // buffers; otherwise every alignment tile's own window, laid out side by
     // side in groups that fit (one alignment tile always does: its pixels
-    // share one displacement).
+    // share one displacement, and its footprint stops at the frame's ring,
+    // so its windows span at most its own pixels plus the rings; the caps
+    // check of the test suite replays this arithmetic for extreme vectors).
     Win W;
     {
       Bounds bd;
@@ -479,6 +436,7 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
             const double fjc = floor(px), fic = floor(py);
             const double frx = px - fjc, fry = py - fic;  // exact
             const int jc = (int)fjc, ic = (int)fic;
+            if (samples_outside(jc, ic, g)) return;  // no in-frame sample: no term
             // Omega at p / 2 - 1/2 (bilinear; the window repeats edge values)
             const double hx = px * 0.5 - 0.5, hy = py * 0.5 - 0.5;
             const double fhj = floor(hx), fhi = floor(hy);

@@ -12,7 +12,7 @@
 // and e = -1/2 d^T Omega^-1 d with d = q + 1/2 - p gives
 //   de/dp = Omega^-1 d,   de/dOmega = 1/2 Omega^-1 d d^T Omega^-1.
 //
-// k_merge_bwd   one workgroup per 64 x 16 output tile, staging each frame as
+// k_merge_bwd   one workgroup per 64 x 8 output tile, staging each frame as
 //               the forward does. Per pixel and frame it forms dL/de for the
 //               nine samples and dL/drho, then
 //               - dL/dp (offsets and the Omega sampling position), summed per
@@ -265,17 +265,8 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
     for (int k = tid; k < ntiles; k += BTHREADS) {
       const int ky = k / ntx, kx = k - ky * ntx;
       const float2 v = sm.sV[k];
-      const double pxa = sm.sX[sm.sClo[kx]] + (double)v.x, pxb = sm.sX[sm.sChi[kx]] + (double)v.x;
-      const double pya = sm.sY[sm.sRlo[ky]] + (double)v.y, pyb = sm.sY[sm.sRhi[ky]] + (double)v.y;
-      Bounds b;
-      b.jc0 = (int)floor(pxa);
-      b.jc1 = (int)floor(pxb);
-      b.ic0 = (int)floor(pya);
-      b.ic1 = (int)floor(pyb);
-      b.hj0 = (int)floor(pxa * 0.5 - 0.5);
-      b.hj1 = (int)floor(pxb * 0.5 - 0.5);
-      b.hi0 = (int)floor(pya * 0.5 - 0.5);
-      b.hi1 = (int)floor(pyb * 0.5 - 0.5);
+      const Bounds b = footprint(sm.sX[sm.sClo[kx]] + (double)v.x, sm.sX[sm.sChi[kx]] + (double)v.x,
+                                 sm.sY[sm.sRlo[ky]] + (double)v.y, sm.sY[sm.sRhi[ky]] + (double)v.y, g);
       sm.sTB[k] = b;
       atomicMin(&sm.sRed[0], b.jc0); atomicMin(&sm.sRed[1], -b.jc1);
       atomicMin(&sm.sRed[2], b.ic0); atomicMin(&sm.sRed[3], -b.ic1);
@@ -295,20 +286,12 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
         bd = sm.sTB[seg];
       }
       const int sty = whole ? -1 : seg / ntx, stx = whole ? -1 : seg % ntx;
-      const int oc0 = bd.hj0, ow = bd.hj1 - bd.hj0 + 2;
-      const int or0 = bd.hi0, oh = bd.hi1 - bd.hi0 + 2;
-      // luma window: the clamped corners' 3x3 neighbourhoods, the outer ring
-      // repeating the edge quads where it leaves the grid (Omega then reads
-      // it without clamps); raw window: the quads inside the grid and every
-      // nine-sample window
-      const int lc0 = clampi(bd.hj0, 0, g.w - 1) - 1;
-      const int lc1 = clampi(bd.hj1 + 1, 0, g.w - 1) + 1;
-      const int lr0 = clampi(bd.hi0, 0, g.h - 1) - 1;
-      const int lr1 = clampi(bd.hi1 + 1, 0, g.h - 1) + 1;
-      const int rc0 = min(2 * max(lc0, 0), bd.jc0 - 1), rc1 = max(2 * min(lc1, g.w - 1) + 1, bd.jc1 + 1);
-      const int rr0 = min(2 * max(lr0, 0), bd.ic0 - 1), rr1 = max(2 * min(lr1, g.h - 1) + 1, bd.ic1 + 1);
-      const int lw = lc1 - lc0 + 1, lh = lr1 - lr0 + 1;
-      const int rw = rc1 - rc0 + 1, rh = rr1 - rr0 + 1;
+      // the forward's windows (one alignment tile's always fit: its footprint
+      // stops at the frame's ring)
+      const Win wn = make_win(bd, g);
+      const int oc0 = wn.oc0, ow = wn.ow, or0 = wn.or0, oh = wn.oh;
+      const int lc0 = wn.lc0, lr0 = wn.lr0, lw = wn.lw, lh = wn.lh;
+      const int rc0 = wn.rc0, rr0 = wn.rr0, rw = wn.rw, rh = wn.rh;
       if (whole && (ow * oh > BCP::OM || lw * lh > BCP::LUMA || rw * rh > BCP::RAW)) {
         whole = false;
         seg = 0;
@@ -401,6 +384,7 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
           const double fjc = floor(px), fic = floor(py);
           const double frx = px - fjc, fry = py - fic;
           const int jc = (int)fjc, ic = (int)fic;
+          if (samples_outside(jc, ic, g)) continue;  // no in-frame sample: no term, no gradient
           const double hx = px * 0.5 - 0.5, hy = py * 0.5 - 0.5;
           const double fhj = floor(hx), fhi = floor(hy);
           const double fx = hx - fhj, fy = hy - fhi;
