@@ -342,6 +342,24 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs,
                                const float* const* motion, float* const* out, void* stream);
 
 /*
+ * hmfsr_batch_plan -- the work layout of the batch graph last captured on the
+ * current device (host values, no device work): the (burst, tile) items of
+ * the persistent robustness launch and of the persistent merge launch of
+ * each tile shape (indices as for hmfsr_autotune), and the workgroups each
+ * launch starts. A workgroup pulls items until the list is exhausted, so
+ * items / workgroups is how many it takes in turn. By default a launch starts
+ * min(items, compute units x resident workgroups per unit) workgroups;
+ * HMFSR_BATCH_GROUPS=<k> (k >= 1) caps every launch at k when a graph is
+ * captured (the cap is part of the graph's signature).
+ *  out  HOST. HMFSR_E_INVALID when no graph was captured on this device.
+ */
+typedef struct {
+  int32_t robust_items, robust_groups;
+  int32_t merge_items[4], merge_groups[4];
+} hmfsr_batch_info;
+hmfsr_status hmfsr_batch_plan(hmfsr_batch_info* out);
+
+/*
  * hmfsr_autotune -- time every compiled tile shape of the merge kernel on this
  * burst (synchronising `stream`), remember the fastest for the burst's class
  * (output scale <= 1, <= 1.5, <= 2, > 2 x frame count <= 4, <= 8, <= 15, > 15)

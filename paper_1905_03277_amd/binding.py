@@ -19,7 +19,7 @@ HMFSR_OK, HMFSR_E_INVALID, HMFSR_E_UNSUPPORTED, HMFSR_E_HIP, HMFSR_E_NOMEM = 0, 
 # Every symbol include/hmfsr.h declares.
 EXPORTED = ("hmfsr_merge", "hmfsr_merge_backward", "hmfsr_stream_begin", "hmfsr_stream_add",
             "hmfsr_stream_end", "hmfsr_align", "hmfsr_noise_table", "hmfsr_auto_tuning",
-            "hmfsr_merge_maps", "hmfsr_merge_batch", "hmfsr_autotune",
+            "hmfsr_merge_maps", "hmfsr_merge_batch", "hmfsr_batch_plan", "hmfsr_autotune",
             "hmfsr_profile_begin", "hmfsr_profile_end", "hmfsr_strerror", "hmfsr_version",
             "hmfsr_release")
 
@@ -64,6 +64,11 @@ class hmfsr_stage_times(ctypes.Structure):
     _fields_ = [("ms_total", ctypes.c_double * NUM_STAGES), ("launches", ctypes.c_int64 * NUM_STAGES)]
 
 
+class hmfsr_batch_info(ctypes.Structure):
+    _fields_ = [("robust_items", ctypes.c_int32), ("robust_groups", ctypes.c_int32),
+                ("merge_items", ctypes.c_int32 * 4), ("merge_groups", ctypes.c_int32 * 4)]
+
+
 class HmfsrError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -104,6 +109,8 @@ def lib() -> ctypes.CDLL:
         L.hmfsr_merge_batch.argtypes = [i32, pd, pt, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                          ctypes.POINTER(vp), vp]
         L.hmfsr_merge_batch.restype = i32
+        L.hmfsr_batch_plan.argtypes = [ctypes.POINTER(hmfsr_batch_info)]
+        L.hmfsr_batch_plan.restype = i32
         L.hmfsr_autotune.argtypes = [pd, pt, vp, vp, vp, vp, ctypes.POINTER(i32)]
         L.hmfsr_autotune.restype = i32
         L.hmfsr_profile_begin.argtypes = []
@@ -234,6 +241,15 @@ def hmfsr_merge_batch(descs, tunings, frames, motion, out, stream: int = 0) -> N
     M = (ctypes.c_void_p * n)(*motion)
     O = (ctypes.c_void_p * n)(*out)
     _check(lib().hmfsr_merge_batch(n, D, T, F, M, O, stream or None), "hmfsr_merge_batch")
+
+
+def hmfsr_batch_plan() -> dict:
+    """Items and workgroups of the persistent launches of the last captured
+    batch graph on the current device."""
+    info = hmfsr_batch_info()
+    _check(lib().hmfsr_batch_plan(ctypes.byref(info)), "hmfsr_batch_plan")
+    return {"robust_items": info.robust_items, "robust_groups": info.robust_groups,
+            "merge_items": list(info.merge_items), "merge_groups": list(info.merge_groups)}
 
 
 def hmfsr_autotune(desc, tuning, frames: int, motion: int, out: int, stream: int = 0) -> int:

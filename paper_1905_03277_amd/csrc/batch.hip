@@ -76,6 +76,21 @@ struct Layout {
   std::vector<size_t> burst_work;  // offset of each burst's Work inside the workspace
 };
 
+// HMFSR_BATCH_GROUPS: a cap on the workgroups of every persistent launch
+// (0 = none), so that each workgroup takes many items in turn.
+int batch_groups_cap() {
+  const char* env = getenv("HMFSR_BATCH_GROUPS");
+  if (!env) return 0;
+  const int k = atoi(env);
+  return k > 0 ? k : 0;
+}
+
+int capped(size_t items, size_t resident, int cap) {
+  size_t g = std::min(items, resident);
+  if (cap > 0) g = std::min(g, (size_t)cap);
+  return (int)std::max<size_t>(g, 1);
+}
+
 }  // namespace
 
 int merge_variant(const Geometry& g) {
@@ -245,7 +260,8 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
     ptrs.push_back(out[i]);
   }
   BatchPlan& P = ds.plan;
-  const bool same = P.exec && P.ws == ds.batch_ws && P.variants == var && P.ptrs == ptrs &&
+  const int cap = batch_groups_cap();
+  const bool same = P.exec && P.ws == ds.batch_ws && P.variants == var && P.ptrs == ptrs && P.groups_cap == cap &&
                     P.descs.size() == (size_t)n_bursts &&
                     memcmp(P.descs.data(), descs, sizeof(hmfsr_desc) * n_bursts) == 0;
   if (same) {
@@ -327,15 +343,20 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
   if (err == hipSuccess) err = launch_prior_batch(d_args, d_first, n_bursts, (int)n_prior, cs);
   if (err == hipSuccess)
     err = launch_guide_stats_batch(d_args, d_bfirst, (int)n_base, d_ffirst, (int)n_fmeans, n_bursts, cs);
+  hmfsr_batch_info info = {};
   if (err == hipSuccess && n_ritems) {
-    const int groups = (int)std::min<size_t>(n_ritems, (size_t)cus * robust_batch_blocks_per_cu());
+    const int groups = capped(n_ritems, (size_t)cus * robust_batch_blocks_per_cu(), cap);
     err = launch_robust_batch(d_args, d_ritems, (int)n_ritems, d_counters, groups, cs);
+    info.robust_items = (int32_t)n_ritems;
+    info.robust_groups = groups;
   }
   for (int v = 0; v < kNumMergeVariants && err == hipSuccess; ++v) {
     const int cnt = group_start[v + 1] - group_start[v];
     if (cnt == 0) continue;
-    const int groups = (int)std::min<size_t>(cnt, (size_t)cus * merge_batch_blocks_per_cu(v));
+    const int groups = capped(cnt, (size_t)cus * merge_batch_blocks_per_cu(v), cap);
     err = launch_merge_batch(v, d_args, d_mitems + group_start[v], cnt, d_counters + 1 + v, groups, cs);
+    info.merge_items[v] = cnt;
+    info.merge_groups[v] = groups;
   }
   const hipError_t end = hipStreamEndCapture(cs, &graph);
   if (err != hipSuccess || end != hipSuccess || !graph) {
@@ -355,9 +376,22 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
   P.ptrs = ptrs;
   P.descs.assign(descs, descs + n_bursts);
   P.tunings.assign(tunings, tunings + n_bursts);
+  P.groups_cap = cap;
+  P.info = info;
   return timed(HMFSR_STAGE_BATCH, s, [&] { return hipGraphLaunch(P.exec, s); }) == hipSuccess
              ? HMFSR_OK
              : HMFSR_E_HIP;
+}
+
+hmfsr_status hmfsr_batch_plan(hmfsr_batch_info* out) {
+  if (!out) return HMFSR_E_INVALID;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  int dev = 0;
+  hmfsr_status st;
+  if ((st = current_device(&dev)) != HMFSR_OK) return st;
+  if (!g_dev[dev].plan.exec) return HMFSR_E_INVALID;
+  *out = g_dev[dev].plan.info;
+  return HMFSR_OK;
 }
 
 }  // extern "C"

@@ -17,6 +17,8 @@ struct BatchPlan {
   std::vector<int> variants;
   void* ws = nullptr;             // batch workspace the graph's arguments point into
   std::vector<hmfsr_tuning> tunings;  // the tunings of the uploaded argument blocks
+  int groups_cap = 0;             // HMFSR_BATCH_GROUPS when captured (0: none)
+  hmfsr_batch_info info = {};     // items and workgroups of the persistent launches
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };

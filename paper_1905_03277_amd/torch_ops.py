@@ -281,6 +281,13 @@ def merge_batch(bursts, outs=None) -> list:
     return outs
 
 
+def batch_plan(device) -> dict:
+    """Items and workgroups of the persistent launches of the last batch graph
+    captured on ``device``."""
+    with torch.cuda.device(device):
+        return binding.hmfsr_batch_plan()
+
+
 def autotune(frames: torch.Tensor, motion: torch.Tensor, desc, tuning,
              out: torch.Tensor | None = None):
     """Run the tile-shape autotuner on one burst; returns (chosen index, output)."""

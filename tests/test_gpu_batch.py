@@ -116,3 +116,79 @@ def test_autotune_picks_a_shape_and_is_used(monkeypatch, tmp_path):
     np.testing.assert_array_equal(again.cpu().numpy(), ref.cpu().numpy())
     lines = (tmp_path / "tune.txt").read_text().split()
     assert lines[-1] == str(v)
+
+
+def items_per_group(plan):
+    """(items, workgroups) of every persistent launch of a batch plan."""
+    out = [(plan["robust_items"], plan["robust_groups"])] if plan["robust_items"] else []
+    out += [(i, g) for i, g in zip(plan["merge_items"], plan["merge_groups"]) if i]
+    return out
+
+
+@pytest.mark.parametrize("cap", [1, 3, 7])
+def test_persistent_loop_few_workgroups_bitwise(cap, monkeypatch):
+    """The persistent kernels with their workgroups capped at 1, 3 and 7, so
+    that each workgroup pulls many (burst, tile) items in turn, across bursts
+    of different frame counts, scales, tile sizes and CFAs, coherent and
+    divergent fields: every burst equals its per-burst hmfsr_merge bit for
+    bit (every output pixel of Sec. 5.1 is computed independently, so the
+    order and grouping of the items cannot matter)."""
+    monkeypatch.setenv("HMFSR_BATCH_GROUPS", str(cap))
+    bursts = make_bursts()
+    rng = np.random.default_rng(300 + cap)
+    for b in bursts[::3]:
+        m = b.motion.numpy().copy()
+        m[1:] += rng.uniform(-40.0, 40.0, size=m[1:].shape).astype(np.float32)
+        m[b.desc.ref_frame] = 0
+        b.motion = torch.from_numpy(m)
+    args = as_args(bursts)
+    want = per_burst(args)
+    outs = torch_ops.merge_batch(args)
+    torch.cuda.synchronize()
+    plan = torch_ops.batch_plan(DEV)
+    launches = items_per_group(plan)
+    print(f"[case] persistent cap {cap}: (items, workgroups) per launch {launches}", flush=True)
+    assert launches and all(g == min(cap, i) for i, g in launches)
+    # the robustness launch and the largest merge launch: many items per workgroup
+    assert launches[0][0] / launches[0][1] >= 3
+    assert max(i / g for i, g in launches[1:]) >= 3
+    for i, (o, w) in enumerate(zip(outs, want)):
+        np.testing.assert_array_equal(o.cpu().numpy(), w, err_msg=f"burst {i}")
+    # a replay of the same graph: the counters are reset by the graph itself
+    for o in outs:
+        o.fill_(-1.0)
+    torch_ops.merge_batch(args, outs)
+    torch.cuda.synchronize()
+    for i, (o, w) in enumerate(zip(outs, want)):
+        np.testing.assert_array_equal(o.cpu().numpy(), w, err_msg=f"replay burst {i}")
+
+
+def test_persistent_loop_full_size_members():
+    """A batch mixing a 12 MP x 8 burst at scale 1 and a 3 MP x 15 burst at
+    scale 2 (the headline and low-light shapes) with small bursts, at the
+    default workgroup count: every persistent launch gives each workgroup at
+    least three items. Bitwise equal to per-burst launches; the two large
+    members agree with the oracle on sampled windows."""
+    from parity_util import assert_parity, oracle_crop
+    big = [synth.make_config(2, device=DEV), synth.make_config(3, device=DEV)]
+    small = make_bursts()[:3]
+    args = [(b.frames, b.motion, b.desc, b.tuning) for b in big] + as_args(small)
+    print("[case] full-size batch: per-burst launches", flush=True)
+    want = [torch_ops.merge(f, m, d, t) for f, m, d, t in args]
+    torch.cuda.synchronize()
+    print("[case] full-size batch: graph", flush=True)
+    outs = torch_ops.merge_batch(args)
+    torch.cuda.synchronize()
+    launches = items_per_group(torch_ops.batch_plan(DEV))
+    print(f"[case] full-size batch: (items, workgroups) per launch {launches}", flush=True)
+    assert launches and all(i / g >= 3 for i, g in launches)
+    for i, (o, w) in enumerate(zip(outs, want)):
+        assert torch.equal(o, w), f"burst {i} differs from its per-burst launch"
+    S = 48
+    for b, o in zip(big, outs[:2]):
+        f, m = b.numpy()
+        OH, OW = o.shape[1:]
+        for oy, ox in ((0, OW - S), (OH // 2, OW // 3), (OH - S, OW // 2)):
+            print("[case] full-size batch window", b.desc.n_frames, oy, ox, flush=True)
+            want_w = oracle_crop(f, m, b.desc, b.tuning, oy, ox, S, S)
+            assert_parity(o[:, oy:oy + S, ox:ox + S].cpu().numpy(), want_w, f"batch member window ({oy},{ox})")
