@@ -52,7 +52,9 @@ typedef enum {
   HMFSR_E_INVALID = -1,     /* bad descriptor, tuning or NULL pointer          */
   HMFSR_E_UNSUPPORTED = -2, /* unknown CFA code, or a device that is not gfx950 */
   HMFSR_E_HIP = -3,         /* a HIP runtime call or kernel launch failed      */
-  HMFSR_E_NOMEM = -4        /* the internal workspace could not be allocated   */
+  HMFSR_E_NOMEM = -4,       /* the internal workspace could not be allocated   */
+  HMFSR_E_TOO_LARGE = -5    /* hmfsr_merge_noalloc: the burst's maps exceed its
+                               static scratch (HMFSR_NOALLOC_SCRATCH_BYTES)      */
 } hmfsr_status;
 
 /*
@@ -160,6 +162,31 @@ typedef struct {
 hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
                          const uint16_t* frames, const float* motion, float* out,
                          float* saved, void* stream);
+
+/*
+ * hmfsr_merge_noalloc -- hmfsr_merge for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc. Same arguments, kernels and results as hmfsr_merge (bit
+ * for bit, for the same tile shape), but the per-frame maps live in a
+ * static scratch array of HMFSR_NOALLOC_SCRATCH_BYTES per device, which the
+ * library's code object holds from load until the process ends; the call
+ * allocates nothing (no hipMalloc, hipFree, events or library allocations)
+ * and profiling does not time it.
+ *  Limit: the maps take about 16 bytes per half-resolution pixel and frame
+ *  (8 or 15 frames of 1024 x 768 and 4 frames of 2016 x 1512 fit; a
+ *  12 MP x 8 burst does not): a burst whose maps exceed the scratch returns
+ *  HMFSR_E_TOO_LARGE before any device work.
+ *  Every call on one device shares that device's scratch and nothing in it
+ *  has to start at zero (each call writes every entry it reads). Calls that
+ *  overlap on one device -- on different streams, or from different threads
+ *  without ordering -- race on the scratch: serialise them (one stream).
+ *  The first call on a device resolves the scratch's device address
+ *  (hipGetSymbolAddress) and keeps it.
+ */
+#define HMFSR_NOALLOC_SCRATCH_BYTES (64u << 20)
+hmfsr_status hmfsr_merge_noalloc(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
+                                 const uint16_t* frames, const float* motion, float* out,
+                                 float* saved, void* stream);
 
 /*
  * hmfsr_merge_backward -- adjoint of hmfsr_merge. Given dL/dC for the output C

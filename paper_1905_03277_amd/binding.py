@@ -15,9 +15,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhmfsr.so")
 
 HMFSR_OK, HMFSR_E_INVALID, HMFSR_E_UNSUPPORTED, HMFSR_E_HIP, HMFSR_E_NOMEM = 0, -1, -2, -3, -4
+HMFSR_E_TOO_LARGE = -5
+NOALLOC_SCRATCH_BYTES = 64 << 20   # HMFSR_NOALLOC_SCRATCH_BYTES
 
 # Every symbol include/hmfsr.h declares.
-EXPORTED = ("hmfsr_merge", "hmfsr_merge_backward", "hmfsr_stream_begin", "hmfsr_stream_add",
+EXPORTED = ("hmfsr_merge", "hmfsr_merge_noalloc", "hmfsr_merge_backward", "hmfsr_stream_begin", "hmfsr_stream_add",
             "hmfsr_stream_end", "hmfsr_align", "hmfsr_noise_table", "hmfsr_auto_tuning",
             "hmfsr_merge_maps", "hmfsr_merge_batch", "hmfsr_batch_plan", "hmfsr_autotune",
             "hmfsr_profile_begin", "hmfsr_profile_end", "hmfsr_strerror", "hmfsr_version",
@@ -90,6 +92,8 @@ def lib() -> ctypes.CDLL:
         pd, pt = ctypes.POINTER(hmfsr_desc), ctypes.POINTER(hmfsr_tuning)
         L.hmfsr_merge.argtypes = [pd, pt, vp, vp, vp, vp, vp]
         L.hmfsr_merge.restype = i32
+        L.hmfsr_merge_noalloc.argtypes = [pd, pt, vp, vp, vp, vp, vp]
+        L.hmfsr_merge_noalloc.restype = i32
         L.hmfsr_merge_backward.argtypes = [pd, pt, vp, vp, vp, vp, vp, vp, vp]
         L.hmfsr_merge_backward.restype = i32
         L.hmfsr_stream_begin.argtypes = [pd, pt, vp, vp, vp]
@@ -170,6 +174,12 @@ def hmfsr_merge(desc: hmfsr_desc, tuning: hmfsr_tuning, frames: int, motion: int
                 saved: int = 0, stream: int = 0) -> None:
     _check(lib().hmfsr_merge(ctypes.byref(desc), ctypes.byref(tuning), frames, motion, out,
                              saved or None, stream or None), "hmfsr_merge")
+
+
+def hmfsr_merge_noalloc(desc: hmfsr_desc, tuning: hmfsr_tuning, frames: int, motion: int, out: int,
+                        saved: int = 0, stream: int = 0) -> None:
+    _check(lib().hmfsr_merge_noalloc(ctypes.byref(desc), ctypes.byref(tuning), frames, motion, out,
+                                     saved or None, stream or None), "hmfsr_merge_noalloc")
 
 
 def hmfsr_merge_backward(desc: hmfsr_desc, tuning: hmfsr_tuning, frames: int, motion: int,

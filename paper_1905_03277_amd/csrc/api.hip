@@ -250,19 +250,18 @@ hmfsr_status make_align_geom(const hmfsr_desc* d, const hmfsr_align_params* p, A
 
 hmfsr_status run_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, const Geometry& g,
                        const uint16_t* frames, const float* motion, float* out, float* saved,
-                       const Work& w, int variant, hipStream_t s) {
+                       const Work& w, int variant, hipStream_t s, bool profiled) {
   const PriorConsts pc = make_prior(tuning);
   const RobustConsts rc = make_robust(desc, tuning);
   const MergeConsts mc = make_merge(desc, tuning, g);
-  if (timed(HMFSR_STAGE_PRIOR, s, [&] { return launch_prior(g, pc, motion, w, s); }) != hipSuccess)
+  auto run = [&](int stage, auto fn) { return profiled ? timed(stage, s, fn) : fn(); };
+  if (run(HMFSR_STAGE_PRIOR, [&] { return launch_prior(g, pc, motion, w, s); }) != hipSuccess)
     return HMFSR_E_HIP;
-  if (timed(HMFSR_STAGE_ROBUST, s, [&] {
-        return launch_robust(g, rc, frames, motion, w, w.rmin, nullptr, s);
-      }) != hipSuccess)
+  if (run(HMFSR_STAGE_ROBUST, [&] { return launch_robust(g, rc, frames, motion, w, w.rmin, nullptr, s); }) !=
+      hipSuccess)
     return HMFSR_E_HIP;
-  if (timed(HMFSR_STAGE_MERGE, s, [&] {
-        return launch_merge(variant, g, mc, frames, motion, w.rmin, out, saved, s);
-      }) != hipSuccess)
+  if (run(HMFSR_STAGE_MERGE, [&] { return launch_merge(variant, g, mc, frames, motion, w.rmin, out, saved, s); }) !=
+      hipSuccess)
     return HMFSR_E_HIP;
   return HMFSR_OK;
 }
@@ -562,6 +561,8 @@ const char* hmfsr_strerror(hmfsr_status status) {
     case HMFSR_E_UNSUPPORTED: return "HMFSR_E_UNSUPPORTED: unknown CFA or device is not gfx950";
     case HMFSR_E_HIP: return "HMFSR_E_HIP: HIP runtime or launch error";
     case HMFSR_E_NOMEM: return "HMFSR_E_NOMEM: workspace allocation failed";
+    case HMFSR_E_TOO_LARGE:
+      return "HMFSR_E_TOO_LARGE: the burst's maps exceed hmfsr_merge_noalloc's static scratch (64 MiB)";
   }
   return "HMFSR: unknown status";
 }

@@ -88,9 +88,11 @@ hmfsr_status grow_buffer(void*& buf, size_t& have, size_t bytes, hipStream_t str
 // Merge tile shape for a burst: HMFSR_MERGE_VARIANT, else the autotuned
 // choice for the burst's (scale, frame count) class, else the default.
 int merge_variant(const Geometry& g);
-// The three kernels of one merge on `s` (workspace from `workspace`).
+// The three kernels of one merge on `s` (workspace from `workspace`). With
+// `profiled` false the launches are never bracketed by timing events (which
+// the event pool may have to create).
 hmfsr_status run_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, const Geometry& g,
                        const uint16_t* frames, const float* motion, float* out, float* saved,
-                       const Work& w, int variant, hipStream_t s);
+                       const Work& w, int variant, hipStream_t s, bool profiled = true);
 
 }  // namespace hmfsr

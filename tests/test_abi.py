@@ -192,3 +192,17 @@ def test_noise_table_and_auto_tuning_validate_on_the_host():
 def test_desc_struct_has_no_padding():
     # the batch graph compares descriptors with memcmp
     assert ctypes.sizeof(binding.hmfsr_desc) == 14 * 4 + 8
+
+
+def test_noalloc_refuses_bursts_beyond_its_scratch_on_the_host():
+    """hmfsr_merge_noalloc checks the burst's map size against its static
+    scratch before any HIP call (the dummy pointers are never used)."""
+    d = synth.Desc(8, 3024, 4032, tile_size=16, scale=1.0)   # 12 MP x 8: ~390 MB of maps
+    desc, tun = binding.make_desc(d), binding.make_tuning(synth.TUNING_SNR22)
+    st = binding.lib().hmfsr_merge_noalloc(ctypes.byref(desc), ctypes.byref(tun), 16, 16, 16, None, None)
+    assert st == binding.HMFSR_E_TOO_LARGE
+    assert "static scratch" in binding.strerror(st)
+    bad = binding.make_desc(synth.Desc(4, 64, 96, tile_size=16, scale=1.5))
+    bad.height = 63
+    assert binding.lib().hmfsr_merge_noalloc(ctypes.byref(bad), ctypes.byref(tun), 16, 16, 16, None,
+                                             None) == binding.HMFSR_E_INVALID
