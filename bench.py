@@ -6,10 +6,11 @@ resident in HBM. Prints one JSON line with input-Bayer MP/s, the dominant
 kernel's roofline position and the FP64 oracle's CPU rate on a bounded sample.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
-                    [--no-batch] [--no-grad] [--no-stream] [--no-align]
+                    [--no-batch] [--no-grad] [--no-stream] [--no-align] [--no-configs]
 
 More legs follow the headline measurement and are reported inside its line:
-the same burst merged frame by frame through the streaming calls, its tile
+the low-light workload (15 x 1512 x 2016 at scale 2) and the small 8 x 256 x
+256 burst, the same burst merged frame by frame through the streaming calls, its tile
 alignment and the raw-burst-to-RGB time (alignment then merge), the
 64-burst batched workload (one graph replay vs per-burst launches) and the
 differentiation workload (16 bursts of 8 x 768 x 1024 at scale 2, forward
@@ -104,40 +105,107 @@ def calibration_copy(dev):
     del a, b
 
 
-def cpu_baseline(burst, budget_s: float = 12.0):
-    """Time the FP64 oracle on windows of the same burst on this host's cores."""
-    import numpy as np
-    try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(limits=1)
-    except Exception:  # pragma: no cover
-        limiter = None
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
+def _plain(obj) -> dict:
+    """A descriptor or tuning as a plain dict (the oracle reads either)."""
+    import dataclasses
+    return {f.name: getattr(obj, f.name) for f in dataclasses.fields(obj) if f.name != "noise_table"}
+
+
+def _oracle_window(job):
+    """One oracle merge of an output window (runs in a worker process with one
+    thread): returns the input Bayer pixels behind the window."""
+    fr, mo, dd, tun, ry, rx, in_px = job
+    from threadpoolctl import threadpool_limits
     import oracle.merge as om
+    with threadpool_limits(limits=1):
+        om.merge_window(fr, mo, dd, tun, ry, rx)
+    return in_px
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(burst, single_s: float = 8.0, all_s: float = 25.0, max_workers: int = 16):
+    """Time the FP64 oracle on the same burst on this host's cores: one thread
+    on windows of 256 x 256 output pixels, then every core (one single-thread
+    worker process each, at most ``max_workers``) on row bands of the whole
+    image, until the bands run out or the time budget does."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
     from parity_util import crop_case
 
     f, m = burst.numpy()
-    S = 256
     d = burst.desc
+    dd, tun = _plain(d), _plain(burst.tuning)
+    n = d.n_frames
+
+    # single thread, windows spread over the image
+    S = 256
     spots = [(d.out_height // 2, d.out_width // 2), (d.out_height // 4, d.out_width // 4),
              (3 * d.out_height // 4, d.out_width // 3)]
-    px = 0
+    px = 0.0
     t0 = time.perf_counter()
     i = 0
-    while True:
+    while time.perf_counter() - t0 < single_s:
         oy, ox = spots[i % len(spots)]
-        fr, mo, dd, ry, rx = crop_case(f, m, d, oy, ox, S, S)
-        om.merge_window(fr, mo, dd, burst.tuning, ry, rx)
-        px += d.n_frames * (S / d.scale) * (S / d.scale)   # input Bayer pixels behind the window
+        fr, mo, dc, ry, rx = crop_case(f, m, d, oy, ox, S, S)
+        px += _oracle_window((fr, mo, _plain(dc), tun, ry, rx, n * (S / d.scale) ** 2))
         i += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    if limiter is not None:
-        limiter.unregister()
-    return {"value": px / dt / 1e6, "unit": "MP/s", "cores": 1, "kind": "oracle",
-            "sample": f"{i} windows of {S}x{S} output px (x{d.n_frames} frames) of the same burst, "
-                      f"{dt:.1f} s, single thread"}
+    dt1 = time.perf_counter() - t0
+    single = px / dt1 / 1e6
+
+    # every core: bands of 192 output rows covering the whole output
+    cores = len(os.sched_getaffinity(0))
+    workers = max(1, min(cores, max_workers))
+    band = 192
+    jobs = []
+    for oy in range(0, d.out_height, band):
+        rows = min(band, d.out_height - oy)
+        fr, mo, dc, ry, rx = crop_case(f, m, d, oy, 0, rows, d.out_width)
+        jobs.append((fr, mo, _plain(dc), tun, ry, rx, n * rows * d.out_width / d.scale ** 2))
+    done_px, done = 0.0, 0
+    env_threads = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env_threads:
+        os.environ[k] = "1"
+    try:
+        with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+            list(ex.map(_oracle_window, [jobs[0]] * workers))   # start the workers and their imports
+            t0 = time.perf_counter()
+            pending = {ex.submit(_oracle_window, j) for j in jobs}
+            while pending:
+                fin, pending = cf.wait(pending, timeout=max(0.1, all_s - (time.perf_counter() - t0)),
+                                       return_when=cf.FIRST_COMPLETED)
+                for fu in fin:
+                    done_px += fu.result()
+                    done += 1
+                if time.perf_counter() - t0 >= all_s:
+                    for fu in pending:
+                        fu.cancel()
+                    break
+            dt = time.perf_counter() - t0
+    finally:
+        for k, v in env_threads.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    whole = done == len(jobs)
+    return {"value": round(done_px / dt / 1e6, 3), "unit": "MP/s", "cores": workers, "kind": "oracle",
+            "sample": (f"{done} of {len(jobs)} bands of {band} output rows x {d.out_width} px (x{n} frames, "
+                       f"each with its input halo) of the 12 MP x 8 burst, {dt:.1f} s, {workers} single-thread "
+                       f"worker processes" + (" (the whole image)" if whole else "")),
+            "host_cores_available": cores, "cpu_model": cpu_model(),
+            "single_thread": {"value": round(single, 3), "unit": "MP/s", "cores": 1,
+                              "sample": f"{i} windows of {S}x{S} output px (x{n} frames), {dt1:.1f} s"}}
 
 
 def bench_batch(dev, reps: int = 3) -> dict:
@@ -196,6 +264,52 @@ def bench_batch(dev, reps: int = 3) -> dict:
             "per_burst_MPs_loop": {"min": round(rates[0], 1), "median": round(rates[len(rates) // 2], 1),
                                    "max": round(rates[-1], 1)},
             "tuned_shapes": {f"{k[0]}/{k[1]}": v for k, v in tuned.items()}}
+
+
+def bench_config(cfg: int, dev, reps: int = 10) -> dict:
+    """Forward merge of another workload: config 3 (Super-Res Zoom low light,
+    15 x 1512 x 2016 at scale 2, SNR-11 tuning) or config 1 (8 x 256 x 256 at
+    scale 1, launch-bound). Whole-merge rate by events, per-kernel times by
+    the library's event timing, and k_merge's position on the ALU roofline."""
+    import torch
+    from paper_1905_03277_amd import binding, synth, torch_ops
+
+    print(f"[bench] config {cfg}", file=sys.stderr, flush=True)
+    b = synth.make_config(cfg, device=dev)
+    d = b.desc
+    out = torch.empty((3, d.out_height, d.out_width), dtype=torch.float32, device=dev)
+
+    def step():
+        torch_ops.merge(b.frames, b.motion, d, b.tuning, out=out)
+
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    binding.hmfsr_profile_begin()
+    for _ in range(reps):
+        step()
+    kern = {k: tot / max(cnt, 1) for k, (tot, cnt) in binding.hmfsr_profile_end().items()}
+    in_mp = d.n_frames * d.height * d.width / 1e6
+    ops = algorithmic_ops(d)["k_merge"]
+    ach = ops / (kern["k_merge"] / 1e3) / 1e12
+    byts = algorithmic_bytes(d)["total"]
+    return {"workload": f"forward merge, {d.n_frames} frames {d.width}x{d.height} RGGB, scale {d.scale:g}, "
+                        f"{d.tile_size} px tiles",
+            "ms": round(ms, 4), "MPs": round(in_mp / (ms / 1e3), 1),
+            "output_MPix_per_frame_ms": round(ms / (d.n_frames * d.out_height * d.out_width / 1e6), 5),
+            "kernels_ms": {k: round(v, 4) for k, v in kern.items()},
+            "roofline": {"bound": "alu", "kernel": "k_merge", "achieved": round(ach, 3),
+                         "peak": round(ALU_PEAK_TOPS, 2), "unit": "Top/s", "frac": round(ach / ALU_PEAK_TOPS, 4),
+                         "algorithmic_ops": ops},
+            "hbm_frac": round(byts / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def bench_stream(burst, out, reps: int = 5) -> dict:
@@ -411,6 +525,7 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the forward + adjoint leg")
     ap.add_argument("--no-stream", action="store_true", help="skip the frame-by-frame streaming leg")
     ap.add_argument("--no-align", action="store_true", help="skip the alignment / raw-to-RGB leg")
+    ap.add_argument("--no-configs", action="store_true", help="skip the config-3 and config-1 legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus 1); the merge shards by "
@@ -488,6 +603,9 @@ def main():
                 "frac": round(byts["total"] / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "wall_s_timed": round(wall, 3),
     }
+    if not args.no_configs:
+        line["config3_low_light"] = bench_config(3, dev)
+        line["config1_small"] = bench_config(1, dev)
     if not args.no_stream:
         line["streaming"] = bench_stream(burst, out)
     if not args.no_align:

@@ -26,7 +26,15 @@
  *  - Outputs are overwritten, never accumulated into.
  *  - Descriptor and tuning values are validated on the host before any
  *    device work: invalid values give HMFSR_E_INVALID and touch nothing.
- *    Device data (frames, motion) is not inspected.
+ *    Device data (frames, motion) is not inspected: a non-finite
+ *    displacement component is taken as +-(max(width, height) + 16) (NaN as
+ *    the negative bound), just past the frame, where no sample lies in it, so
+ *    the frame adds nothing there. With the environment variable
+ *    HMFSR_DEBUG=1, hmfsr_merge, hmfsr_merge_backward, hmfsr_merge_maps,
+ *    hmfsr_stream_add and hmfsr_merge_batch first scan the motion vectors of
+ *    the frames other than the base frame on the device (synchronising
+ *    `stream`) and return HMFSR_E_DATA, with a line on stderr naming the
+ *    first non-finite value, before any other work.
  */
 #ifndef HMFSR_H
 #define HMFSR_H
@@ -53,8 +61,9 @@ typedef enum {
   HMFSR_E_UNSUPPORTED = -2, /* unknown CFA code, or a device that is not gfx950 */
   HMFSR_E_HIP = -3,         /* a HIP runtime call or kernel launch failed      */
   HMFSR_E_NOMEM = -4,       /* the internal workspace could not be allocated   */
-  HMFSR_E_TOO_LARGE = -5    /* hmfsr_merge_noalloc: the burst's maps exceed its
+  HMFSR_E_TOO_LARGE = -5,   /* hmfsr_merge_noalloc: the burst's maps exceed its
                                static scratch (HMFSR_NOALLOC_SCRATCH_BYTES)      */
+  HMFSR_E_DATA = -6         /* HMFSR_DEBUG=1 only: device data failed a check  */
 } hmfsr_status;
 
 /*

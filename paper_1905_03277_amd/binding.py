@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhmfsr.so")
 
 HMFSR_OK, HMFSR_E_INVALID, HMFSR_E_UNSUPPORTED, HMFSR_E_HIP, HMFSR_E_NOMEM = 0, -1, -2, -3, -4
-HMFSR_E_TOO_LARGE = -5
+HMFSR_E_TOO_LARGE, HMFSR_E_DATA = -5, -6
 NOALLOC_SCRATCH_BYTES = 64 << 20   # HMFSR_NOALLOC_SCRATCH_BYTES
 
 # Every symbol include/hmfsr.h declares.

@@ -285,6 +285,7 @@ hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning, con
   const Geometry g = make_geometry(desc);
   void* ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
+  if (debug_enabled() && (st = debug_check_motion(dev, motion, g.n, g.ref, g.TY, g.TX, s)) != HMFSR_OK) return st;
   if ((st = workspace(dev, work_bytes(g), s, &ws)) != HMFSR_OK) return st;
   return run_merge(desc, tuning, g, frames, motion, out, saved, work_carve(ws, g), merge_variant(g), s);
 }
@@ -328,6 +329,7 @@ hmfsr_status hmfsr_stream_add(const hmfsr_desc* desc, const hmfsr_tuning* tuning
   const size_t mbytes = (size_t)g.TY * g.TX * 2 * sizeof(float);
   const size_t off_m = (2 * fbytes + 255) / 256 * 256, off_w = off_m + (2 * mbytes + 255) / 256 * 256;
   hipStream_t s = (hipStream_t)stream;
+  if (debug_enabled() && (st = debug_check_motion(dev, motion, 1, -1, g.TY, g.TX, s)) != HMFSR_OK) return st;
   void* ws = nullptr;
   if ((st = stream_workspace(dev, off_w + work_bytes(g), s, &ws)) != HMFSR_OK) return st;
   uint16_t* frames = (uint16_t*)ws;
@@ -381,6 +383,7 @@ hmfsr_status hmfsr_merge_backward(const hmfsr_desc* desc, const hmfsr_tuning* tu
   if ((st = current_device(&dev)) != HMFSR_OK) return st;
   const Geometry g = make_geometry(desc);
   hipStream_t s = (hipStream_t)stream;
+  if (debug_enabled() && (st = debug_check_motion(dev, motion, g.n, g.ref, g.TY, g.TX, s)) != HMFSR_OK) return st;
   void* ws = nullptr;
   const bool need_saved = saved == nullptr;
   if ((st = bwd_workspace(dev, bwd_bytes(g, need_saved), s, &ws)) != HMFSR_OK) return st;
@@ -438,6 +441,7 @@ hmfsr_status hmfsr_merge_maps(const hmfsr_desc* desc, const hmfsr_tuning* tuning
   const Geometry g = make_geometry(desc);
   void* ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
+  if (debug_enabled() && (st = debug_check_motion(dev, motion, g.n, g.ref, g.TY, g.TX, s)) != HMFSR_OK) return st;
   if ((st = workspace(dev, work_bytes(g), s, &ws)) != HMFSR_OK) return st;
   const Work w = work_carve(ws, g);
   const size_t plane = (size_t)g.h * g.w;
@@ -561,6 +565,7 @@ const char* hmfsr_strerror(hmfsr_status status) {
     case HMFSR_E_UNSUPPORTED: return "HMFSR_E_UNSUPPORTED: unknown CFA or device is not gfx950";
     case HMFSR_E_HIP: return "HMFSR_E_HIP: HIP runtime or launch error";
     case HMFSR_E_NOMEM: return "HMFSR_E_NOMEM: workspace allocation failed";
+    case HMFSR_E_DATA: return "HMFSR_E_DATA: device data failed an HMFSR_DEBUG check (non-finite motion)";
     case HMFSR_E_TOO_LARGE:
       return "HMFSR_E_TOO_LARGE: the burst's maps exceed hmfsr_merge_noalloc's static scratch (64 MiB)";
   }
@@ -607,7 +612,7 @@ void hmfsr_release(void) {
   const bool have_cur = hipGetDevice(&cur) == hipSuccess;
   for (int d = 0; d < kMaxDevices; ++d) {
     DeviceState& st = g_dev[d];
-    if (!st.workspace && !st.batch_ws && !st.bwd_ws && !st.stream_ws && !st.align_ws && !st.sum_ws &&
+    if (!st.workspace && !st.batch_ws && !st.bwd_ws && !st.stream_ws && !st.align_ws && !st.sum_ws && !st.debug_ws &&
         !st.plan.exec && !st.capture_stream)
       continue;
     if (hipSetDevice(d) != hipSuccess) continue;
@@ -626,6 +631,9 @@ void hmfsr_release(void) {
     if (st.sum_ws) (void)hipFree(st.sum_ws);
     st.sum_ws = nullptr;
     st.sum_ws_bytes = 0;
+    if (st.debug_ws) (void)hipFree(st.debug_ws);
+    st.debug_ws = nullptr;
+    st.debug_ws_bytes = 0;
     if (st.capture_stream) (void)hipStreamDestroy(st.capture_stream);
     st.workspace = st.batch_ws = st.bwd_ws = nullptr;
     st.workspace_bytes = st.batch_ws_bytes = st.bwd_ws_bytes = 0;

@@ -175,6 +175,11 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
   if ((st = current_device(&dev)) != HMFSR_OK) return st;
   DeviceState& ds = g_dev[dev];
   hipStream_t s = (hipStream_t)stream;
+  if (debug_enabled())
+    for (int i = 0; i < n_bursts; ++i) {
+      const Geometry gi = make_geometry(&descs[i]);
+      if ((st = debug_check_motion(dev, motion[i], gi.n, gi.ref, gi.TY, gi.TX, s)) != HMFSR_OK) return st;
+    }
 
   // per-burst geometry, tile shape and work sizes
   std::vector<Geometry> geo(n_bursts);

@@ -38,6 +38,8 @@ struct DeviceState {
   size_t align_ws_bytes = 0;
   void* sum_ws = nullptr;     // frame sums for the SNR-dependent tuning
   size_t sum_ws_bytes = 0;
+  void* debug_ws = nullptr;   // HMFSR_DEBUG: the device checks' result word
+  size_t debug_ws_bytes = 0;
   hipStream_t capture_stream = nullptr;
   BatchPlan plan;
 };
@@ -84,6 +86,13 @@ hmfsr_status stream_workspace(int dev, size_t bytes, hipStream_t stream, void** 
 hmfsr_status align_workspace(int dev, size_t bytes, hipStream_t stream, void** out);  // caller holds g_mutex
 // Grow a per-device buffer (caller holds g_mutex).
 hmfsr_status grow_buffer(void*& buf, size_t& have, size_t bytes, hipStream_t stream, void** out);
+
+// HMFSR_DEBUG set (and not "0"): calls check their device data first.
+bool debug_enabled();
+// Scan motion [n][TY][TX][2] (frame `ref` skipped; ref < 0: none) for
+// non-finite values; synchronises `s`. HMFSR_E_DATA (and a line on stderr
+// naming the first one) if any (caller holds g_mutex).
+hmfsr_status debug_check_motion(int dev, const float* motion, int n, int ref, int TY, int TX, hipStream_t s);
 
 // Merge tile shape for a burst: HMFSR_MERGE_VARIANT, else the autotuned
 // choice for the burst's (scale, frame count) class, else the default.

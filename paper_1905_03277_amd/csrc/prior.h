@@ -11,6 +11,9 @@ namespace hmfsr {
 // M_x (M_y) is the spread of the horizontal (vertical) displacements over the
 // 3x3 tile neighbourhood, tiles outside the grid skipped; M > M_th is
 // evaluated as M_x^2 + M_y^2 > M_th^2, rounded operation by operation.
+// A non-finite component counts as the bound the merge and robustness kernels
+// clamp it to (+-(max(W, H) + 16), NaN as the negative one); finite values are
+// used as they are.
 __device__ __forceinline__ bool prior_moving(const float* __restrict__ motion, const Geometry& g,
                                              double m_th, int n, int ty, int tx) {
   double xmax = -INFINITY, xmin = INFINITY, ymax = -INFINITY, ymin = INFINITY;
@@ -19,7 +22,10 @@ __device__ __forceinline__ bool prior_moving(const float* __restrict__ motion, c
       const int y = ty + a, x = tx + b;
       if (y < 0 || y >= g.TY || x < 0 || x >= g.TX) continue;
       const float* v = motion + (((size_t)n * g.TY + y) * g.TX + x) * 2;
-      const double vx = v[0], vy = v[1];
+      const float vlim = (float)(max(g.W, g.H) + 16);
+      const float fx = v[0], fy = v[1];
+      const double vx = isfinite(fx) ? fx : fminf(fmaxf(fx, -vlim), vlim);
+      const double vy = isfinite(fy) ? fy : fminf(fmaxf(fy, -vlim), vlim);
       xmax = fmax(xmax, vx);
       xmin = fmin(xmin, vx);
       ymax = fmax(ymax, vy);
