@@ -22,6 +22,10 @@
 //                 pixel in LDS, into six per-thread sums;
 //               - dL/drho, transposed through the fixed R_hat bilinear weights
 //                 onto the tile's R_hat window (per-workgroup partials).
+//               Both sums over a row's pixels are segmented scans across the
+//               wave's lanes (lane = output column; the alignment tile and the
+//               R_hat corner columns of a lane are fixed runs), then sums over
+//               the tile's rows through LDS.
 // k_robust_bwd  one workgroup per (aligned frame, alignment tile): gathers
 //               dL/dR_hat, hands it to the 5x5 argmin of eq. (9), then
 //               through the clamp and exponential of eq. (5) and the
@@ -57,7 +61,6 @@ struct BwdSmem {
   int sRya[BMH], sRyb[BMH];           // R_hat window rows of each pixel row
   int sRxa[MW], sRxb[MW];             // R_hat window columns of each pixel column
   float sRfx[MW];
-  int sJlo[BCP::RH_W], sJhi[BCP::RH_W];  // pixel columns touching each window column
   int sIlo[BCP::RH_H], sIhi[BCP::RH_H];  // pixel rows touching each window row
   float2 sV[BCP::VT];
   Bounds sTB[BCP::VT];
@@ -71,16 +74,29 @@ struct BwdSmem {
   float4 sP[2][BCP::OM];
   float2 sP2[BCP::OM];
   float sRh[BCP::RH];
-  float sGr[BMH][MW];    // dL/drho per pixel, this frame
-  float2 sGp[BMH][MW];   // dL/dp per pixel, this frame
-  double2 sHm[BMH][BCP::TX];
-  float sHr[BMH][BCP::RH_W];
+  double2 sHm[BMH][BCP::TX];     // per pixel row and alignment tile column: sum of dL/dp
+  float sHa[BMH][BCP::RH_W];     // per pixel row and R_hat column: dL/drho through the left corners
+  float sHb[BMH][BCP::RH_W];     // ... through the right corners
+  int sRun[MW];  // per lane: first lane of its runs (alignment tile, left and right R_hat corner column)
   double sAcc[BWAVES][6];
   int sRed[8];
   int sRh0[4];
 };
 
 __device__ __forceinline__ float pick3(const float (&a)[3], int c) { return c == 0 ? a[0] : (c == 1 ? a[1] : a[2]); }
+
+// Inclusive sum of v over lanes [start, lane] (start <= lane: the first lane
+// of this lane's run of equal keys), Hillis-Steele order: the run's last lane
+// then holds the run's sum, with the same bits on every call.
+template <typename T>
+__device__ __forceinline__ T run_sum(T v, int lane, int start) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T u = __shfl_up(v, off, 64);
+    if (lane - off >= start) v += u;
+  }
+  return v;
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -162,19 +178,9 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
     sm.sRfx[tid] = rfx;
   }
   __syncthreads();
-  // pixel columns (rows) whose R_hat corners include window column J (row I):
-  // the corners are monotonic in the pixel position.
-  if (tid < rhw) {
-    int lo = ncol, hi = -1;
-    for (int c = 0; c < ncol; ++c) {
-      if (sm.sRxa[c] <= tid && tid <= sm.sRxb[c]) {
-        lo = min(lo, c);
-        hi = c;
-      }
-    }
-    sm.sJlo[tid] = lo;
-    sm.sJhi[tid] = hi;
-  } else if (tid >= 64 && tid < 64 + rhh) {
+  // pixel rows whose R_hat corners include window row I: the corners are
+  // monotonic in the pixel position.
+  if (tid >= 64 && tid < 64 + rhh) {
     const int I = tid - 64;
     int lo = nrow, hi = -1;
     for (int r = 0; r < nrow; ++r) {
@@ -188,6 +194,23 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
   }
   const int txl = sm.sTxCol[lane] - txA;
   const float vlim = (float)(max(g.W, g.H) + 16);
+  // runs of lanes (output columns) sharing an alignment tile column, a left
+  // and a right R_hat corner column: each lane's first lane of its run (bits
+  // 0-6, 8-14, 16-22) and whether it is the run's last (bits 7, 15, 23);
+  // columns past the tile are runs of their own and never the last of one
+  if (tid < MW) {
+    int run_t = lane, run_a = lane, run_b = lane;
+    bool end_t = false, end_a = false, end_b = false;
+    if (col_ok) {
+      run_t = sm.sClo[txl];
+      end_t = lane == sm.sChi[txl];
+      while (run_a > 0 && sm.sRxa[run_a - 1] == rxa) --run_a;
+      while (run_b > 0 && sm.sRxb[run_b - 1] == rxb) --run_b;
+      end_a = lane == ncol - 1 || sm.sRxa[lane + 1] != rxa;
+      end_b = lane == ncol - 1 || sm.sRxb[lane + 1] != rxb;
+    }
+    sm.sRun[lane] = run_t | (end_t << 7) | (run_a << 8) | (end_a << 15) | (run_b << 16) | (end_b << 23);
+  }
 
   // ---- the forward's normaliser and dL/dC per pixel ----------------------
   // C is kept as a float pair (hi + lo): x - C is then accurate to a float
@@ -256,11 +279,10 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
     }
     // clamping keeps non-finite or huge vectors finite and changes no result
     if (tid < ntiles) sm.sV[tid] = make_float2(fminf(fmaxf(v.x, -vlim), vlim), fminf(fmaxf(v.y, -vlim), vlim));
+    // this frame's dL/drho and dL/dp of the thread's pixels (0 where skipped)
+    float pgr[BPX], pgx[BPX], pgy[BPX];
 #pragma unroll
-    for (int p = 0; p < BPX; ++p) {
-      sm.sGr[wave * BPX + p][lane] = 0.f;
-      sm.sGp[wave * BPX + p][lane] = make_float2(0.f, 0.f);
-    }
+    for (int p = 0; p < BPX; ++p) pgr[p] = pgx[p] = pgy[p] = 0.f;
     __syncthreads();
     for (int k = tid; k < ntiles; k += BTHREADS) {
       const int ky = k / ntx, kx = k - ky * ntx;
@@ -512,10 +534,9 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
           }
 #pragma unroll
           for (int e = 0; e < 6; ++e) acc[e] += (double)s6[e];
-          if (!is_ref) {
-            sm.sGr[r][lane] = grho;
-            sm.sGp[r][lane] = make_float2(gpx, gpy);
-          }
+          pgr[p] = grho;
+          pgx[p] = gpx;
+          pgy[p] = gpy;
         }
       }
       if (whole || ++seg >= ntiles) break;
@@ -523,28 +544,40 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
     }
 
     if (!is_ref) {
-      __syncthreads();
-      // rows x (alignment tile columns, R_hat window columns)
-      const int per_row = ntx + rhw;
-      for (int k = tid; k < nrow * per_row; k += BTHREADS) {
-        const int r = k / per_row, q = k - r * per_row;
-        if (q < ntx) {
-          double sx = 0.0, sy = 0.0;
-          for (int c = sm.sClo[q]; c <= sm.sChi[q]; ++c) {
-            const float2 gp = sm.sGp[r][c];
-            sx += (double)gp.x;
-            sy += (double)gp.y;
+      // over each of this wave's pixel rows, in registers: dL/dp summed per
+      // alignment tile column (both rows at once when they share a tile row)
+      // and dL/drho summed per R_hat corner column
+      const int r0 = wave * BPX;
+      const int runs = sm.sRun[lane];
+      const int run_t = runs & 127, run_a = (runs >> 8) & 127, run_b = (runs >> 16) & 127;
+      const bool end_t = (runs >> 7) & 1, end_a = (runs >> 15) & 1, end_b = (runs >> 23) & 1;
+      bool joined = false;
+      if (BPX == 2) joined = r0 + 1 >= nrow || sm.sTyRow[r0] == sm.sTyRow[r0 + 1];  // uniform
+#pragma unroll
+      for (int p = 0; p < BPX; ++p) {
+        const int r = r0 + p;
+        if (r >= nrow) continue;  // uniform
+        if (!(joined && p == 1)) {
+          double sx = (double)pgx[p], sy = (double)pgy[p];
+          if (joined && BPX == 2) {
+            sx += (double)pgx[1];
+            sy += (double)pgy[1];
           }
-          sm.sHm[r][q] = make_double2(sx, sy);
-        } else {
-          const int J = q - ntx;
-          float s = 0.f;
-          for (int c = sm.sJlo[J]; c <= sm.sJhi[J]; ++c) {
-            const float wgt = (sm.sRxa[c] == J ? 1.f - sm.sRfx[c] : 0.f) + (sm.sRxb[c] == J ? sm.sRfx[c] : 0.f);
-            s = fmaf(wgt, sm.sGr[r][c], s);
+          sx = run_sum(sx, lane, run_t);
+          sy = run_sum(sy, lane, run_t);
+          if (end_t) {
+            sm.sHm[r][txl] = make_double2(sx, sy);
+            if (joined && BPX == 2 && r + 1 < nrow) sm.sHm[r + 1][txl] = make_double2(0.0, 0.0);
           }
-          sm.sHr[r][J] = s;
         }
+        if (lane < rhw) {
+          sm.sHa[r][lane] = 0.f;
+          sm.sHb[r][lane] = 0.f;
+        }
+        const float ga = run_sum((1.f - rfx) * pgr[p], lane, run_a);
+        const float gb = run_sum(rfx * pgr[p], lane, run_b);
+        if (end_a) sm.sHa[r][rxa] = ga;
+        if (end_b) sm.sHb[r][rxb] = gb;
       }
       __syncthreads();
       const int nwin = rhh * rhw;
@@ -566,7 +599,7 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
           for (int r = sm.sIlo[I]; r <= sm.sIhi[I]; ++r) {
             const float fyr = sm.sRow[r].fy;
             const float wgt = (sm.sRya[r] == I ? 1.f - fyr : 0.f) + (sm.sRyb[r] == I ? fyr : 0.f);
-            s = fmaf(wgt, sm.sHr[r][J], s);
+            s = fmaf(wgt, sm.sHa[r][J] + sm.sHb[r][J], s);
           }
           part_rh[((size_t)n * bc.n_tiles + tile) * kBwdRH + q] = s;
         }
