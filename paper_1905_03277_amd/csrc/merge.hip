@@ -170,6 +170,7 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
 
   // ---- accumulators -----------------------------------------------------
   using Acc = typename std::conditional<SAVE, double, float>::type;
+  using EF = typename std::conditional<SAVE, double, float>::type;  // exponent arithmetic
   Acc num[PX][3], den[PX][3];
   float M[PX][3];
 #pragma unroll
@@ -452,26 +453,39 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
               const double bot = fma(fx, o11 - o10, o10);
               O[e] = fma(fy, bot - top, top);
             }
-            // eq. (2): log2 w = -1/2 log2(e) d^T Omega^-1 d
+            // eq. (2): log2 w = -1/2 log2(e) d^T Omega^-1 d. Omega_bar, its
+            // determinant and inverse in float64 (Omega is ill-conditioned,
+            // k1/k2 up to ~10^3); the inverse's entries, the offsets and the
+            // nine exponents then in EF: float where the normaliser is not
+            // kept (the exponents' terms are products of well-scaled values,
+            // so each exponent carries a float rounding of its largest term,
+            // a relative weight error of ~10^-5 where it matters), float64 in
+            // the forward that keeps its normaliser, whose weights the adjoint
+            // recomputes in float64 and must reproduce.
             const double sc = NEG_HALF_LOG2E * recip64_1(O[0] * O[2] - O[1] * O[1]);
-            const double qa = O[2] * sc, qb2 = -2.0 * O[1] * sc, qc = O[0] * sc;
-            // sample offsets d = q + 1/2 - p; far away where the sample is outside the frame
-            double dx[3], dy[3];
+            const EF qa = (EF)(O[2] * sc), qb2 = (EF)(-2.0 * O[1] * sc), qc = (EF)(O[0] * sc);
+            // sample offsets d = q + 1/2 - p; far away where the sample is
+            // outside the frame (far enough that its weight is 0, near enough
+            // that no product overflows: the row distance dominates)
+            EF dx[3], dy[3];
+            {
+              const EF fx0 = (EF)frx, fy0 = (EF)fry;
   #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-              dx[j] = ((double)j - 0.5) - frx;
-              dy[j] = ((double)j - 0.5) - fry;
+              for (int j = 0; j < 3; ++j) {
+                dx[j] = ((EF)j - (EF)0.5) - fx0;
+                dy[j] = ((EF)j - (EF)0.5) - fy0;
+              }
             }
             if (!(jc >= 1 && jc <= g.W - 2 && ic >= 1 && ic <= g.H - 2)) {
   #pragma unroll
               for (int j = 0; j < 3; ++j) {
                 const int qj = jc + j - 1, qi = ic + j - 1;
-                if (qj < 0 || qj >= g.W) dx[j] = FAR_X;
-                if (qi < 0 || qi >= g.H) dy[j] = FAR_Y;
+                if (qj < 0 || qj >= g.W) dx[j] = SAVE ? (EF)FAR_X : (EF)FAR_X32;
+                if (qi < 0 || qi >= g.H) dy[j] = SAVE ? (EF)FAR_Y : (EF)FAR_Y32;
               }
             }
             // exponent of sample (i, j): ax[j] + cy[i] + by[i] dx[j]
-            double ax[3], cy[3], by[3];
+            EF ax[3], cy[3], by[3];
   #pragma unroll
             for (int j = 0; j < 3; ++j) {
               ax[j] = qa * (dx[j] * dx[j]);
@@ -488,11 +502,11 @@ __device__ __forceinline__ void merge_tile(const uint16_t* __restrict__ frames,
             float d[3][3];
             auto exponents = [&]() {
               const float MX = xIsR ? M[p][0] : M[p][2], MY = xIsR ? M[p][2] : M[p][0], MG = M[p][1];
-              const double g0 = (double)(isG ? MG : MX), g1 = (double)(isG ? MX : MG);
-              const double g2 = (double)(isG ? MY : MG), g3 = (double)(isG ? MG : MY);
+              const EF g0 = (EF)(isG ? MG : MX), g1 = (EF)(isG ? MX : MG);
+              const EF g2 = (EF)(isG ? MY : MG), g3 = (EF)(isG ? MG : MY);
               // the group's reference joins the row term
-              const double r1c = cy[1] - g0, r1s = cy[1] - g1;
-              const double r0m = cy[0] - g2, r0c = cy[0] - g3, r2m = cy[2] - g2, r2c = cy[2] - g3;
+              const EF r1c = cy[1] - g0, r1s = cy[1] - g1;
+              const EF r0m = cy[0] - g2, r0c = cy[0] - g3, r2m = cy[2] - g2, r2c = cy[2] - g3;
               d[1][1] = (float)fma(by[1], dx[1], ax[1] + r1c);
               d[1][0] = (float)fma(by[1], dx[0], ax[0] + r1s);
               d[1][2] = (float)fma(by[1], dx[2], ax[2] + r1s);

@@ -16,6 +16,10 @@ constexpr double NEG_HALF_LOG2E = -0.72134752044448170368;
 // Distances given to out-of-frame sample columns / rows: their quadratic
 // form is then ~1e200 or more (Omega^-1 is bounded below), i.e. weight 0.
 constexpr double FAR_X = 1e100, FAR_Y = 1e120;
+// The same in float exponent arithmetic: the quadratic form's coefficients
+// stay within [1e-5, 1e7] in magnitude for any practical tuning, so the far
+// terms land in [1e11, 1e38] and the cross term stays below 1e31.
+constexpr float FAR_X32 = 1e8f, FAR_Y32 = 1e16f;
 
 template <int MH>
 struct Caps {

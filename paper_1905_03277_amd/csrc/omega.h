@@ -53,6 +53,9 @@ __device__ __forceinline__ double rsqrt64(double x) {
 // last bit).
 __device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? x * rsqrt64(x) : 0.0; }
 
+// sqrt(x) for x >= 0 to ~4e-15 relative (one Newton step).
+__device__ __forceinline__ double sqrt64_1(double x) { return x > 0.0 ? x * rsqrt64_1(x) : 0.0; }
+
 // What the adjoint needs of one pixel's kernel covariance besides Omega.
 struct OmegaParts {
   double c2, s2;         // cos 2phi, sin 2phi of the gradient direction phi
@@ -90,7 +93,7 @@ __device__ __forceinline__ void omega_core(const Q (&l)[3][3], const OmegaConsts
   const double tr = txx + tyy;
   double rad = 0.0, c2 = 1.0, s2 = 0.0, A = 1.0;
   if (r2 > 0.0) {
-    const double y = rsqrt64(r2);  // 1 / rad
+    const double y = rsqrt64_1(r2);  // 1 / rad
     rad = r2 * y;
     c2 = half * y;
     s2 = txy * y;
@@ -99,7 +102,7 @@ __device__ __forceinline__ void omega_core(const Q (&l)[3][3], const OmegaConsts
     A = 1.0 + rsqrt64_1(0.5 * tr * y);
   }
   const double invA = recip64_1(A);
-  const double sqrt_l1 = sqrt64(0.5 * tr + rad);
+  const double sqrt_l1 = sqrt64_1(0.5 * tr + rad);
   const double D_raw = 1.0 - sqrt_l1 * c.inv_16_range_dtr + c.d_th;
   const double D = D_raw < 0.0 ? 0.0 : (D_raw > 1.0 ? 1.0 : D_raw);
   const double k1s = (1.0 - D) * (c.kd_st * A) + D * c.kd_dn;
