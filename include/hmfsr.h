@@ -380,9 +380,11 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs,
 /*
  * hmfsr_batch_plan -- the work layout of the batch graph last captured on the
  * current device (host values, no device work): the (burst, tile) items of
- * the persistent robustness launch and of the persistent merge launch of
- * each tile shape (indices as for hmfsr_autotune), and the workgroups each
- * launch starts. A workgroup pulls items until the list is exhausted, so
+ * the persistent robustness launch and of each persistent merge launch, and
+ * the workgroups each launch starts. Merge launch c (0..7) takes the bursts
+ * of tile shape c / 2 (indices as for hmfsr_autotune) whose raw footprint is
+ * loaded in batches of four (c even) or eight (c odd) samples per thread, as
+ * the burst's own hmfsr_merge launch would. A workgroup pulls items until the list is exhausted, so
  * items / workgroups is how many it takes in turn. By default a launch starts
  * min(items, compute units x resident workgroups per unit) workgroups;
  * HMFSR_BATCH_GROUPS=<k> (k >= 1) caps every launch at k when a graph is
@@ -391,7 +393,7 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs,
  */
 typedef struct {
   int32_t robust_items, robust_groups;
-  int32_t merge_items[4], merge_groups[4];
+  int32_t merge_items[8], merge_groups[8];
 } hmfsr_batch_info;
 hmfsr_status hmfsr_batch_plan(hmfsr_batch_info* out);
 

@@ -68,7 +68,7 @@ class hmfsr_stage_times(ctypes.Structure):
 
 class hmfsr_batch_info(ctypes.Structure):
     _fields_ = [("robust_items", ctypes.c_int32), ("robust_groups", ctypes.c_int32),
-                ("merge_items", ctypes.c_int32 * 4), ("merge_groups", ctypes.c_int32 * 4)]
+                ("merge_items", ctypes.c_int32 * 8), ("merge_groups", ctypes.c_int32 * 8)]
 
 
 class HmfsrError(RuntimeError):

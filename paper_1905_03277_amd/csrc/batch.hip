@@ -4,8 +4,9 @@
 // hmfsr_merge_batch lays out one workspace for every burst (rejection
 // strengths, R_hat), per-burst argument blocks and cost-ordered work lists,
 // then records into a hipGraph: a counter reset, the motion prior of every
-// (burst, frame, tile), one persistent robustness launch over all (burst,
-// tile) items and one persistent merge launch per tile shape. The graph is
+// (burst, frame, tile), the guide statistics, one persistent robustness
+// launch over all (burst, tile) items and one persistent merge launch per
+// class (tile shape, raw-load batch size), each with an XCD-chunked queue. The graph is
 // kept and replayed while the bursts' shapes and buffers stay the same;
 // changed tuning values are uploaded before the replay.
 #include <stdio.h>
@@ -15,6 +16,7 @@
 #include <algorithm>
 #include <numeric>
 
+#include "device_util.h"
 #include "host.h"
 
 namespace hmfsr {
@@ -72,7 +74,8 @@ void tune_save() {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t counters = 0, args = 0, first = 0, bfirst = 0, ffirst = 0, ritems = 0, mitems = 0, work = 0, total = 0;
+  size_t counters = 0, bounds = 0, args = 0, first = 0, bfirst = 0, ffirst = 0, ritems = 0, mitems = 0, work = 0,
+         total = 0;
   std::vector<size_t> burst_work;  // offset of each burst's Work inside the workspace
 };
 
@@ -83,6 +86,26 @@ int batch_groups_cap() {
   if (!env) return 0;
   const int k = atoi(env);
   return k > 0 ? k : 0;
+}
+
+// Persistent launches of a batch: the robustness launch (0), then one merge
+// launch per class (1 + class). Each has an XCD-chunked item queue.
+constexpr int kQueues = 1 + kNumMergeClasses;
+
+// Bounds of XCDS contiguous chunks of items [0, n) of about equal cost
+// (cost(i) per item), into out[0 .. XCDS].
+template <typename C>
+void xcd_chunks(int n, C cost, int* out) {
+  double total = 0.0;
+  for (int i = 0; i < n; ++i) total += cost(i);
+  double acc = 0.0;
+  int x = 1;
+  out[0] = 0;
+  for (int i = 0; i < n && x < XCDS; ++i) {
+    acc += cost(i);
+    while (x < XCDS && acc >= total * x / XCDS) out[x++] = i + 1;
+  }
+  while (x <= XCDS) out[x++] = n;
 }
 
 int capped(size_t items, size_t resident, int cap) {
@@ -204,7 +227,8 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
   if (n_prior > 0x7fffffff || n_base > 0x7fffffff || n_fmeans > 0x7fffffff || n_ritems > 0x7fffffff || n_mitems > 0x7fffffff)
     return HMFSR_E_INVALID;
   size_t off = 0;
-  L.counters = off; off += 256;
+  L.counters = off; off += align256(sizeof(int) * kQueues * XCDS);
+  L.bounds = off; off += align256(sizeof(int) * kQueues * (XCDS + 1));
   L.args = off; off += align256(sizeof(BurstArgs) * n_bursts);
   L.first = off; off += align256(sizeof(int) * n_bursts);
   L.bfirst = off; off += align256(sizeof(int) * n_bursts);
@@ -291,17 +315,25 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
   ritems.reserve(n_ritems);
   for (int i : order)
     for (int t = 0; t < rtiles[i]; ++t) ritems.push_back({i, t});
-  // one merge list per tile shape, stored back to back
+  // one merge list per class (tile shape, load batch), stored back to back
+  std::vector<int> mcls(n_bursts);
+  for (int i = 0; i < n_bursts; ++i) mcls[i] = merge_class(var[i], geo[i].scale);
   std::vector<WorkItem> mitems;
   mitems.reserve(n_mitems);
-  std::vector<int> group_start(kNumMergeVariants + 1, 0);
-  for (int v = 0; v < kNumMergeVariants; ++v) {
-    group_start[v] = (int)mitems.size();
+  std::vector<int> group_start(kNumMergeClasses + 1, 0);
+  for (int c = 0; c < kNumMergeClasses; ++c) {
+    group_start[c] = (int)mitems.size();
     for (int i : order)
-      if (var[i] == v)
+      if (mcls[i] == c)
         for (int t = 0; t < mtiles[i]; ++t) mitems.push_back({i, t});
   }
-  group_start[kNumMergeVariants] = (int)mitems.size();
+  group_start[kNumMergeClasses] = (int)mitems.size();
+  // XCD chunks of every persistent launch, balanced by frames per item
+  std::vector<int> bounds(kQueues * (XCDS + 1), 0);
+  xcd_chunks((int)n_ritems, [&](int i) { return (double)(geo[ritems[i].burst].n - 1); }, &bounds[0]);
+  for (int c = 0; c < kNumMergeClasses; ++c)
+    xcd_chunks(group_start[c + 1] - group_start[c],
+               [&](int i) { return (double)geo[mitems[group_start[c] + i].burst].n; }, &bounds[(1 + c) * (XCDS + 1)]);
   std::vector<int> first(n_bursts), bfirst(n_bursts), ffirst(n_bursts);
   {
     size_t acc = 0, bacc = 0, facc = 0;
@@ -328,7 +360,8 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
       (n_ritems && hipMemcpy(base + L.ritems, ritems.data(), sizeof(WorkItem) * n_ritems,
                              hipMemcpyHostToDevice) != hipSuccess) ||
       hipMemcpy(base + L.mitems, mitems.data(), sizeof(WorkItem) * n_mitems, hipMemcpyHostToDevice) !=
-          hipSuccess)
+          hipSuccess ||
+      hipMemcpy(base + L.bounds, bounds.data(), sizeof(int) * bounds.size(), hipMemcpyHostToDevice) != hipSuccess)
     return HMFSR_E_HIP;
   if (!ds.capture_stream && hipStreamCreateWithFlags(&ds.capture_stream, hipStreamNonBlocking) != hipSuccess)
     return HMFSR_E_HIP;
@@ -339,29 +372,31 @@ hmfsr_status hmfsr_merge_batch(int32_t n_bursts, const hmfsr_desc* descs, const 
   const int* d_ffirst = (const int*)(base + L.ffirst);
   const WorkItem* d_ritems = (const WorkItem*)(base + L.ritems);
   const WorkItem* d_mitems = (const WorkItem*)(base + L.mitems);
-  int* d_counters = (int*)(base + L.counters);  // [0] robustness, [1 + v] merge shape v
+  int* d_counters = (int*)(base + L.counters);  // [queue][XCDS]: robustness, then merge class c
+  const int* d_bounds = (const int*)(base + L.bounds);  // [queue][XCDS + 1]
   const int cus = ds.cus > 0 ? ds.cus : 256;
   hipStream_t cs = ds.capture_stream;
   hipGraph_t graph = nullptr;
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return HMFSR_E_HIP;
-  hipError_t err = launch_fill_i32(d_counters, 0, 1 + kNumMergeVariants, cs);
+  hipError_t err = launch_fill_i32(d_counters, 0, kQueues * XCDS, cs);
   if (err == hipSuccess) err = launch_prior_batch(d_args, d_first, n_bursts, (int)n_prior, cs);
   if (err == hipSuccess)
     err = launch_guide_stats_batch(d_args, d_bfirst, (int)n_base, d_ffirst, (int)n_fmeans, n_bursts, cs);
   hmfsr_batch_info info = {};
   if (err == hipSuccess && n_ritems) {
     const int groups = capped(n_ritems, (size_t)cus * robust_batch_blocks_per_cu(), cap);
-    err = launch_robust_batch(d_args, d_ritems, (int)n_ritems, d_counters, groups, cs);
+    err = launch_robust_batch(d_args, d_ritems, d_bounds, d_counters, groups, cs);
     info.robust_items = (int32_t)n_ritems;
     info.robust_groups = groups;
   }
-  for (int v = 0; v < kNumMergeVariants && err == hipSuccess; ++v) {
-    const int cnt = group_start[v + 1] - group_start[v];
+  for (int c = 0; c < kNumMergeClasses && err == hipSuccess; ++c) {
+    const int cnt = group_start[c + 1] - group_start[c];
     if (cnt == 0) continue;
-    const int groups = capped(cnt, (size_t)cus * merge_batch_blocks_per_cu(v), cap);
-    err = launch_merge_batch(v, d_args, d_mitems + group_start[v], cnt, d_counters + 1 + v, groups, cs);
-    info.merge_items[v] = cnt;
-    info.merge_groups[v] = groups;
+    const int groups = capped(cnt, (size_t)cus * merge_batch_blocks_per_cu(c), cap);
+    err = launch_merge_batch(c, d_args, d_mitems + group_start[c], d_bounds + (1 + c) * (XCDS + 1),
+                             d_counters + (1 + c) * XCDS, groups, cs);
+    info.merge_items[c] = cnt;
+    info.merge_groups[c] = groups;
   }
   const hipError_t end = hipStreamEndCapture(cs, &graph);
   if (err != hipSuccess || end != hipSuccess || !graph) {

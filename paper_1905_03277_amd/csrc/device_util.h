@@ -35,4 +35,34 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return x * q + min(x, r) + l;
 }
 
+// Persistent work distribution over the XCDs. A launch's items [0, n) are
+// split into XCDS contiguous chunks of about equal cost (chunk x = [bounds[x],
+// bounds[x + 1])), each with its own counter (zero at launch). A workgroup on
+// XCD x (dispatch is round-robin) takes the items of chunk x in turn, then
+// what is left of the other chunks, x + 1 first, so that neighbouring items
+// (tiles of one burst) meet in one L2 and no XCD idles while another has work.
+// `slot` is a workgroup-shared int; `body(item)` runs on the whole workgroup.
+struct ItemQueue {
+  const int* bounds;  // [XCDS + 1]
+  int* counters;      // [XCDS]
+};
+
+template <typename F>
+__device__ __forceinline__ void for_each_item(const ItemQueue& q, int* slot, F&& body) {
+  const int home = blockIdx.x % XCDS;
+  for (int k = 0; k < XCDS; ++k) {
+    const int c = (home + k) % XCDS;
+    const int lo = q.bounds[c], hi = q.bounds[c + 1];
+    if (lo >= hi) continue;  // uniform
+    while (true) {
+      __syncthreads();
+      if (threadIdx.x == 0) *slot = lo + atomicAdd(&q.counters[c], 1);
+      __syncthreads();
+      const int it = __builtin_amdgcn_readfirstlane(*slot);  // uniform: scalar loads follow
+      if (it >= hi) break;
+      body(it);
+    }
+  }
+}
+
 }  // namespace hmfsr

@@ -107,10 +107,16 @@ extern const int kNumMergeVariants;
 hipError_t launch_merge(int variant, const Geometry& g, const MergeConsts& mc, const uint16_t* frames,
                         const float* motion, const float* rmin, float* out, float* saved,
                         hipStream_t stream);
-hipError_t launch_merge_batch(int variant, const BurstArgs* bursts, const WorkItem* items, int n_items,
-                              int* counter, int n_groups, hipStream_t stream);
-hipError_t launch_robust_batch(const BurstArgs* bursts, const WorkItem* items, int n_items,
-                               int* counter, int n_groups, hipStream_t stream);
+// Class of a burst in the batched merge: 2 x tile shape + 1 where the
+// raw-footprint loads go in batches of eight (the burst's own launch's choice).
+constexpr int kNumMergeClasses = 8;
+int merge_class(int variant, double scale);
+// `bounds` [XCDS + 1] and `counters` [XCDS] of the launch's item queue (see
+// for_each_item).
+hipError_t launch_merge_batch(int cls, const BurstArgs* bursts, const WorkItem* items, const int* bounds,
+                              int* counters, int n_groups, hipStream_t stream);
+hipError_t launch_robust_batch(const BurstArgs* bursts, const WorkItem* items, const int* bounds,
+                               int* counters, int n_groups, hipStream_t stream);
 // Guide statistics of every burst of a batch, the base frames' and the aligned
 // frames' in two flat launches: workgroup i belongs to the last burst b with
 // first[b] <= i (first[b] = the workgroups of the bursts before b).
@@ -129,7 +135,7 @@ hipError_t launch_merge_stream(const Geometry& g, const MergeConsts& mc, const u
                                int first, hipStream_t stream);
 hipError_t launch_stream_finish(const Geometry& g, const MergeConsts& mc, const float* state, float* out,
                                 hipStream_t stream);
-int merge_batch_blocks_per_cu(int variant);
+int merge_batch_blocks_per_cu(int cls);
 int robust_batch_blocks_per_cu();
 int robust_tiles_x(const Geometry& g);
 int robust_tiles_y(const Geometry& g);

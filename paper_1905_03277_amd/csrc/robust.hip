@@ -179,10 +179,12 @@ __global__ __launch_bounds__(THREADS) void k_frame_means(const uint16_t* __restr
   frame_means_block(frames, g, gmu, n, t % ns, (t / ns) * FM_WAVES + (threadIdx.x >> 6));
 }
 
-// Every (burst, aligned frame, strip, band) of a batch, one workgroup each.
+// Every (burst, aligned frame, strip, band) of a batch, one workgroup each;
+// each XCD takes a contiguous run of the flat list (neighbours share an L2).
 __global__ __launch_bounds__(THREADS) void k_frame_means_batch(const BurstArgs* __restrict__ bursts,
-                                                               const int* __restrict__ first, int n_bursts) {
-  const int i = blockIdx.x, bi = burst_of(first, n_bursts, i);
+                                                               const int* __restrict__ first, int n_bursts,
+                                                               int total) {
+  const int i = xcd_tile(blockIdx.x, total), bi = burst_of(first, n_bursts, i);
   const BurstArgs& b = bursts[bi];
   const int ns = fm_strips(b.g), per = ns * fm_bands(b.g);
   const int k = i - first[bi], m = k / per, t = k - m * per;
@@ -322,11 +324,12 @@ __global__ __launch_bounds__(THREADS) void k_base_stats(const uint16_t* __restri
   base_stats_tile(frames, g, rc, gmu, gref, t % tx_n, t / tx_n, sm);
 }
 
-// Every (burst, tile) of a batch, one workgroup each.
+// Every (burst, tile) of a batch, one workgroup each, in XCD-contiguous runs.
 __global__ __launch_bounds__(THREADS) void k_base_stats_batch(const BurstArgs* __restrict__ bursts,
-                                                              const int* __restrict__ first, int n_bursts) {
+                                                              const int* __restrict__ first, int n_bursts,
+                                                              int total) {
   __shared__ BaseSmem sm;
-  const int i = blockIdx.x, bi = burst_of(first, n_bursts, i);
+  const int i = xcd_tile(blockIdx.x, total), bi = burst_of(first, n_bursts, i);
   const BurstArgs& b = bursts[bi];
   const int tx_n = means_tiles_x(b.g), t = i - first[bi];
   base_stats_tile(b.frames, b.g, b.rc, b.gmu, b.gref, t % tx_n, t / tx_n, sm);
@@ -594,22 +597,16 @@ __global__ __launch_bounds__(THREADS, 6) void k_robust(const float* __restrict__
               min(m_per, g.n - 1 - m_first), sm);
 }
 
-// Persistent form over (burst, tile) items of a batch.
-__global__ __launch_bounds__(THREADS) void k_robust_batch(const BurstArgs* __restrict__ bursts,
-                                                          const WorkItem* __restrict__ items,
-                                                          int n_items, int* __restrict__ counter) {
+// Persistent form over (burst, tile) items of a batch (XCD-chunked queue).
+__global__ __launch_bounds__(THREADS, 6) void k_robust_batch(const BurstArgs* __restrict__ bursts,
+                                                          const WorkItem* __restrict__ items, ItemQueue q) {
   __shared__ RobustSmem sm;
-  while (true) {
-    __syncthreads();
-    if (threadIdx.x == 0) sm.sItem = atomicAdd(counter, 1);
-    __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(sm.sItem);  // uniform: scalar loads below
-    if (it >= n_items) break;
+  for_each_item(q, &sm.sItem, [&](int it) {
     const WorkItem w = items[it];
     const BurstArgs& b = bursts[w.burst];
     robust_tile(b.motion, b.s_tile, b.mov, b.g, b.rc, b.gmu, b.gref, b.rmin, nullptr,
                 w.tile % b.robust_tiles_x, w.tile / b.robust_tiles_x, 0, b.g.n - 1, sm);
-  }
+  });
 }
 
 }  // namespace
@@ -648,13 +645,13 @@ hipError_t launch_guide_stats_batch(const BurstArgs* bursts, const int* base_fir
                                     const int* frame_first, int frame_total, int n_bursts, hipStream_t stream) {
   if (base_total > 0) {
     hipLaunchKernelGGL(k_base_stats_batch, dim3(base_total), dim3(THREADS), 0, stream, bursts, base_first,
-                       n_bursts);
+                       n_bursts, base_total);
     const hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
   if (frame_total > 0)
     hipLaunchKernelGGL(k_frame_means_batch, dim3(frame_total), dim3(THREADS), 0, stream, bursts, frame_first,
-                       n_bursts);
+                       n_bursts, frame_total);
   return hipGetLastError();
 }
 
@@ -664,11 +661,10 @@ int robust_batch_blocks_per_cu() {
   return b > 0 ? b : 1;
 }
 
-hipError_t launch_robust_batch(const BurstArgs* bursts, const WorkItem* items, int n_items,
-                               int* counter, int n_groups, hipStream_t stream) {
-  if (n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_robust_batch, dim3(n_groups), dim3(THREADS), 0, stream, bursts, items, n_items,
-                     counter);
+hipError_t launch_robust_batch(const BurstArgs* bursts, const WorkItem* items, const int* bounds,
+                               int* counters, int n_groups, hipStream_t stream) {
+  hipLaunchKernelGGL(k_robust_batch, dim3(n_groups), dim3(THREADS), 0, stream, bursts, items,
+                     ItemQueue{bounds, counters});
   return hipGetLastError();
 }
 
