@@ -347,6 +347,57 @@ def bench_stream(burst, out, reps: int = 5) -> dict:
             "state_bytes": 9 * 4 * d.out_height * d.out_width}
 
 
+def align_error_split(burst, motion, frames=(1, 2, 3)) -> dict:
+    """Ground-truth error of aligned vectors, split by the base frame's
+    structure per tile: the smaller eigenvalue of the Lucas-Kanade normal
+    matrix per window pixel, in units of half the noise variance of a
+    half-resolution pixel at mid-grey ("flat" < 1, "weak" 1-10, "textured"
+    >= 10). Frames 1-3 only (the occluder enters from frame 4)."""
+    import numpy as np
+    import torch
+    d = burst.desc
+    f = burst.frames[d.ref_frame].to(torch.float64)
+    q = f[0::2, 0::2] + f[0::2, 1::2] + f[1::2, 0::2] + f[1::2, 1::2]
+    h, w = q.shape
+    xi = torch.arange(w, device=q.device)
+    yi = torch.arange(h, device=q.device)
+    gx = (q[:, (xi + 1).clamp(max=w - 1)] - q[:, (xi - 1).clamp(min=0)]) / 2.0
+    gy = (q[(yi + 1).clamp(max=h - 1), :] - q[(yi - 1).clamp(min=0), :]) / 2.0
+
+    def integral(a):
+        z = torch.zeros((h + 1, w + 1), dtype=a.dtype, device=a.device)
+        z[1:, 1:] = a.cumsum(0).cumsum(1)
+        return z
+
+    B = d.tile_size // 2
+    ty = torch.arange(d.tiles_y, device=q.device)
+    tx = torch.arange(d.tiles_x, device=q.device)
+    y0 = (ty * B - B // 2).clamp(min=0).view(-1, 1)
+    y1 = (ty * B + B + B // 2).clamp(max=h).view(-1, 1)
+    x0 = (tx * B - B // 2).clamp(min=0).view(1, -1)
+    x1 = (tx * B + B + B // 2).clamp(max=w).view(1, -1)
+
+    def box(a):
+        z = integral(a)
+        return z[y1, x1] - z[y0, x1] - z[y1, x0] + z[y0, x0]
+
+    hxx, hxy, hyy = box(gx * gx), box(gx * gy), box(gy * gy)
+    npx = ((y1 - y0) * (x1 - x0)).to(torch.float64)
+    lmin = ((hxx + hyy) - torch.sqrt((hxx - hyy) ** 2 + 4 * hxy ** 2)) / 2.0 / npx
+    var = 4.0 * (d.noise_a * 0.5 + d.noise_b) * (d.white_level - d.black_level) ** 2
+    rel = (lmin / (var / 2.0)).cpu().numpy()
+    m = motion.cpu().numpy()
+    gt = burst.motion.cpu().numpy()
+    res = {}
+    for name, lo, hi in (("flat", 0.0, 1.0), ("weak", 1.0, 10.0), ("textured", 10.0, float("inf"))):
+        sel = (rel >= lo) & (rel < hi)
+        e = np.concatenate([np.hypot(*(m[k] - gt[k])[sel].reshape(-1, 2).T) for k in frames]) if sel.any() else None
+        res[name] = {"tiles": round(float(sel.mean()), 3),
+                     "median_px": None if e is None else round(float(np.median(e)), 3),
+                     "p90_px": None if e is None else round(float(np.percentile(e, 90)), 3)}
+    return res
+
+
 def bench_align(burst, out, reps: int = 10) -> dict:
     """Tile alignment (Sec. 3.2) of the same 12 MP x 8 burst: pyramid, block
     matching on every level, Lucas-Kanade; and raw burst to RGB (alignment then
@@ -384,8 +435,12 @@ def bench_align(burst, out, reps: int = 10) -> dict:
     in_mp = d.n_frames * d.height * d.width / 1e6
     tiles = d.tiles_y * d.tiles_x
     alg_bytes = 2 * d.n_frames * d.height * d.width + 8 * d.n_frames * tiles
+    al()
+    gated = align_error_split(burst, motion)
+    ungated = align_error_split(burst, torch_ops.align(burst.frames, d, {"gate": 0.0}))
     return {"workload": "alignment of the 12 MP x 8 burst (4 levels, radii 4/2, 3 Lucas-Kanade "
-                        "iterations, 16 px tiles)",
+                        "iterations, noise gate 4, 16 px tiles)",
+            "gt_error": {"noise_gate_4": gated, "no_gate": ungated},
             "ms": round(res["align"], 3), "MPs": round(in_mp / (res["align"] / 1e3), 1),
             "stage_ms": round(tot / max(cnt, 1), 3),
             "hbm_algorithmic_bytes": alg_bytes,

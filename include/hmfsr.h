@@ -264,17 +264,23 @@ hmfsr_status hmfsr_stream_end(const hmfsr_desc* desc, const hmfsr_tuning* tuning
  *  radius_coarse  search radius (pixels) on the coarsest level, 1..8 (default 4)
  *  radius_fine    search radius on every finer level, 1..8 (default 2)
  *  lk_iterations  Lucas-Kanade iterations, 0..16 (default 3)
+ *  gate           noise gate kappa, 0..1000 (default 4; 0 turns it off): a
+ *                 block keeps its guess unless its best candidate lowers the
+ *                 cost by more than kappa standard deviations of the cost
+ *                 differences that noise alone produces (below)
  */
 typedef struct {
   int32_t levels, radius_coarse, radius_fine, lk_iterations;
+  float gate;
 } hmfsr_align_params;
 
 /*
  * hmfsr_align -- per-tile alignment vectors of every frame against the base
  * frame (Sec. 3.2), in the layout hmfsr_merge reads, so that a raw burst goes
  * to RGB through hmfsr_align then hmfsr_merge.
- *  desc     as for hmfsr_merge; only n_frames, height, width, ref_frame and
- *           tile_size are used, and tile_size must be <= 64 (S.2's largest).
+ *  desc     as for hmfsr_merge; only n_frames, height, width, ref_frame,
+ *           tile_size (<= 64, S.2's largest) and, for the noise gate,
+ *           black_level, white_level, noise_a and noise_b are used.
  *  params   NULL for the defaults.
  *  frames   DEVICE uint16 [n_frames][height][width], 4-byte aligned.
  *  motion   DEVICE float32 [n_frames][TY][TX][2], 8-byte aligned (output):
@@ -291,7 +297,15 @@ typedef struct {
  * squared differences (edge-replicated frame) over guess + [-R, R]^2, ties to
  * the smallest offset from the guess and then to the first in row-major
  * order; the guess is twice the vector of the coarser block holding the
- * block's centre (0 on the coarsest level). Each tile's vector is then
+ * block's centre (0 on the coarsest level). Noise gate: with the noise model
+ * of Sec. 5.2.2 a level-l pixel (a sum of m = 4^(l+1) raw values) has
+ * variance v = m (a x + b) R^2 (R = white - black, x the block's mean
+ * brightness in [0, 1]), and noise alone spreads the cost difference of two
+ * candidates over N pixels by sqrt(12 N) v; the winner replaces the guess only
+ * when N gain^2 > 12 kappa^2 (N v)^2, decided in float64 with the operations
+ * rounded in a fixed order (S the block's integer sum, nm = N m,
+ * e = clamp(S - nm black, 0, nm R), u = (a R) e + ((nm b) R) R, then
+ * (N gain) gain > (((12 kappa) kappa) u) u). Each tile's vector is then
  * refined by translation-only Lucas-Kanade on level 0 over the tile grown by
  * half a tile on every side: central-difference gradients of the base frame,
  * bilinear error image, v -= H^-1 b; tiles whose normal matrix H has

@@ -27,6 +27,22 @@ Readings:
     the smallest dx^2 + dy^2, then to the first in row-major scan order;
   * the guess for a block is twice the vector of the coarser level's block that
     holds the block's centre (zero on the coarsest level);
+  * noise gate (kappa = ``gate`` >= 0, default 4; 0 turns it off): a block
+    keeps its guess unless the winner lowers the cost by more than kappa
+    standard deviations of what noise alone moves a cost difference by. With
+    the noise model of Sec. 5.2.2 every raw value x (normalised to [0, 1] by
+    black and white level) has variance (a x + b) R^2 in raw units, R = white -
+    black; a level-l pixel sums m = 4^(l+1) raw values, so its variance is
+    v = m (a x + b) R^2, x taken at the block's mean (clamped to [0, 1]). For
+    two candidates over N pixels of noise only, the cost difference
+    sum (n1 - n0)^2 - (n2 - n0)^2 has variance 12 N v^2. The test is taken
+    without divisions or roots, in float64 with every operation rounded in
+    the order written: with S the block's integer sum, e = clamp(S - N m black,
+    0, N m R) and u = a R e + N m b R R (= N v), the block moves iff
+    N gain^2 > 12 kappa^2 u^2, gain = SSD(guess) - SSD(winner). It stops noise
+    from steering flat blocks and blocks along straight edges (the aperture
+    problem) off their guess; content that moves (or aliases) gains far more
+    than that and is matched as before;
   * Lucas-Kanade on level 0 (translation only, template gradients): with
     g(p) the central-difference gradient of the base image (edge-replicated)
     and e(p) = I_n(p + v) - I_0(p) (I_n sampled bilinearly, edge-clamped as in
@@ -42,7 +58,7 @@ from __future__ import annotations
 
 import numpy as np
 
-DEFAULTS = dict(levels=4, radius_coarse=4, radius_fine=2, lk_iterations=3, coarse_block=8)
+DEFAULTS = dict(levels=4, radius_coarse=4, radius_fine=2, lk_iterations=3, coarse_block=8, gate=4.0)
 
 
 def quad_sums(frame):
@@ -68,10 +84,29 @@ def block_grid(shape, block):
     return -(-shape[0] // block), -(-shape[1] // block)
 
 
-def match_block(base, img, block, by, bx, guess, radius):
+def noise_gate_moves(tpl, level, gain, gate, noise):
+    """The noise gate's decision for a block ``tpl`` of pyramid level ``level``
+    whose best candidate lowers the cost by the integer ``gain``: True when
+    the move is significant. noise = (a, b, black, white) of the descriptor
+    (float32 values); every float64 operation below is rounded in the order
+    written, as the device code does it."""
+    a, b, black, white = (float(np.float32(x)) for x in noise)
+    kappa = float(np.float32(gate))
+    rng = white - black
+    n = float(tpl.size)
+    nm = n * (4.0 ** (level + 1))
+    e = float(int(np.sum(tpl, dtype=np.int64))) - nm * black
+    e = min(max(e, 0.0), nm * rng)
+    u = (a * rng) * e + ((nm * b) * rng) * rng
+    g = float(gain)
+    return (n * g) * g > (((12.0 * kappa) * kappa) * u) * u
+
+
+def match_block(base, img, block, by, bx, guess, radius, gate=0.0, noise=None, level=0):
     """Integer offset (ux, uy) of block (by, bx) of ``base`` found in ``img``:
     minimum SSD over guess + [-R, R]^2, ties to the smallest dx^2 + dy^2,
-    then to the first candidate in row-major order."""
+    then to the first candidate in row-major order; with gate > 0 the guess
+    is kept unless ``noise_gate_moves`` finds the winner's gain significant."""
     h, w = base.shape
     ys = np.arange(by * block, min(by * block + block, h))
     xs = np.arange(bx * block, min(bx * block + block, w))
@@ -86,20 +121,24 @@ def match_block(base, img, block, by, bx, guess, radius):
             xx = np.clip(xs + ux, 0, w - 1)
             diff = img[np.ix_(yy, xx)] - tpl
             key = (int(np.sum(diff * diff)), dx * dx + dy * dy, k)
+            if dx == 0 and dy == 0:
+                ssd_guess = key[0]
             if best is None or key < best[0]:
                 best = (key, ux, uy)
             k += 1
+    if gate > 0 and not noise_gate_moves(tpl, level, ssd_guess - best[0][0], gate, noise):
+        return gx, gy
     return best[1], best[2]
 
 
-def match_level(base, img, block, guess, radius):
+def match_level(base, img, block, guess, radius, gate=0.0, noise=None, level=0):
     """Block matching of one level. guess: [BY][BX][2] integer (dx, dy).
     Returns the chosen integer offsets [BY][BX][2]."""
     by_n, bx_n = block_grid(base.shape, block)
     out = np.zeros((by_n, bx_n, 2), dtype=np.int64)
     for by in range(by_n):
         for bx in range(bx_n):
-            out[by, bx] = match_block(base, img, block, by, bx, guess[by, bx], radius)
+            out[by, bx] = match_block(base, img, block, by, bx, guess[by, bx], radius, gate, noise, level)
     return out
 
 
@@ -196,6 +235,7 @@ def align(frames, desc, params=None, debug=False):
     n = frames.shape[0]
     ref = int(desc.ref_frame if not isinstance(desc, dict) else desc["ref_frame"])
     tile = int(desc.tile_size if not isinstance(desc, dict) else desc["tile_size"])
+    noise = desc_noise(desc)
     b0 = tile // 2
     grays = [quad_sums(frames[k]) for k in range(n)]
     pyr_ref, blocks = _levels_and_blocks(grays[ref], tile, p)
@@ -217,7 +257,7 @@ def align(frames, desc, params=None, debug=False):
             else:
                 guess = upsample_guess(vec, blocks[lv + 1], shape, blocks[lv])
                 radius = p["radius_fine"]
-            vec = match_level(pyr_ref[lv], pyr[lv], blocks[lv], guess, radius)
+            vec = match_level(pyr_ref[lv], pyr[lv], blocks[lv], guess, radius, p["gate"], noise, lv)
             per_level.append(vec)
         v = lucas_kanade(pyr_ref[0], pyr[0], b0, vec, p["lk_iterations"])
         motion[k] = 2.0 * v
@@ -225,6 +265,15 @@ def align(frames, desc, params=None, debug=False):
     if debug:
         return motion, steps
     return motion
+
+
+def desc_noise(desc):
+    """(noise_a, noise_b, black_level, white_level) of a descriptor or of a
+    dict (missing keys: 1e-3, 1e-6, 64, 4095, the 12-bit defaults)."""
+    names = (("noise_a", 1e-3), ("noise_b", 1e-6), ("black_level", 64.0), ("white_level", 4095.0))
+    if isinstance(desc, dict):
+        return tuple(float(desc.get(k, v)) for k, v in names)
+    return tuple(float(getattr(desc, k)) for k, _ in names)
 
 
 def _levels_and_blocks(grays_ref, tile, p):
@@ -243,6 +292,7 @@ def align_sampled(frames, desc, frame, tiles, params=None):
     frames = np.asarray(frames)
     ref = int(desc.ref_frame if not isinstance(desc, dict) else desc["ref_frame"])
     tile = int(desc.tile_size if not isinstance(desc, dict) else desc["tile_size"])
+    noise = desc_noise(desc)
     tiles = [(int(a), int(b)) for a, b in tiles]
     if frame == ref:
         return np.zeros((len(tiles), 2)), np.zeros((len(tiles), 2), dtype=np.int64)
@@ -264,7 +314,7 @@ def align_sampled(frames, desc, frame, tiles, params=None):
                 g = vec(lv + 1, cy, cx)
                 guess = (2 * g[0], 2 * g[1])
                 radius = p["radius_fine"]
-            memo[key] = match_block(pyr_ref[lv], pyr[lv], blocks[lv], by, bx, guess, radius)
+            memo[key] = match_block(pyr_ref[lv], pyr[lv], blocks[lv], by, bx, guess, radius, p["gate"], noise, lv)
         return memo[key]
 
     base_f = pyr_ref[0].astype(np.float64)

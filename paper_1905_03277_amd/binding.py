@@ -56,10 +56,11 @@ class hmfsr_tuning(ctypes.Structure):
 
 class hmfsr_align_params(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("radius_coarse", ctypes.c_int32),
-                ("radius_fine", ctypes.c_int32), ("lk_iterations", ctypes.c_int32)]
+                ("radius_fine", ctypes.c_int32), ("lk_iterations", ctypes.c_int32),
+                ("gate", ctypes.c_float)]
 
 
-ALIGN_DEFAULTS = dict(levels=4, radius_coarse=4, radius_fine=2, lk_iterations=3)
+ALIGN_DEFAULTS = dict(levels=4, radius_coarse=4, radius_fine=2, lk_iterations=3, gate=4.0)
 
 
 class hmfsr_stage_times(ctypes.Structure):
@@ -210,7 +211,7 @@ def make_align_params(params=None) -> hmfsr_align_params:
     """hmfsr_align_params from a dict (missing keys take the defaults)."""
     p = dict(ALIGN_DEFAULTS)
     p.update(params or {})
-    return hmfsr_align_params(*(int(p[f]) for f, _ in hmfsr_align_params._fields_))
+    return hmfsr_align_params(*((float if t is ctypes.c_float else int)(p[f]) for f, t in hmfsr_align_params._fields_))
 
 
 def hmfsr_align(desc, params, frames: int, motion: int, block_match: int = 0, stream: int = 0) -> None:

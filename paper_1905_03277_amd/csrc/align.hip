@@ -4,7 +4,10 @@
 // finest level's vectors.
 //
 // Every integer step (pyramid, costs, the argmin and its tie rules) is exact,
-// so the block-matching vectors are fully determined by the frames. The
+// and the noise gate that keeps a block at its guess when the winner's gain
+// is within the noise (the noise model of Sec. 5.2.2) compares float64 values
+// rounded in a fixed order, so the block-matching vectors are fully
+// determined by the frames and the descriptor. The
 // Lucas-Kanade normal matrix is an exact integer sum as well; its solve and
 // the error image run in float64.
 #include <stdint.h>
@@ -79,7 +82,24 @@ struct MatchLevel {
   int parent;               // 1 when the coarser level supplies the guess
   int pB, pgby, pgbx;       // the coarser level's block edge and grid
   long long pvoff;
+  int level;                // pyramid level (a pixel sums 4^(level+1) raw values)
+  double k12, na, nb, black, rng;  // noise gate: (12 kappa) kappa (0: off) and the noise model
 };
+
+// Noise gate of block matching: does a winner that lowers the cost by `gain`
+// below the guess's cost move the block? N pixels with integer sum S on a
+// level whose pixels sum m raw values. The operations are rounded one by one
+// in this order (no contraction), so that every caller takes the same
+// decision for the same integers.
+__device__ __forceinline__ bool gate_moves(const MatchLevel& ml, int npx, long long S, unsigned long long gain) {
+  const double n = (double)npx;
+  const double nm = __dmul_rn(n, (double)(1ll << (2 * ml.level + 2)));
+  double e = __dsub_rn((double)S, __dmul_rn(nm, ml.black));
+  e = fmin(fmax(e, 0.0), __dmul_rn(nm, ml.rng));
+  const double u = __dadd_rn(__dmul_rn(__dmul_rn(ml.na, ml.rng), e), __dmul_rn(__dmul_rn(__dmul_rn(nm, ml.nb), ml.rng), ml.rng));
+  const double g = (double)gain;
+  return __dmul_rn(__dmul_rn(n, g), g) > __dmul_rn(__dmul_rn(ml.k12, u), u);
+}
 
 // Persistent launches: kWaves independent waves per workgroup. Wave w of
 // workgroup b (XCD-aware order) takes the contiguous item range
@@ -234,6 +254,8 @@ __global__ __launch_bounds__(256) void k_align_match(const int32_t* __restrict__
                           by * B + gy - R, bx * B + gx - R, ml.h, ml.w, l);
     wave_sync();
     PKey best{~0ull, 0x7fffffff};
+    const int kc = R * D + R;  // the candidate at the guess
+    unsigned long long ssd_c = 0;
     if (valid) {
       for (int k = l; k < K; k += LPG) {
         const int dyi = k / D, dxi = k - (k / D) * D;
@@ -274,6 +296,7 @@ __global__ __launch_bounds__(256) void k_align_match(const int32_t* __restrict__
           }
         }
         const int dx = dxi - R, dy = dyi - R;
+        if (k == kc) ssd_c = ssd;
         key_min(best, PKey{ssd, ((dx * dx + dy * dy) << 16) | k});
       }
     }
@@ -281,8 +304,21 @@ __global__ __launch_bounds__(256) void k_align_match(const int32_t* __restrict__
     key_min(best, dpp_key<0x141>(best));
     key_min(best, dpp_key<0x4E>(best));
     key_min(best, dpp_key<0xB1>(best));
+    bool keep = false;
+    if (ml.k12 > 0.0) {
+      // the guess's cost (one lane of the group holds it) and the block's sum
+      long long S = 0;
+      if (valid)
+        for (int r = 0; r < nby; ++r)
+          for (int c = l; c < nbx; c += LPG) S += tpl[r * B + c];
+      for (int m = 8; m >= 1; m >>= 1) {
+        S += __shfl_xor(S, m, LPG);
+        ssd_c += __shfl_xor(ssd_c, m, LPG);
+      }
+      keep = !gate_moves(ml, nby * nbx, S, ssd_c - best.ssd);
+    }
     if (valid && l == 0) {
-      const int k = best.tie & 0xffff;
+      const int k = keep ? kc : best.tie & 0xffff;
       const int dyi = k / D, dxi = k - (k / D) * D;
       vecs[(long long)f * vstride + ml.voff + t] = make_int2(gx + dxi - R, gy + dyi - R);
     }
@@ -611,6 +647,12 @@ hipError_t launch_align(const AlignGeom& ag, const uint16_t* frames, int H, int 
       ml.pgby = ml.parent ? ag.gby[l + 1] : 1;
       ml.pgbx = ml.parent ? ag.gbx[l + 1] : 1;
       ml.pvoff = ml.parent ? ag.voff[l + 1] : 0;
+      ml.level = l;
+      ml.k12 = ag.gate_k12;
+      ml.na = ag.na;
+      ml.nb = ag.nb;
+      ml.black = ag.black;
+      ml.rng = ag.rng;
       const int E = ml.B + 2 * ml.R;
       const int waves = ml.B <= 8 ? kWaves : 1;  // keeps LDS within 64 KiB per workgroup
       const size_t lds = (size_t)waves * 4 * (ml.B * ml.B + E * E) * 4;

@@ -211,7 +211,8 @@ namespace {
 hmfsr_status make_align_geom(const hmfsr_desc* d, const hmfsr_align_params* p, AlignGeom* ag) {
   if (d->tile_size > 64) return HMFSR_E_INVALID;
   if (p->levels < 1 || p->levels > kAlignMaxLevels || p->radius_coarse < 1 || p->radius_coarse > 8 ||
-      p->radius_fine < 1 || p->radius_fine > 8 || p->lk_iterations < 0 || p->lk_iterations > 16)
+      p->radius_fine < 1 || p->radius_fine > 8 || p->lk_iterations < 0 || p->lk_iterations > 16 ||
+      !(p->gate >= 0.0f && p->gate <= 1000.0f))
     return HMFSR_E_INVALID;
   AlignGeom a;
   memset(&a, 0, sizeof(a));
@@ -243,6 +244,12 @@ hmfsr_status make_align_geom(const hmfsr_desc* d, const hmfsr_align_params* p, A
   a.radius_coarse = p->radius_coarse;
   a.radius_fine = p->radius_fine;
   a.lk_iterations = p->lk_iterations;
+  const double kappa = (double)p->gate;
+  a.gate_k12 = (12.0 * kappa) * kappa;
+  a.na = (double)d->noise_a;
+  a.nb = (double)d->noise_b;
+  a.black = (double)d->black_level;
+  a.rng = (double)d->white_level - (double)d->black_level;
   *ag = a;
   return HMFSR_OK;
 }
@@ -469,7 +476,7 @@ hmfsr_status hmfsr_align(const hmfsr_desc* desc, const hmfsr_align_params* param
   if (st != HMFSR_OK) return st;
   if (!frames || !motion || ((uintptr_t)frames & 3) || ((uintptr_t)motion & 7) || ((uintptr_t)block_match & 7))
     return HMFSR_E_INVALID;
-  const hmfsr_align_params defaults = {4, 4, 2, 3};
+  const hmfsr_align_params defaults = {4, 4, 2, 3, 4.0f};
   AlignGeom ag;
   if ((st = make_align_geom(desc, params ? params : &defaults, &ag)) != HMFSR_OK) return st;
   std::lock_guard<std::mutex> lock(g_mutex);

@@ -197,6 +197,9 @@ struct AlignGeom {
   long long voff[kAlignMaxLevels];     // int2 offset of each level's vectors in one frame's set
   long long vstride;                   // int2 vectors per frame
   int radius_coarse, radius_fine, lk_iterations;
+  // noise gate: (12 kappa) kappa (0: off), then the noise model's a, b,
+  // black level and raw range white - black, as float64 from float32
+  double gate_k12, na, nb, black, rng;
 };
 
 // Workspace: pyramids [n][fstride] int32, then vectors [n][vstride] int2.

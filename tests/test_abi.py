@@ -135,6 +135,7 @@ def _align_call(desc, params, frames=8, motion=8, bm=None):
 @pytest.mark.parametrize("field,value", [
     ("levels", 0), ("levels", 7), ("radius_coarse", 0), ("radius_coarse", 9), ("radius_fine", 0),
     ("radius_fine", 9), ("lk_iterations", -1), ("lk_iterations", 17),
+    ("gate", -1.0), ("gate", 1001.0), ("gate", float("nan")), ("gate", float("inf")),
 ])
 def test_align_rejects_invalid_params(field, value):
     desc, _ = _good()

@@ -107,6 +107,39 @@ def test_even_integer_shift_exact():
     assert tuple(m[2, 8, 8]) == (-6.0, 10.0)
 
 
+@pytest.mark.parametrize("gate", [0.0, 1.5, 4.0, 40.0])
+def test_noise_gate_flat_edge_and_texture(gate):
+    """The noise gate on static flat and straight-edge content under noise
+    (where it keeps blocks at their guess) and on a shifted noisy texture
+    (where real offsets pass it): bit-exact against the oracle for gates off,
+    tight, default and loose."""
+    from test_oracle_align import noisy_raw, step_scene
+    rng = np.random.default_rng(900)
+    h, w = 128, 192
+    x = step_scene(h, w)
+    frames = np.stack([noisy_raw(rng, x, (h, w)) for _ in range(4)]).clip(0, 4095).astype(np.uint16)
+    d = synth.Desc(4, h, w, tile_size=16, noise_a=1e-3, noise_b=1e-6)
+    check_full(frames, d, {"gate": gate}, what=f"flat + edge, gate {gate}")
+    b = synth.make_burst(5, 160, 224, seed=5600, tile_size=16, scene="texture", sigma_t=6.0)
+    f, _ = b.numpy()
+    check_full(f, b.desc, {"gate": gate}, what=f"noisy texture, gate {gate}")
+
+
+def test_noise_gate_16_bit_range():
+    """16-bit raw values (white level 65535): level-3 costs exceed 2^53, and
+    the gate still decides as the oracle does."""
+    from test_oracle_align import textured_canvas
+    rng = np.random.default_rng(901)
+    h = w = 256
+    pad = 32
+    canvas = textured_canvas(h + 2 * pad, seed=21).astype(np.float64) * 16.0
+    clean = shifted_frames(canvas, h, w, pad, [(0, 0), (8, -6), (-14, 4)])
+    noisy = clean + rng.normal(size=clean.shape) * np.sqrt(1e-3 * clean + 1e4)
+    frames = np.ascontiguousarray(np.round(noisy).clip(0, 65535).astype(np.uint16))
+    d = synth.Desc(3, h, w, tile_size=16, black_level=0.0, white_level=65535.0, noise_a=2e-4, noise_b=1e-6)
+    check_full(frames, d, what="16-bit")
+
+
 def test_repeatable_bits():
     b = synth.make_config(1)
     m1, bm1 = gpu_align(b.frames, b.desc)

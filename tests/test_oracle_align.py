@@ -220,3 +220,106 @@ def test_sampled_tiles_equal_full_alignment():
             np.testing.assert_array_equal(ms[i], m[k, ty, tx])
             if k:
                 np.testing.assert_array_equal(bm[i], steps[k]["block_match"][ty, tx])
+
+
+# ----------------------------------------------------------------------------- noise gate
+A_N, B_N, BLACK, WHITE = 1e-3, 1e-6, 64.0, 4095.0
+NOISE = (A_N, B_N, BLACK, WHITE)
+
+
+def noisy_raw(rng, x, shape):
+    """Raw values of brightness x (float array or scalar) under the noise
+    model of Sec. 5.2.2: black + R (x + sqrt(a x + b) z), rounded."""
+    r = WHITE - BLACK
+    z = rng.normal(size=shape)
+    return np.round(BLACK + r * (x + np.sqrt(A_N * np.asarray(x) + B_N) * z)).astype(np.int64)
+
+
+def gate_threshold(tpl, level, gate):
+    """Smallest integer gain the oracle's gate lets move a block (bisection)."""
+    lo, hi = 0, 1
+    while not oa.noise_gate_moves(tpl, level, hi, gate, NOISE):
+        hi *= 2
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if oa.noise_gate_moves(tpl, level, mid, gate, NOISE):
+            hi = mid
+        else:
+            lo = mid
+    return hi
+
+
+@pytest.mark.parametrize("level,x", [(0, 0.3), (1, 0.3), (0, 0.05), (2, 0.7), (1, 0.001)])
+def test_noise_gate_threshold_is_kappa_noise_spreads(level, x):
+    """Monte Carlo: on a flat block of level l (a pixel sums 4^(l+1) raw
+    values drawn from the noise model), the cost difference of two
+    pixel-disjoint candidates has a standard deviation s; the gate's threshold
+    is kappa s. Fails for a wrong raw count per level, a wrong constant, a
+    noise model evaluated at the wrong brightness (black level not removed)
+    or a dropped term."""
+    rng = np.random.default_rng(40 + level)
+    m = 2 ** (level + 1)                 # raw pixels per level pixel, per axis
+    nb, trials = 8, 3000
+    raw = noisy_raw(rng, x, (trials, 3, nb * m, nb * m))
+    lvl = raw.reshape(trials, 3, nb, m, nb, m).sum(axis=(3, 5))
+    d1 = lvl[:, 1] - lvl[:, 0]
+    d2 = lvl[:, 2] - lvl[:, 0]
+    gains = (d1 * d1).sum(axis=(1, 2)) - (d2 * d2).sum(axis=(1, 2))
+    s = gains.std()
+    for kappa in (1.0, 4.0):
+        thr = gate_threshold(lvl[0, 0], level, kappa)
+        assert abs(thr / (kappa * s) - 1.0) < 0.06, (thr, kappa * s)
+
+
+def step_scene(h, w):
+    """Brightness: flat 0.3 left, 0.6 right of a vertical step edge."""
+    x = np.full((h, w), 0.3)
+    x[:, w // 2:] = 0.6
+    return x
+
+
+def test_noise_gate_keeps_flat_and_edge_blocks():
+    """Static flat and straight-edge content under noise: without the gate
+    noise moves many blocks (along the edge: the aperture problem); with it
+    every block keeps the zero vector, on every level."""
+    rng = np.random.default_rng(77)
+    h, w = 128, 192
+    x = step_scene(h, w)
+    frames = np.stack([noisy_raw(rng, x, (h, w)) for _ in range(4)]).clip(0, 4095).astype(np.uint16)
+    desc = dict(ref_frame=0, tile_size=16, noise_a=A_N, noise_b=B_N, black_level=BLACK, white_level=WHITE)
+    _, st0 = oa.align(frames, desc, dict(gate=0.0), debug=True)
+    _, st4 = oa.align(frames, desc, debug=True)
+    moved = sum(int(np.abs(st0[k]["block_match"]).sum() > 0) for k in (1, 2, 3))
+    assert moved == 3
+    for k in (1, 2, 3):
+        for lv in st4[k]["levels"]:
+            assert not lv.any()
+
+
+def test_noise_gate_keeps_real_shifts():
+    """Textured content shifted by whole (even) pixels under the same noise:
+    the gain of the true offset is far above the noise spread, so the gated
+    matcher still finds the exact shift, up to 20 half-res pixels away."""
+    rng = np.random.default_rng(78)
+    h = w = 256
+    pad = 48
+    canvas = textured_canvas(h + 2 * pad, seed=11).astype(np.float64)
+    shifts = [(0, 0), (40, -24), (-6, 10)]
+    clean = shifted_frames(canvas, h, w, pad, shifts)
+    xs = (clean - BLACK) / (WHITE - BLACK)
+    frames = np.stack([noisy_raw(rng, xs[k], (h, w)) for k in range(3)]).clip(0, 4095).astype(np.uint16)
+    desc = dict(ref_frame=0, tile_size=16, noise_a=A_N, noise_b=B_N, black_level=BLACK, white_level=WHITE)
+    _, st = oa.align(frames, desc, debug=True)
+    for k, (vx, vy) in enumerate(shifts[1:], start=1):
+        bm = st[k]["block_match"][3:-3, 3:-3].reshape(-1, 2)
+        assert (bm == (vx // 2, vy // 2)).all(axis=1).mean() > 0.97
+
+
+def test_noise_gate_off_equals_plain_argmin():
+    rng = np.random.default_rng(3)
+    base = rng.integers(0, 3, size=(21, 19)).astype(np.int64)
+    img = rng.integers(0, 3, size=(21, 19)).astype(np.int64)
+    for by in range(3):
+        for bx in range(3):
+            assert oa.match_block(base, img, 8, by, bx, (1, -1), 2, 0.0, NOISE, 0) == \
+                _brute_match(base.tolist(), img.tolist(), 8, by, bx, (1, -1), 2)
