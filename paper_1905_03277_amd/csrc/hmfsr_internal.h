@@ -56,7 +56,7 @@ struct BurstArgs {
   float* s_tile;  // workspace [n][TY][TX]
   unsigned char* mov;  // workspace [n][TY][TX]
   float* rmin;    // workspace [n][h][w]
-  float* gmu;     // workspace [n][3][h][w + 2]
+  uint2* gmu;     // workspace [n][h][w + 2]
   float* gref;    // workspace [h][w]
   Geometry g;
   MergeConsts mc;
@@ -78,8 +78,9 @@ struct Work {
   float* s_tile;  // [n][TY][TX]
   unsigned char* mov;  // [n][TY][TX] 1 where the motion prior chose s1 (eq. 8)
   float* rmin;    // [n][h][w]
-  float* gmu;     // [n][3][h][w + 2] 3x3 box means of every frame's guide (raw units), a
-                  // replicated edge column on either side (column Q at Q + 1)
+  uint2* gmu;     // [n][h][w + 2] 3x3 box sums of every frame's guide (raw units, packed as
+                  // guide_maps.h states), a replicated edge column on either side (column
+                  // Q at Q + 1)
   float* gref;    // [h][w] base frame: 1 / sum_c sigma_c^2 of eq. (5)-(6), negated where S.3 finds a loss
 };
 size_t work_bytes(const Geometry& g);

@@ -103,9 +103,9 @@ size_t a256(size_t b) { return (b + 255) / 256 * 256; }
 
 size_t work_bytes(const Geometry& g) {
   const size_t plane = (size_t)g.h * g.w * sizeof(float);
-  const size_t mu_plane = (size_t)g.h * (g.w + 2) * sizeof(float);
+  const size_t mu_plane = (size_t)g.h * (g.w + 2) * sizeof(uint2);
   return a256((size_t)g.TY * g.TX * g.n * sizeof(float)) + a256((size_t)g.TY * g.TX * g.n) +
-         a256(plane * g.n) + a256(mu_plane * 3 * g.n) + a256(plane);
+         a256(plane * g.n) + a256(mu_plane * g.n) + a256(plane);
 }
 
 Work work_carve(void* base, const Geometry& g) {
@@ -118,8 +118,8 @@ Work work_carve(void* base, const Geometry& g) {
   p += a256((size_t)g.TY * g.TX * g.n);
   w.rmin = (float*)p;
   p += a256(plane * g.n);
-  w.gmu = (float*)p;
-  p += a256((size_t)g.h * (g.w + 2) * sizeof(float) * 3 * g.n);
+  w.gmu = (uint2*)p;
+  p += a256((size_t)g.h * (g.w + 2) * sizeof(uint2) * g.n);
   w.gref = (float*)p;
   return w;
 }

@@ -36,6 +36,7 @@
 #include <math.h>
 
 #include "device_util.h"
+#include "guide_maps.h"
 #include "hmfsr_internal.h"
 #include "noise.h"
 #include "merge_common.h"
@@ -645,12 +646,12 @@ __device__ int rh_tiles(int I, int n_out, int edge, int n_tiles_axis, int n_half
   }
   return cnt;
 }
-// The guide statistics are read from the forward's maps: the 3x3 means of
+// The guide statistics are read from the forward's maps: the 3x3 sums of
 // every frame (rows of w + 2 with a replicated edge column each side) and the
 // base frame's 1 / sum sigma^2 (its sign carries the S.3 test, which the
 // clamped R here already reflects), so the adjoint differentiates exactly the
 // values the forward used.
-__global__ __launch_bounds__(64, 4) void k_robust_bwd(const float* __restrict__ gmu,
+__global__ __launch_bounds__(64, 4) void k_robust_bwd(const uint2* __restrict__ gmu,
                                                    const float* __restrict__ gref,
                                                    const float* __restrict__ motion,
                                                    const float* __restrict__ rmap,
@@ -674,8 +675,8 @@ __global__ __launch_bounds__(64, 4) void k_robust_bwd(const float* __restrict__ 
   const float* R = rmap + (size_t)n * plane;
   const int ws = g.w + 2;
   const size_t mplane = (size_t)g.h * ws;
-  const float* mref = gmu + (size_t)g.ref * 3 * mplane;
-  const float* mfr = gmu + (size_t)n * 3 * mplane;
+  const uint2* mref = gmu + (size_t)g.ref * mplane;
+  const uint2* mfr = gmu + (size_t)n * mplane;
   const bool moving = prior_moving(motion, g, pc.m_th, n, ty, tx);
   const float s_used = moving ? pc.s1 : pc.s2;
   const float vlim = (float)(max(g.W, g.H) + 16);
@@ -756,9 +757,9 @@ __global__ __launch_bounds__(64, 4) void k_robust_bwd(const float* __restrict__ 
         if (gR != 0.f && Rv > 0.f && Rv < 1.f) {  // unclamped R of eq. (5)
           const float inv = fabsf(gref[(size_t)i * g.w + j]);  // 1 / sum_c sigma_c^2, eq. (5)
           float mu_ref[3], dmd2[3];
+          guide_means(mref[(size_t)i * ws + j + 1], mu_ref);
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            mu_ref[c] = mref[(size_t)c * mplane + (size_t)i * ws + j + 1];
             float sig2;
             noise_md(rc, mu_ref[c], c, sig2, dmd2[c]);
           }
@@ -769,11 +770,14 @@ __global__ __launch_bounds__(64, 4) void k_robust_bwd(const float* __restrict__ 
           const int xa = clampi((int)fhx, 0, g.w - 1), xb = clampi((int)fhx + 1, 0, g.w - 1);
           const int ya = clampi((int)fhy, 0, g.h - 1), yb = clampi((int)fhy + 1, 0, g.h - 1);
           float top[3], bot[3], dtop[3], dbot[3];
+          float ea[3], eb[3], ec[3], ed[3];
+          guide_means(mfr[(size_t)ya * ws + xa + 1], ea);
+          guide_means(mfr[(size_t)ya * ws + xb + 1], eb);
+          guide_means(mfr[(size_t)yb * ws + xa + 1], ec);
+          guide_means(mfr[(size_t)yb * ws + xb + 1], ed);
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const float* m = mfr + (size_t)c * mplane;
-            const float ma = m[(size_t)ya * ws + xa + 1], mb = m[(size_t)ya * ws + xb + 1];
-            const float mc = m[(size_t)yb * ws + xa + 1], md = m[(size_t)yb * ws + xb + 1];
+            const float ma = ea[c], mb = eb[c], mc = ec[c], md = ed[c];
             dtop[c] = mb - ma;
             top[c] = fmaf(fx, dtop[c], ma);
             dbot[c] = md - mc;

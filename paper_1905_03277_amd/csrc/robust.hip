@@ -3,12 +3,13 @@
 // (eq. 7-8, precomputed per tile) and the 5x5 minimum (eq. 9).
 //
 // Two passes:
-//  * guide statistics: k_frame_means writes the 3x3 box means of every
-//    aligned frame's guide (R, mean G, B; edge-replicated) into a map
-//    [n][3][h][w + 2] (the edge columns repeated once on either side, so that
-//    the two horizontal bilinear corners are adjacent whatever the clamping),
-//    one wave walking down a 64-column strip with the row sums in registers;
-//    k_base_stats writes the base frame's means and the reciprocal of its
+//  * guide statistics: k_frame_means writes the 3x3 box sums of every
+//    aligned frame's guide (R, the two greens, B; edge-replicated; exact
+//    integers packed into 8 bytes, guide_maps.h) into a map [n][h][w + 2]
+//    (the edge columns repeated once on either side, so that the two
+//    horizontal bilinear corners are adjacent whatever the clamping), one
+//    wave walking down a 64-column strip with the row sums in registers;
+//    k_base_stats writes the base frame's sums and the reciprocal of its
 //    noise-corrected variance sum of eq. (5)-(6) into [h][w], negated where
 //    the S.3 test below finds a variance loss.
 //  * k_robust: one workgroup per 32x16 tile of the base half-res grid, the
@@ -30,6 +31,7 @@
 // where A < hf * 81 B (variance lost to the low-pass) and the tile's motion
 // prior chose s1 (eq. 8), R of the aligned frame is 0.
 #include "device_util.h"
+#include "guide_maps.h"
 #include "hmfsr_internal.h"
 #include "noise.h"
 
@@ -56,25 +58,20 @@ __host__ __device__ __forceinline__ int robust_tiles_y_(const Geometry& g) { ret
 __host__ __device__ __forceinline__ int means_tiles_x(const Geometry& g) { return (g.w + GM_W - 1) / GM_W; }
 __host__ __device__ __forceinline__ int means_tiles_y(const Geometry& g) { return (g.h + GM_H - 1) / GM_H; }
 
-// Row stride of the mean maps: column Q of row P at P * mu_stride + Q + 1,
+// Row stride of the guide maps: column Q of row P at P * mu_stride + Q + 1,
 // columns -1 and w repeating columns 0 and w - 1.
 __device__ __forceinline__ int mu_stride(const Geometry& g) { return g.w + 2; }
 
-// Raw buffer resource over one mean-map plane (word 3 as for gfx9 raw
-// buffers); a plane holds at most 16384 x 16386 floats, below 2^31 bytes.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* p, size_t floats) {
-  return __builtin_amdgcn_make_buffer_rsrc((void*)p, 0, (int)(floats * 4), 0x00020000);
+// Raw buffer resource over `bytes` bytes from p (word 3 as for gfx9 raw
+// buffers; bytes below 2^31).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t bytes_rsrc(const void* p, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, 0, (int)bytes, 0x00020000);
 }
 
-// One float at byte offset off.
-__device__ __forceinline__ float ld_one(__amdgpu_buffer_rsrc_t r, int off) {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-
-// Two consecutive floats at byte offset off (one dwordx2 load).
-__device__ __forceinline__ float2 ld_pair(__amdgpu_buffer_rsrc_t r, int off) {
+// One packed guide-map entry at byte offset off (one dwordx2 load).
+__device__ __forceinline__ uint2 ld_entry(__amdgpu_buffer_rsrc_t r, int off) {
   const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
-  return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
+  return make_uint2(v[0], v[1]);
 }
 
 // Last burst b with first[b] <= i.
@@ -99,6 +96,14 @@ __host__ __device__ __forceinline__ int fm_bands(const Geometry& g) {
   return (g.h + FM_ROWS * FM_WAVES - 1) / (FM_ROWS * FM_WAVES);
 }
 
+// Guide of one quad (its two 32-bit rows) as integers: R, the sum of the two
+// greens, B.
+__device__ __forceinline__ void guide_sums_of(uint32_t top, uint32_t bot, const Geometry& g, uint32_t (&v)[3]) {
+  v[0] = quad_at(top, bot, g.red_pos);
+  v[1] = quad_at(top, bot, g.green_pos[0]) + quad_at(top, bot, g.green_pos[1]);
+  v[2] = quad_at(top, bot, g.blue_pos);
+}
+
 // Guide pixel of one quad (its two 32-bit rows) in raw units: R, mean of the
 // two greens, B.
 __device__ __forceinline__ void guide_of(uint32_t top, uint32_t bot, const Geometry& g, float (&v)[3]) {
@@ -108,7 +113,7 @@ __device__ __forceinline__ void guide_of(uint32_t top, uint32_t bot, const Geome
 }
 
 __device__ __forceinline__ void frame_means_block(const uint16_t* __restrict__ frames, const Geometry& g,
-                                                  float* __restrict__ gmu, int n, int strip, int band) {
+                                                  uint2* __restrict__ gmu, int n, int strip, int band) {
   const int lane = threadIdx.x & 63;
   const int P0 = band * FM_ROWS;
   if (P0 >= g.h) return;  // uniform per wave; no barrier follows
@@ -117,8 +122,7 @@ __device__ __forceinline__ void frame_means_block(const uint16_t* __restrict__ f
   const int Jh = clampi(lane == 0 ? J - 1 : J + 1, 0, g.w - 1);  // the edge lanes' outer neighbour
   const uint16_t* f = frames + (size_t)n * g.H * g.W;
   const int ws = mu_stride(g);
-  const size_t plane = (size_t)g.h * ws;
-  float* mu = gmu + (size_t)n * 3 * plane;
+  uint2* mu = gmu + (size_t)n * g.h * ws;
   // every row's quads first, so that the loads are all in flight together
   uint32_t top[FM_ROWS + 2], bot[FM_ROWS + 2], htop[FM_ROWS + 2], hbot[FM_ROWS + 2];
 #pragma unroll
@@ -135,31 +139,28 @@ __device__ __forceinline__ void frame_means_block(const uint16_t* __restrict__ f
       hbot[i] = *(const uint32_t*)(f + (size_t)(2 * I + 1) * g.W + 2 * Jh);
     }
   }
-  // 3x3 box mean, separable: Hs = (g(Q-1) + g(Q)) + g(Q+1), then
-  // (Hs(P-1) + Hs(P)) + Hs(P+1), times 1/9
-  float h0[3] = {0.f, 0.f, 0.f}, h1[3] = {0.f, 0.f, 0.f};
+  // 3x3 box sums, separable: Hs = g(Q-1) + g(Q) + g(Q+1), then
+  // Hs(P-1) + Hs(P) + Hs(P+1), in integers
+  uint32_t h0[3] = {0u, 0u, 0u}, h1[3] = {0u, 0u, 0u};
 #pragma unroll
   for (int i = 0; i < FM_ROWS + 2; ++i) {
-    float v[3], hv[3] = {0.f, 0.f, 0.f};
-    guide_of(top[i], bot[i], g, v);
-    if (edge) guide_of(htop[i], hbot[i], g, hv);
-    float hs[3];
+    uint32_t v[3], hv[3] = {0u, 0u, 0u};
+    guide_sums_of(top[i], bot[i], g, v);
+    if (edge) guide_sums_of(htop[i], hbot[i], g, hv);
+    uint32_t hs[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const float up = __shfl_up(v[c], 1, 64), dn = __shfl_down(v[c], 1, 64);
-      const float l = lane == 0 ? hv[c] : up, r = lane == 63 ? hv[c] : dn;
-      hs[c] = (l + v[c]) + r;
+      const uint32_t up = __shfl_up(v[c], 1, 64), dn = __shfl_down(v[c], 1, 64);
+      const uint32_t l = lane == 0 ? hv[c] : up, r = lane == 63 ? hv[c] : dn;
+      hs[c] = l + v[c] + r;
     }
-    const int P = P0 + i - 2;  // the row whose mean is complete
+    const int P = P0 + i - 2;  // the row whose sums are complete
     if (i >= 2 && J < g.w && P < g.h) {
-      float* row = mu + (size_t)P * ws + J + 1;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float m = ((h0[c] + h1[c]) + hs[c]) * (1.f / 9.f);
-        row[(size_t)c * plane] = m;
-        if (J == 0) row[(size_t)c * plane - 1] = m;        // column -1
-        if (J == g.w - 1) row[(size_t)c * plane + 1] = m;  // column w
-      }
+      uint2* row = mu + (size_t)P * ws + J + 1;
+      const uint2 m = pack_guide_sums(h0[0] + h1[0] + hs[0], h0[1] + h1[1] + hs[1], h0[2] + h1[2] + hs[2]);
+      row[0] = m;
+      if (J == 0) row[-1] = m;        // column -1
+      if (J == g.w - 1) row[1] = m;  // column w
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -173,7 +174,7 @@ __device__ __forceinline__ void frame_means_block(const uint16_t* __restrict__ f
 // XCD so that neighbouring strips and bands, which share the edge columns and
 // rows, meet in one L2.
 __global__ __launch_bounds__(THREADS) void k_frame_means(const uint16_t* __restrict__ frames, Geometry g,
-                                                         float* __restrict__ gmu) {
+                                                         uint2* __restrict__ gmu) {
   const int n = (int)blockIdx.y < g.ref ? (int)blockIdx.y : (int)blockIdx.y + 1;
   const int ns = fm_strips(g), t = xcd_tile(blockIdx.x, ns * fm_bands(g));
   frame_means_block(frames, g, gmu, n, t % ns, (t / ns) * FM_WAVES + (threadIdx.x >> 6));
@@ -201,7 +202,7 @@ struct BaseSmem {
 // One 64x16 tile (tile_x, tile_y): the base frame's 3x3 guide means into
 // gmu[ref] and the reciprocal variance sum, with its S.3 sign, into gref.
 __device__ __forceinline__ void base_stats_tile(const uint16_t* __restrict__ frames, const Geometry& g,
-                                                const RobustConsts& rc, float* __restrict__ gmu,
+                                                const RobustConsts& rc, uint2* __restrict__ gmu,
                                                 float* __restrict__ gref, int tile_x, int tile_y, BaseSmem& sm) {
   const int tid = threadIdx.x;
   const int I0 = tile_y * GM_H, J0 = tile_x * GM_W;
@@ -255,14 +256,13 @@ __device__ __forceinline__ void base_stats_tile(const uint16_t* __restrict__ fra
   }
   // 3x3 mean and population variance of the guide, noise-corrected per
   // channel (eq. 6), the reciprocal of their sum (eq. 5)
-  const size_t mplane = (size_t)g.h * mu_stride(g);
   for (int k = tid; k < GM_H * GM_W; k += THREADS) {
     const int i = k >> 6, j = k & (GM_W - 1);  // GM_W == 64
     if (i >= oh || j >= ow) continue;
     const int P = I0 + i, Q = J0 + j;
     const int o = (i + 1) * GW_W + (j + 1);  // window position of (P - 1, Q - 1)
     float den = 0.f;
-    float mu3[3];
+    float sum3[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       float v[9];
@@ -274,7 +274,7 @@ __device__ __forceinline__ void base_stats_tile(const uint16_t* __restrict__ fra
           v[a * 3 + b] = sm.G[c][o + a * GW_W + b];
           s += v[a * 3 + b];
         }
-      const float mu = s * (1.f / 9.f);
+      const float mu = __fmul_rn(s, 1.f / 9.f);  // the map's mean (guide_maps.h)
       float var_ms = 0.f;
 #pragma unroll
       for (int q = 0; q < 9; ++q) var_ms = fmaf(v[q] - mu, v[q] - mu, var_ms);
@@ -283,7 +283,7 @@ __device__ __forceinline__ void base_stats_tile(const uint16_t* __restrict__ fra
       // the mean of two greens)
       float var_md, dmd2_unused;
       noise_md(rc, mu, c, var_md, dmd2_unused);
-      mu3[c] = mu;
+      sum3[c] = s;
       den += fmaxf(var_ms, var_md);  // sigma = max(sigma_ms, sigma_md), eq. (6)
     }
     float inv = 1.f / den;
@@ -310,14 +310,15 @@ __device__ __forceinline__ void base_stats_tile(const uint16_t* __restrict__ fra
       }
       if (A < rc.hf * (81.0 * B)) inv = -inv;
     }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) gmu[((size_t)g.ref * 3 + c) * mplane + (size_t)P * mu_stride(g) + Q + 1] = mu3[c];
+    // the sums are exact floats: the guide values are integers and halves
+    gmu[((size_t)g.ref * g.h + P) * mu_stride(g) + Q + 1] =
+        pack_guide_sums((uint32_t)sum3[0], (uint32_t)(2.f * sum3[1]), (uint32_t)sum3[2]);
     gref[(size_t)P * g.w + Q] = inv;
   }
 }
 
 __global__ __launch_bounds__(THREADS) void k_base_stats(const uint16_t* __restrict__ frames, Geometry g,
-                                                        RobustConsts rc, float* __restrict__ gmu,
+                                                        RobustConsts rc, uint2* __restrict__ gmu,
                                                         float* __restrict__ gref) {
   __shared__ BaseSmem sm;
   const int tx_n = means_tiles_x(g), t = xcd_tile(blockIdx.x, tx_n * means_tiles_y(g));
@@ -366,7 +367,7 @@ struct RobustSmem {
 // and so the results, are the same either way.
 __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, const float* __restrict__ s_tile,
                                             const unsigned char* __restrict__ mov, const Geometry& g,
-                                            const RobustConsts& rc, const float* __restrict__ gmu,
+                                            const RobustConsts& rc, const uint2* __restrict__ gmu,
                                             const float* __restrict__ gref, float* __restrict__ rmin,
                                             float* __restrict__ robust, int tile_x, int tile_y, int m_first,
                                             int m_count, RobustSmem& sm) {
@@ -375,7 +376,7 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
   const int ra0 = I0 - 2, ca0 = J0 - 2;  // region origin (may be outside the grid)
   const size_t plane = (size_t)g.h * g.w;
   const int ws = mu_stride(g);
-  const size_t mplane = (size_t)g.h * ws;
+  const size_t mplane = (size_t)g.h * ws;  // entries of one frame's guide map
 
   if (tid < RR_W) sm.sTxR[tid] = min(2 * clampi(ca0 + tid, 0, g.w - 1) / g.T, g.TX - 1);
   if (tid >= 64 && tid < 64 + RR_H) {
@@ -412,9 +413,9 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
       Ic[q] = clampi(ra0 + rr, 0, g.h - 1);
       Jc[q] = clampi(ca0 + cc, 0, g.w - 1);
       gi[q] = gref[(size_t)Ic[q] * g.w + Jc[q]];
+      guide_means(gmu[(size_t)g.ref * mplane + (size_t)Ic[q] * ws + Jc[q] + 1], mr[q]);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        mr[q][c] = gmu[((size_t)g.ref * 3 + c) * mplane + (size_t)Ic[q] * ws + Jc[q] + 1];
         float sig2_unused;
         noise_md(rc, mr[q][c], c, sig2_unused, dm[q][c]);  // d_md^2 at the base brightness
       }
@@ -467,32 +468,31 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
         between();
         return false;
       }
-      const float* fm = gmu + (size_t)n * 3 * mplane;
-      const __amdgpu_buffer_rsrc_t q0 = plane_rsrc(fm, mplane), q1 = plane_rsrc(fm + mplane, mplane),
-                                   q2 = plane_rsrc(fm + 2 * mplane, mplane);
-      const int base = Y0 * ws + X0;  // the window's first entry in the plane (below 2^29)
+      // the map's rows Y0 .. Y0 + wy - 1 (fewer than WCAP rows of at most
+      // 16386 entries: below 2^31 bytes)
+      const __amdgpu_buffer_rsrc_t q =
+          bytes_rsrc(gmu + ((size_t)n * g.h + Y0) * ws, (size_t)wy * ws * sizeof(uint2));
       const float inv = 1.f / (float)wx;
       const int nw = wx * wy;
       // every load of the copy in flight before the first store
-      float v[WPT][3];
+      uint2 v[WPT];
 #pragma unroll
       for (int i = 0; i < WPT; ++i) {
         const int k = tid + i * THREADS;
         if (k >= nw) continue;
         const int r = split_row(k, inv);
-        const int off = (base + mul24(r, ws) + (k - mul24(r, wx))) * 4;
-        v[i][0] = ld_one(q0, off);
-        v[i][1] = ld_one(q1, off);
-        v[i][2] = ld_one(q2, off);
+        v[i] = ld_entry(q, (mul24(r, ws) + X0 + (k - mul24(r, wx))) * (int)sizeof(uint2));
       }
       between();
 #pragma unroll
       for (int i = 0; i < WPT; ++i) {
         const int k = tid + i * THREADS;
         if (k >= nw) continue;
-        sm.sW[0][k] = v[i][0];
-        sm.sW[1][k] = v[i][1];
-        sm.sW[2][k] = v[i][2];
+        float m[3];
+        guide_means(v[i], m);
+        sm.sW[0][k] = m[0];
+        sm.sW[1][k] = m[1];
+        sm.sW[2][k] = m[2];
       }
       return true;
     };
@@ -500,9 +500,7 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
     __syncthreads();
     for (int fl = 0; fl < nf; ++fl) {
       const int m = m0 + fl, n = m < g.ref ? m : m + 1;
-      const float* mun = gmu + (size_t)n * 3 * mplane;
-      const __amdgpu_buffer_rsrc_t rs[3] = {plane_rsrc(mun, mplane), plane_rsrc(mun + mplane, mplane),
-                                            plane_rsrc(mun + 2 * mplane, mplane)};
+      const uint2* mun = gmu + (size_t)n * mplane;
       const int X0 = sm.sBox[fl][0], Y0 = sm.sBox[fl][2], wx = -sm.sBox[fl][1] - X0 + 1;
 #pragma unroll
       for (int q = 0; q < PP; ++q) {
@@ -526,15 +524,17 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
             mm[c][3] = sm.sW[c][ib + 1];
           }
         } else {
-          const int oa = (ya * ws + x0) * 4, ob = (yb * ws + x0) * 4;  // bytes, below 2^31
+          const uint2* ra = mun + (size_t)ya * ws + x0;
+          const uint2* rb = mun + (size_t)yb * ws + x0;
+          float e[4][3];
+          guide_means(ra[0], e[0]);
+          guide_means(ra[1], e[1]);
+          guide_means(rb[0], e[2]);
+          guide_means(rb[1], e[3]);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const float2 ra = ld_pair(rs[c], oa), rb = ld_pair(rs[c], ob);
-            mm[c][0] = ra.x;
-            mm[c][1] = ra.y;
-            mm[c][2] = rb.x;
-            mm[c][3] = rb.y;
-          }
+          for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) mm[c][k] = e[k][c];
         }
         float num = 0.f;
 #pragma unroll
@@ -587,7 +587,7 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
 __global__ __launch_bounds__(THREADS, 6) void k_robust(const float* __restrict__ motion,
                                                     const float* __restrict__ s_tile,
                                                     const unsigned char* __restrict__ mov, Geometry g,
-                                                    RobustConsts rc, const float* __restrict__ gmu,
+                                                    RobustConsts rc, const uint2* __restrict__ gmu,
                                                     const float* __restrict__ gref, float* __restrict__ rmin,
                                                     float* __restrict__ robust, int m_per) {
   __shared__ RobustSmem sm;
