@@ -64,9 +64,9 @@ def algorithmic_bytes(desc) -> dict:
 
 
 # Sources whose code the merge kernel's traffic figures depend on.
-TRAFFIC_SOURCES = ("paper_1905_03277_amd/csrc/merge.hip", "paper_1905_03277_amd/csrc/merge_common.h",
-                   "paper_1905_03277_amd/csrc/omega.h", "paper_1905_03277_amd/csrc/device_util.h",
-                   "paper_1905_03277_amd/csrc/hmfsr_internal.h")
+TRAFFIC_SOURCES = ("paper_1905_03277_amd/csrc/merge.hip", "paper_1905_03277_amd/csrc/merge_tile.h",
+                   "paper_1905_03277_amd/csrc/merge_common.h", "paper_1905_03277_amd/csrc/omega.h",
+                   "paper_1905_03277_amd/csrc/device_util.h", "paper_1905_03277_amd/csrc/hmfsr_internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "merge_fwd_12mp_x8_traffic.md")
 CALIB_BYTES = 256 << 20    # the plain copy the HBM counters are scaled by
 

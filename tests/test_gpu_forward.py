@@ -71,6 +71,33 @@ def test_robustness_maps_any_motion(spread):
     np.testing.assert_allclose(maps["robust_min"].cpu().numpy(), ref["r_hat"], rtol=0, atol=5e-5)
 
 
+@pytest.mark.parametrize("spread", [0.0, 60.0], ids=["coherent", "divergent"])
+def test_sixteen_bit_raw_values(spread):
+    """Raw values up to 65535 (a 12-bit burst times 16 plus 15, black level
+    1024, white level 65535): the guide maps' 3x3 sums then need all their
+    bits (up to 9 x 65535 per colour, 18 x 65535 for the greens). R, R_hat
+    and the merge against the oracle, through the staged corner window
+    (coherent field) and the direct reads (divergent field)."""
+    b = synth.make_burst(4, 96, 160, seed=63, scale=1.5, tile_size=16)
+    f, m = b.numpy()
+    f16 = (f.astype(np.uint32) * 16 + 15).astype(np.uint16)
+    assert f16.max() == 65535
+    desc = b.desc.replace(black_level=1024.0, white_level=65535.0)
+    rng = np.random.default_rng(64)
+    m = m.copy()
+    m[1:] += rng.uniform(-spread, spread, size=m[1:].shape).astype(np.float32)
+    m[0] = 0
+    m = m.astype(np.float32)
+    case("16-bit", spread=spread)
+    maps = torch_ops.merge_maps(torch.from_numpy(f16.astype(np.int16)).to(DEV), torch.from_numpy(m).to(DEV),
+                                desc, b.tuning)
+    ref = om.prepare(f16, m, desc, b.tuning)
+    np.testing.assert_allclose(maps["robust"].cpu().numpy(), ref["r"], rtol=0, atol=5e-5)
+    np.testing.assert_allclose(maps["robust_min"].cpu().numpy(), ref["r_hat"], rtol=0, atol=5e-5)
+    got = gpu_merge(f16, m, desc, b.tuning)
+    assert_parity(got, om.merge(f16, m, desc, b.tuning), "16-bit")
+
+
 SMALL = [
     # name, n, h, w, scale, tile, cfa, ref, sigma_t
     ("s1_rggb", 4, 64, 96, 1.0, 16, 0, 0, 1.5),
