@@ -581,6 +581,8 @@ def main():
     ap.add_argument("--no-stream", action="store_true", help="skip the frame-by-frame streaming leg")
     ap.add_argument("--no-align", action="store_true", help="skip the alignment / raw-to-RGB leg")
     ap.add_argument("--no-configs", action="store_true", help="skip the config-3 and config-1 legs")
+    ap.add_argument("--only-config", type=int, choices=(1, 3), default=None,
+                    help="time only that workload's forward merge (for a profile of it alone) and print its record")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus 1); the merge shards by "
@@ -592,6 +594,10 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.only_config is not None:
+        print(json.dumps({"only_config": args.only_config, **bench_config(args.only_config, dev, args.steps)}),
+              flush=True)
+        return
     print("[bench] generating 8x3024x4032 burst", file=sys.stderr, flush=True)
     burst = synth.make_config(2, device=dev)
     d = burst.desc
