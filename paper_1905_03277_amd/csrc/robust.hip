@@ -12,7 +12,7 @@
 //    k_base_stats writes the base frame's sums and the reciprocal of its
 //    noise-corrected variance sum of eq. (5)-(6) into [h][w], negated where
 //    the S.3 test below finds a variance loss.
-//  * k_robust: one workgroup per 32x16 tile of the base half-res grid, the
+//  * k_robust: one workgroup per 32x32 tile of the base half-res grid, the
 //    aligned frames in turn (the base statistics stay in registers; on small
 //    grids the frames are split over several workgroups per tile). R is
 //    evaluated on the tile plus a 2-pixel border (the min-pool footprint;
@@ -38,7 +38,7 @@
 namespace hmfsr {
 namespace {
 
-constexpr int RB_W = 32, RB_H = 16;              // output tile of R_hat (half-res px)
+constexpr int RB_W = 32, RB_H = 32;              // output tile of R_hat (half-res px)
 constexpr int RR_W = RB_W + 4, RR_H = RB_H + 4;  // robustness region incl. the min-pool border
 constexpr int RR_N = RR_W * RR_H;
 constexpr int TT_X = RR_W / 4 + 2, TT_Y = RR_H / 4 + 2;  // alignment tiles spanned (T >= 8)
@@ -339,10 +339,11 @@ __global__ __launch_bounds__(THREADS) void k_base_stats_batch(const BurstArgs* _
 // ---- pass 2: robustness and its 5x5 minimum ---------------------------------------
 constexpr int TT = TT_X * TT_Y;
 constexpr int NF = 4;                               // aligned frames whose tile data are staged at once
-constexpr int PP = (RR_N + THREADS - 1) / THREADS;  // region pixels per thread
-constexpr int WCAP = 1152;  // mean-map window of one frame (per channel): every corner of the region
-constexpr int WPT = (WCAP + THREADS - 1) / THREADS;  // window entries per thread
-constexpr long long kRobustGroups = 6144;  // target workgroup count of one robustness launch
+constexpr int RTHREADS = 512;                          // robustness workgroup
+constexpr int PP = (RR_N + RTHREADS - 1) / RTHREADS;  // region pixels per thread
+constexpr int WCAP = 2048;  // guide-map window of one frame (per channel): every corner of the region
+constexpr int WPT = (WCAP + RTHREADS - 1) / RTHREADS;  // window entries per thread
+constexpr long long kRobustGroups = 3072;  // target workgroup count of one robustness launch
 
 struct RobustSmem {
   float sW[3][WCAP];           // the frame's mean maps over the region's corners
@@ -357,7 +358,7 @@ struct RobustSmem {
   int sItem;
 };
 
-// R_hat of one 32x16 half-res tile (tile_x, tile_y), aligned frames
+// R_hat of one 32x32 half-res tile (tile_x, tile_y), aligned frames
 // m_first .. m_first + m_count - 1 (m indexes the frames other than the base).
 //
 // Per frame, the mean-map rows and columns that hold any bilinear corner of
@@ -406,7 +407,7 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
     const float rinv = 1.f / (float)RR_W;
 #pragma unroll
     for (int q = 0; q < PP; ++q) {
-      const int k = tid + q * THREADS;
+      const int k = tid + q * RTHREADS;
       const int kk = k < RR_N ? k : RR_N - 1;
       const int rr = split_row(kk, rinv), cc = kk - rr * RR_W;
       kt[q] = (sm.sTyR[rr] - tyA) * ntx + (sm.sTxR[cc] - txA);
@@ -434,7 +435,7 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
     // corner of u + v/2 is u + floor(v/2), u integer, with the same fractions
     // for every pixel of the tile), the rejection strength, the prior's
     // choice, and the tile's corner window (monotonic in the pixel position)
-    for (int k = tid; k < nf * ntiles; k += THREADS) {
+    for (int k = tid; k < nf * ntiles; k += RTHREADS) {
       const int fl = k / ntiles, kk = k - fl * ntiles;
       const int m = m0 + fl, n = m < g.ref ? m : m + 1;
       const int ky = kk / ntx, kx = kk - ky * ntx;
@@ -478,7 +479,7 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
       uint2 v[WPT];
 #pragma unroll
       for (int i = 0; i < WPT; ++i) {
-        const int k = tid + i * THREADS;
+        const int k = tid + i * RTHREADS;
         if (k >= nw) continue;
         const int r = split_row(k, inv);
         v[i] = ld_entry(q, (mul24(r, ws) + X0 + (k - mul24(r, wx))) * (int)sizeof(uint2));
@@ -486,7 +487,7 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
       between();
 #pragma unroll
       for (int i = 0; i < WPT; ++i) {
-        const int k = tid + i * THREADS;
+        const int k = tid + i * RTHREADS;
         if (k >= nw) continue;
         float m[3];
         guide_means(v[i], m);
@@ -504,7 +505,7 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
       const int X0 = sm.sBox[fl][0], Y0 = sm.sBox[fl][2], wx = -sm.sBox[fl][1] - X0 + 1;
 #pragma unroll
       for (int q = 0; q < PP; ++q) {
-        const int k = tid + q * THREADS;
+        const int k = tid + q * RTHREADS;
         if (k >= RR_N) continue;
         const int4 of = sm.sOF[fl][kt[q]];
         const float fx = __int_as_float(of.z), fy = __int_as_float(of.w);
@@ -559,7 +560,7 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
       // its first pass runs while the next frame's window loads (the window
       // is free again)
       auto rows_min = [&] {
-        for (int k = tid; k < RR_H * RB_W; k += THREADS) {
+        for (int k = tid; k < RR_H * RB_W; k += RTHREADS) {
           const int r = k >> 5, j = k & 31;  // RB_W == 32
           const float* row = sm.sR + r * RR_W + j;
           sm.sTmp[k] = fminf(fminf(fminf(row[0], row[1]), fminf(row[2], row[3])), row[4]);
@@ -568,7 +569,7 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
       if (fl + 1 < nf) staged = stage(fl + 1, rows_min);
       else rows_min();
       __syncthreads();
-      for (int k = tid; k < RB_H * RB_W; k += THREADS) {
+      for (int k = tid; k < RB_H * RB_W; k += RTHREADS) {
         const int i = k >> 5, j = k & 31;
         if (i >= oh || j >= ow) continue;
         const float* col = sm.sTmp + i * RB_W + j;
@@ -584,7 +585,7 @@ __device__ __forceinline__ void robust_tile(const float* __restrict__ motion, co
 }
 
 // Workgroup (tile, group of m_per aligned frames).
-__global__ __launch_bounds__(THREADS, 6) void k_robust(const float* __restrict__ motion,
+__global__ __launch_bounds__(RTHREADS, 6) void k_robust(const float* __restrict__ motion,
                                                     const float* __restrict__ s_tile,
                                                     const unsigned char* __restrict__ mov, Geometry g,
                                                     RobustConsts rc, const uint2* __restrict__ gmu,
@@ -598,7 +599,7 @@ __global__ __launch_bounds__(THREADS, 6) void k_robust(const float* __restrict__
 }
 
 // Persistent form over (burst, tile) items of a batch (XCD-chunked queue).
-__global__ __launch_bounds__(THREADS, 6) void k_robust_batch(const BurstArgs* __restrict__ bursts,
+__global__ __launch_bounds__(RTHREADS, 6) void k_robust_batch(const BurstArgs* __restrict__ bursts,
                                                           const WorkItem* __restrict__ items, ItemQueue q) {
   __shared__ RobustSmem sm;
   for_each_item(q, &sm.sItem, [&](int it) {
@@ -636,7 +637,7 @@ hipError_t launch_robust(const Geometry& g, const RobustConsts& rc, const uint16
   int m_per = (int)((work + kRobustGroups - 1) / kRobustGroups);
   m_per = m_per < 1 ? 1 : (m_per > na ? na : m_per);
   const int groups = (na + m_per - 1) / m_per;
-  hipLaunchKernelGGL(k_robust, dim3(tiles, groups), dim3(THREADS), 0, stream, motion, w.s_tile, w.mov, g, rc, w.gmu,
+  hipLaunchKernelGGL(k_robust, dim3(tiles, groups), dim3(RTHREADS), 0, stream, motion, w.s_tile, w.mov, g, rc, w.gmu,
                      w.gref, rmin, robust, m_per);
   return hipGetLastError();
 }
@@ -657,13 +658,13 @@ hipError_t launch_guide_stats_batch(const BurstArgs* bursts, const int* base_fir
 
 int robust_batch_blocks_per_cu() {
   int b = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_robust_batch, THREADS, 0) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_robust_batch, RTHREADS, 0) != hipSuccess) return 1;
   return b > 0 ? b : 1;
 }
 
 hipError_t launch_robust_batch(const BurstArgs* bursts, const WorkItem* items, const int* bounds,
                                int* counters, int n_groups, hipStream_t stream) {
-  hipLaunchKernelGGL(k_robust_batch, dim3(n_groups), dim3(THREADS), 0, stream, bursts, items,
+  hipLaunchKernelGGL(k_robust_batch, dim3(n_groups), dim3(RTHREADS), 0, stream, bursts, items,
                      ItemQueue{bounds, counters});
   return hipGetLastError();
 }
