@@ -164,8 +164,8 @@ typedef struct {
  *          tile shape is used, so `out` can differ from a call without it in
  *          the last bits.
  * The internal workspace holds per-frame maps of the base half-resolution
- * grid (the guide's 3x3 means and R_hat): about 16 bytes per half-resolution
- * pixel and frame.
+ * grid (the guide's packed 3x3 sums and R_hat): about 12 bytes per
+ * half-resolution pixel and frame.
  * Returns HMFSR_OK, or an error code with nothing enqueued.
  */
 hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
@@ -181,8 +181,8 @@ hmfsr_status hmfsr_merge(const hmfsr_desc* desc, const hmfsr_tuning* tuning,
  * library's code object holds from load until the process ends; the call
  * allocates nothing (no hipMalloc, hipFree, events or library allocations)
  * and profiling does not time it.
- *  Limit: the maps take about 16 bytes per half-resolution pixel and frame
- *  (8 or 15 frames of 1024 x 768 and 4 frames of 2016 x 1512 fit; a
+ *  Limit: the maps take about 12 bytes per half-resolution pixel and frame
+ *  (up to 16 frames of 1024 x 768 and 6 frames of 2016 x 1512 fit; a
  *  12 MP x 8 burst does not): a burst whose maps exceed the scratch returns
  *  HMFSR_E_TOO_LARGE before any device work.
  *  Every call on one device shares that device's scratch and nothing in it
@@ -217,7 +217,7 @@ hmfsr_status hmfsr_merge_noalloc(const hmfsr_desc* desc, const hmfsr_tuning* tun
  *            base frame's vectors are ignored by the merge and get 0.
  * Kernel weights are recomputed, not stored. Sums are taken in a fixed order:
  * repeated calls give identical bits. The internal workspace grows to about
- * 20 bytes per half-resolution pixel and frame (the forward's maps and R)
+ * 16 bytes per half-resolution pixel and frame (the forward's maps and R)
  * plus 3 bytes per output pixel and frame (per-tile partials), and 48 bytes
  * per output pixel more when saved is NULL.
  */
