@@ -585,8 +585,8 @@ def main():
                     help="time only that workload's forward merge (for a profile of it alone) and print its record")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (--gpus 1); the merge shards by "
-              "output bands, which is described but not run.", file=sys.stderr)
+        print("bench.py times the merge on one GPU only (--gpus 1); sharding the merge by "
+              "output bands across GPUs is designed but not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
