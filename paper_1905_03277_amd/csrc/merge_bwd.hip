@@ -75,9 +75,10 @@ struct BwdSmem {
   float4 sP[2][BCP::OM];
   float2 sP2[BCP::OM];
   float sRh[BCP::RH];
-  double2 sHm[BMH][BCP::TX];     // per pixel row and alignment tile column: sum of dL/dp
-  float sHa[BMH][BCP::RH_W];     // per pixel row and R_hat column: dL/drho through the left corners
-  float sHb[BMH][BCP::RH_W];     // ... through the right corners
+  // per frame slot (frame index & 1): a frame's sums are added up during the next frame
+  double2 sHm[2][BMH][BCP::TX];  // per pixel row and alignment tile column: sum of dL/dp
+  float sHa[2][BMH][BCP::RH_W];  // per pixel row and R_hat column: dL/drho through the left corners
+  float sHb[2][BMH][BCP::RH_W];  // ... through the right corners
   int sRun[MW];  // per lane: first lane of its runs (alignment tile, left and right R_hat corner column)
   double sAcc[BWAVES][6];
   int sRed[8];
@@ -246,6 +247,39 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
   }
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 
+  // Over the tile's pixel rows, in fixed order, the per-row sums a frame left
+  // in slot `slot`: dL/dp per alignment tile and dL/drho onto the tile's R_hat
+  // window, into frame m's per-workgroup partials. Runs after the barrier
+  // that opens the next frame (or follows the last), beside that frame's
+  // first loads.
+  auto add_rows = [&](int slot, int m) {
+    const int nwin = rhh * rhw;
+    for (int k = tid; k < ntiles + nwin; k += BTHREADS) {
+      if (k < ntiles) {
+        const int ky = k / ntx, kx = k - ky * ntx;
+        double sx = 0.0, sy = 0.0;
+        for (int r = sm.sRlo[ky]; r <= sm.sRhi[ky]; ++r) {
+          sx += sm.sHm[slot][r][kx].x;
+          sy += sm.sHm[slot][r][kx].y;
+        }
+        double* dst = part_mo + (((size_t)tile * g.n + m) * kBwdVT + k) * 2;
+        dst[0] = sx;
+        dst[1] = sy;
+      } else {
+        const int q = k - ntiles;
+        const int I = q / rhw, J = q - I * rhw;
+        float s = 0.f;
+        for (int r = sm.sIlo[I]; r <= sm.sIhi[I]; ++r) {
+          const float fyr = sm.sRow[r].fy;
+          const float wgt = (sm.sRya[r] == I ? 1.f - fyr : 0.f) + (sm.sRyb[r] == I ? fyr : 0.f);
+          s = fmaf(wgt, sm.sHa[slot][r][J] + sm.sHb[slot][r][J], s);
+        }
+        part_rh[((size_t)m * bc.n_tiles + tile) * kBwdRH + q] = s;
+      }
+    }
+  };
+  auto frame_of = [&](int fi) { return fi == 0 ? g.ref : (fi <= g.ref ? fi - 1 : fi); };
+
   for (int fi = 0; fi < g.n; ++fi) {
     const int n = fi == 0 ? g.ref : (fi <= g.ref ? fi - 1 : fi);
     const bool is_ref = n == g.ref;
@@ -260,20 +294,24 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
       v = make_float2(p[0], p[1]);
     }
     if (tid < 8) sm.sRed[tid] = 0x7fffffff;
+    // every load of the R_hat window in flight before its stores (entries
+    // past the window re-read its last one and are not stored); the previous
+    // frame's row sums are added up while they are
+    constexpr int RHT = (BCP::RH + BTHREADS - 1) / BTHREADS;
+    const int nrh = rhw * rhh;
+    float rhv[RHT];
     if (!is_ref) {
-      // every load of the window in flight before its stores (entries past
-      // the window re-read its last one and are not stored)
-      constexpr int RHT = (BCP::RH + BTHREADS - 1) / BTHREADS;
       const float* rm = rmin + (size_t)n * g.h * g.w;
       const float inv = 1.f / (float)rhw;
-      const int nrh = rhw * rhh;
-      float rhv[RHT];
 #pragma unroll
       for (int i = 0; i < RHT; ++i) {
         const int k = min(tid + i * BTHREADS, nrh - 1);
         const int r = split_row(k, inv);
         rhv[i] = rm[(unsigned)((rhr0 + r) * g.w + rhc0 + k - r * rhw)];  // below 2^28
       }
+    }
+    if (fi >= 2) add_rows((fi - 1) & 1, frame_of(fi - 1));  // frame 0 is the base frame: no sums
+    if (!is_ref) {
 #pragma unroll
       for (int i = 0; i < RHT; ++i)
         if (tid + i * BTHREADS < nrh) sm.sRh[tid + i * BTHREADS] = rhv[i];
@@ -567,46 +605,24 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
           sx = run_sum(sx, lane, run_t);
           sy = run_sum(sy, lane, run_t);
           if (end_t) {
-            sm.sHm[r][txl] = make_double2(sx, sy);
-            if (joined && BPX == 2 && r + 1 < nrow) sm.sHm[r + 1][txl] = make_double2(0.0, 0.0);
+            sm.sHm[fi & 1][r][txl] = make_double2(sx, sy);
+            if (joined && BPX == 2 && r + 1 < nrow) sm.sHm[fi & 1][r + 1][txl] = make_double2(0.0, 0.0);
           }
         }
         if (lane < rhw) {
-          sm.sHa[r][lane] = 0.f;
-          sm.sHb[r][lane] = 0.f;
+          sm.sHa[fi & 1][r][lane] = 0.f;
+          sm.sHb[fi & 1][r][lane] = 0.f;
         }
         const float ga = run_sum((1.f - rfx) * pgr[p], lane, run_a);
         const float gb = run_sum(rfx * pgr[p], lane, run_b);
-        if (end_a) sm.sHa[r][rxa] = ga;
-        if (end_b) sm.sHb[r][rxb] = gb;
-      }
-      __syncthreads();
-      const int nwin = rhh * rhw;
-      for (int k = tid; k < ntiles + nwin; k += BTHREADS) {
-        if (k < ntiles) {
-          const int ky = k / ntx, kx = k - ky * ntx;
-          double sx = 0.0, sy = 0.0;
-          for (int r = sm.sRlo[ky]; r <= sm.sRhi[ky]; ++r) {
-            sx += sm.sHm[r][kx].x;
-            sy += sm.sHm[r][kx].y;
-          }
-          double* dst = part_mo + (((size_t)tile * g.n + n) * kBwdVT + k) * 2;
-          dst[0] = sx;
-          dst[1] = sy;
-        } else {
-          const int q = k - ntiles;
-          const int I = q / rhw, J = q - I * rhw;
-          float s = 0.f;
-          for (int r = sm.sIlo[I]; r <= sm.sIhi[I]; ++r) {
-            const float fyr = sm.sRow[r].fy;
-            const float wgt = (sm.sRya[r] == I ? 1.f - fyr : 0.f) + (sm.sRyb[r] == I ? fyr : 0.f);
-            s = fmaf(wgt, sm.sHa[r][J] + sm.sHb[r][J], s);
-          }
-          part_rh[((size_t)n * bc.n_tiles + tile) * kBwdRH + q] = s;
-        }
+        if (end_a) sm.sHa[fi & 1][r][rxa] = ga;
+        if (end_b) sm.sHb[fi & 1][r][rxb] = gb;
       }
     }
   }
+  // the last frame's row sums (a burst of the base frame alone has none)
+  __syncthreads();
+  if (g.n >= 2) add_rows((g.n - 1) & 1, frame_of(g.n - 1));
 
   // ---- the six covariance-scalar sums of the workgroup ------------------
 #pragma unroll
