@@ -87,16 +87,43 @@ struct BwdSmem {
 
 __device__ __forceinline__ float pick3(const float (&a)[3], int c) { return c == 0 ? a[0] : (c == 1 ? a[1] : a[2]); }
 
+// One 32-bit lane move of a DPP control (gfx9 encodings: row_shr:n = 0x110 +
+// n within rows of 16 lanes; row_bcast:15 = 0x142, lane 15 of each row to the
+// next; row_bcast:31 = 0x143, lane 31 to rows 2 and 3). Rows outside
+// row_mask, and lanes without a source, receive 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), CTRL, ROWS, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, ROWS, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Inclusive sum of v over lanes [start, lane] (start <= lane: the first lane
-// of this lane's run of equal keys), Hillis-Steele order: the run's last lane
-// then holds the run's sum, with the same bits on every call.
+// of this lane's run of equal keys): Hillis-Steele steps of 1, 2, 4 and 8
+// lanes inside each row of 16, then the last lane of row 0 (and of row 2) to
+// row 1 (row 3), then the last lane of row 1 to rows 2 and 3, each added only
+// where the source lies in the lane's run. The run's last lane then holds
+// the run's sum, with the same bits on every call.
 template <typename T>
 __device__ __forceinline__ T run_sum(T v, int lane, int start) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const T u = __shfl_up(v, off, 64);
-    if (lane - off >= start) v += u;
-  }
+  const int in_row = lane & 15, row0 = lane & ~15;
+  T u = dpp_f<0x111, 0xF>(v);
+  if (in_row >= 1 && lane - 1 >= start) v += u;
+  u = dpp_f<0x112, 0xF>(v);
+  if (in_row >= 2 && lane - 2 >= start) v += u;
+  u = dpp_f<0x114, 0xF>(v);
+  if (in_row >= 4 && lane - 4 >= start) v += u;
+  u = dpp_f<0x118, 0xF>(v);
+  if (in_row >= 8 && lane - 8 >= start) v += u;
+  u = dpp_f<0x142, 0xA>(v);  // lanes 15 and 47 to rows 1 and 3
+  if ((lane & 16) && row0 - 1 >= start) v += u;
+  u = dpp_f<0x143, 0xC>(v);  // lane 31 to rows 2 and 3
+  if (lane >= 32 && 31 >= start) v += u;
   return v;
 }
 
