@@ -62,7 +62,8 @@ CASES = [dict(scale=1.0, seed=1), dict(scale=1.5, seed=2, cfa=1),
          dict(scale=2.0, seed=3, cfa=3, tile=8), dict(scale=1.5, seed=4, cfa=2, ref=2),
          dict(scale=1.0, seed=5, h=70, w=102, tile=16),          # ragged output tiles
          dict(scale=2.0, seed=6, n=6, h=64, w=96, tile=32),
-         dict(scale=1.25, seed=7, n=3, h=40, w=136, tile=8, jitter=0.3)]
+         dict(scale=1.25, seed=7, n=3, h=40, w=136, tile=8, jitter=0.3),
+         dict(scale=1.5, seed=8, n=2, ref=1)]   # one aligned frame: its sums are added after the loop
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "-".join(f"{k}{v}" for k, v in c.items()))
