@@ -7,11 +7,13 @@ kernel's roofline position and the FP64 oracle's CPU rate on a bounded sample.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
                     [--no-batch] [--no-grad] [--no-stream] [--no-align] [--no-configs]
+    python bench.py --only-config {1,3} [--steps K]   (that workload's merge alone)
 
 More legs follow the headline measurement and are reported inside its line:
 the low-light workload (15 x 1512 x 2016 at scale 2) and the small 8 x 256 x
 256 burst, the same burst merged frame by frame through the streaming calls, its tile
-alignment and the raw-burst-to-RGB time (alignment then merge), the
+alignment (with its ground-truth error split by tile structure, with and
+without the noise gate) and the raw-burst-to-RGB time (alignment then merge), the
 64-burst batched workload (one graph replay vs per-burst launches) and the
 differentiation workload (16 bursts of 8 x 768 x 1024 at scale 2, forward
 plus adjoint).
