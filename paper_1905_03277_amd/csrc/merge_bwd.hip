@@ -85,7 +85,18 @@ struct BwdSmem {
   int sRh0[4];
 };
 
-__device__ __forceinline__ float pick3(const float (&a)[3], int c) { return c == 0 ? a[0] : (c == 1 ? a[1] : a[2]); }
+// Per-channel values a[R, G, B] routed to the four colour groups of a 3x3
+// window (centre, left/right, up/down, corners): green centres put green on
+// the centre and corners, otherwise green sits left/right and up/down; the
+// other two groups take red and blue as `xIsR` says. Selects only, so the
+// routing never branches.
+__device__ __forceinline__ void route4(const float (&a)[3], bool isG, bool xIsR, float (&o)[4]) {
+  const float X = xIsR ? a[0] : a[2], Y = xIsR ? a[2] : a[0], G = a[1];
+  o[0] = isG ? G : X;
+  o[1] = isG ? X : G;
+  o[2] = isG ? Y : G;
+  o[3] = isG ? G : Y;
+}
 
 // One 32-bit lane move of a DPP control (gfx9 encodings: row_shr:n = 0x110 +
 // n within rows of 16 lanes; row_bcast:15 = 0x142, lane 15 of each row to the
@@ -523,16 +534,12 @@ __global__ __launch_bounds__(BTHREADS, 3) void k_merge_bwd(
           const int c0 = colour_of(mc.col4, pr * 2 + pc);
           const int c1 = colour_of(mc.col4, pr * 2 + (pc ^ 1));
           const bool isG = c0 == 1;
-          const int chX = ((isG ? c1 : c0) == 0) ? 0 : 2, chY = 2 - chX;
-          const int chg[4] = {isG ? 1 : chX, isG ? chX : 1, isG ? chY : 1, isG ? 1 : chY};
+          const bool xIsR = (isG ? c1 : c0) == 0;  // group "X" (centre or left/right) is red
           float Mg[4], Gg[4], Ch[4], Cl[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            Mg[q] = pick3(mref[p], chg[q]);
-            Gg[q] = pick3(gam[p], chg[q]);
-            Ch[q] = pick3(chi[p], chg[q]);
-            Cl[q] = pick3(clo[p], chg[q]);
-          }
+          route4(mref[p], isG, xIsR, Mg);
+          route4(gam[p], isG, xIsR, Gg);
+          route4(chi[p], isG, xIsR, Ch);
+          route4(clo[p], isG, xIsR, Cl);
           const int vb = (ic - 1 - rr0) * rw + (jc - 1 - rc0);
           float a[3][3];
           float grho = 0.f;
