@@ -716,6 +716,10 @@ __global__ __launch_bounds__(64, 4) void k_robust_bwd(const uint2* __restrict__ 
     return;
   }
   __shared__ float sR[RB + 8][RB + 8];
+  // per R row of the block's window and cell column: the minimum over the
+  // cell's five columns and the offset (-2..2) of its first occurrence
+  __shared__ float sHv[RB + 8][RB + 4];
+  __shared__ int sHj[RB + 8][RB + 4];
   __shared__ float sG[RB + 4][RB + 4];
   __shared__ int sA[RB + 4][RB + 4];
   // output tiles whose R_hat windows cover each cell row / column of the block
@@ -763,34 +767,60 @@ __global__ __launch_bounds__(64, 4) void k_robust_bwd(const uint2* __restrict__ 
         }
       }
       __syncthreads();
-      // dL/dR_hat of the cells whose 5x5 window can reach the block, and
-      // where it goes: the first minimum of the window in scan order.
+      // dL/dR_hat of the cells whose 5x5 window can reach the block: the
+      // window partials of every output tile holding the cell, in tile order.
+      // Beside it, the first minimum of each window row over the cells' five
+      // columns (row k of the R window holds image row clamp(bi0 - 4 + k)).
       for (int k = tid; k < (RB + 4) * (RB + 4); k += 64) {
         const int r2 = k / (RB + 4), c2 = k - r2 * (RB + 4);
         const int I = bi0 - 2 + r2, J = bj0 - 2 + c2;
         float gr = 0.f;
-        int arg = -1;
-        // dL/dR_hat: the window partials of every output tile holding the cell, in tile order
         for (int a = 0; a < sNr[r2]; ++a) {
           const float* row = part_rh + ((size_t)n * bc.n_tiles + sTr[r2][a] * bc.tiles_x) * kBwdRH;
           for (int b2 = 0; b2 < sNc[c2]; ++b2)
             gr += row[(size_t)sTc[c2][b2] * kBwdRH + (I - sLr[r2][a]) * sWc[c2][b2] + (J - sLc[c2][b2])];
         }
-        if (gr != 0.f) {
-          float best = INFINITY;
-          for (int di = -2; di <= 2; ++di) {
-            const int ci = clampi(I + di, 0, g.h - 1);
-            for (int dj = -2; dj <= 2; ++dj) {
-              const int cj = clampi(J + dj, 0, g.w - 1);
-              const float v = sR[ci - (bi0 - 4)][cj - (bj0 - 4)];
-              if (v < best) {
-                best = v;
-                arg = ci * g.w + cj;
-              }
-            }
+        sG[r2][c2] = gr;
+      }
+      for (int k = tid; k < (RB + 8) * (RB + 4); k += 64) {
+        const int rr = k / (RB + 4), c2 = k - rr * (RB + 4);
+        float best = INFINITY;
+        int bj = 0;
+#pragma unroll
+        for (int dj = -2; dj <= 2; ++dj) {
+          const float v = sR[rr][c2 + 2 + dj];
+          if (v < best) {
+            best = v;
+            bj = dj;
           }
         }
-        sG[r2][c2] = gr;
+        sHv[rr][c2] = best;
+        sHj[rr][c2] = bj;
+      }
+      __syncthreads();
+      // where each cell's dL/dR_hat goes: the first minimum of its window in
+      // scan order (rows, then columns), i.e. the first row holding the
+      // window's minimum and that row's first minimum. Clamped positions
+      // repeat a border cell, so ties between them name the same cell.
+      for (int k = tid; k < (RB + 4) * (RB + 4); k += 64) {
+        const int r2 = k / (RB + 4), c2 = k - r2 * (RB + 4);
+        int arg = -1;
+        if (sG[r2][c2] != 0.f) {
+          float best = INFINITY;
+          int bi = 0;
+#pragma unroll
+          for (int di = -2; di <= 2; ++di) {
+            const float v = sHv[r2 + 2 + di][c2];
+            if (v < best) {
+              best = v;
+              bi = di;
+            }
+          }
+          if (best < INFINITY) {
+            const int I = bi0 - 2 + r2, J = bj0 - 2 + c2;
+            arg = clampi(I + bi, 0, g.h - 1) * g.w + clampi(J + sHj[r2 + 2 + bi][c2], 0, g.w - 1);
+          }
+        }
         sA[r2][c2] = arg;
       }
       __syncthreads();
