@@ -23,6 +23,14 @@
  *    hmfsr_release(). Calls that run concurrently on one device must use
  *    the same stream (the workspace is shared); the library serialises its
  *    host-side bookkeeping with a mutex.
+ *  - Graph capture: once an eager call of the same burst size has sized the
+ *    workspace, hmfsr_merge and hmfsr_merge_backward enqueue kernel launches
+ *    only (no allocation, copy, fill or synchronisation) and may be
+ *    captured into a HIP graph. The graph then reads the workspace it was
+ *    captured with: a later call that grows the workspace, or
+ *    hmfsr_release(), frees it, and the graph must not be replayed after
+ *    that. With HMFSR_DEBUG set these calls synchronise and cannot be
+ *    captured. hmfsr_merge_noalloc uses a fixed scratch buffer instead.
  *  - Outputs are overwritten, never accumulated into.
  *  - Descriptor and tuning values are validated on the host before any
  *    device work: invalid values give HMFSR_E_INVALID and touch nothing.
